@@ -1,0 +1,181 @@
+/*
+ * mpv.h - C ABI of the MI355X (gfx950) multi-scale MPV stereo matcher.
+ *
+ * The library computes the disparity map U that the paper's Multi-Path-Viterbi
+ * approximately minimises (Section 3.2, eqs. EU and viterbi): a per-pixel matching cost
+ * (census 5x5 / Hamming here, in place of the paper's SSIM), a min-plus Viterbi pass
+ * along several scanline directions with a truncated total-variation transition
+ * lambda*min(|d-d'|, tau) (eq. e(p,u); Section 3.3 fast technique), the sum of the path
+ * energies, winner-take-all disparity, a left-right consistency check, and the
+ * coarse-to-fine search-band propagation of the image pyramid (Section 3.4).
+ *
+ * Conventions for every entry point
+ *  - Pointers to images, volumes and maps are DEVICE pointers (hipMalloc'd or torch
+ *    tensors); parameter structs are host pointers read during the call only.
+ *  - Every call is asynchronous: work is enqueued on `stream` (0 = the null stream) and
+ *    nothing synchronises. Host-visible results need a stream synchronisation.
+ *  - Argument, shape, workspace and overflow problems are detected before anything is
+ *    enqueued and returned as a status; nothing is launched then. A failed launch
+ *    returns MPV_ERR_DEVICE. No C++ exception crosses the ABI.
+ *  - The caller owns all memory. The library allocates nothing; scratch comes from the
+ *    caller's workspace, sized by the matching *_workspace_bytes call. Concurrent calls
+ *    on different streams need distinct workspaces and outputs.
+ *  - Images are uint8, row-major, `pitch` bytes between rows (pitch >= width).
+ *    Volumes are [H][W][cap] with the disparity slot innermost. Disparity maps are
+ *    int16 [H][W] with -1 meaning invalid.
+ *  - The left image is the reference: left pixel (x, y) with disparity d matches right
+ *    pixel (x - d, y). A candidate with x - d < 0 costs 24 (every census bit differs).
+ */
+#ifndef MPV_H
+#define MPV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPV_OK = 0,
+    MPV_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad parameter */
+    MPV_ERR_UNSUPPORTED = 2, /* valid but outside what the kernels implement */
+    MPV_ERR_WORKSPACE = 3,   /* workspace missing or too small */
+    MPV_ERR_OVERFLOW = 4,    /* the requested sum type cannot hold the energies */
+    MPV_ERR_DEVICE = 5       /* a HIP call or launch failed */
+} mpv_status;
+
+/* Aggregate-sum export types for mpv_aggregate / mpv_disparity. */
+#define MPV_AGG_U16 0
+#define MPV_AGG_I32 1
+
+#define MPV_MAX_DISP 256
+#define MPV_MAX_LEVELS 4
+#define MPV_MAX_WIDTH 4096
+
+/* Scan directions, in the order of the paper's multi-path table (Section 3.2, Table alg):
+ * bit r of a path mask selects direction r. num_paths = P selects the first P. */
+#define MPV_DIR_L2R 0   /* (+1, 0) */
+#define MPV_DIR_R2L 1   /* (-1, 0) */
+#define MPV_DIR_T2B 2   /* ( 0,+1) */
+#define MPV_DIR_B2T 3   /* ( 0,-1) */
+#define MPV_DIR_TL2BR 4 /* (+1,+1) */
+#define MPV_DIR_BR2TL 5 /* (-1,-1) */
+#define MPV_DIR_TR2BL 6 /* (-1,+1) */
+#define MPV_DIR_BL2TR 7 /* (+1,-1) */
+
+typedef struct {
+    const uint8_t *data; /* device pointer */
+    int32_t width, height, pitch;
+} mpv_image;
+
+/* Per-pixel search band (Section 3.4's per-pixel search scope). Pixel p searches the
+ * disparities lo[p] .. lo[p] + len[p] - 1, stored in slots 0 .. len[p]-1 of a
+ * [H][W][cap] volume. lo == NULL means the full range [0, num_disp) with cap = num_disp;
+ * len == NULL means len[p] = cap everywhere. Requires 1 <= len[p] <= cap and
+ * 0 <= lo[p] <= num_disp - len[p]; disparities outside a band are absent Viterbi nodes.
+ * The maps are not validated; the kernels clamp lo to [0, num_disp-1] and len to
+ * [1, min(cap, num_disp-lo)], so a map that breaks the rule still stays in bounds. */
+typedef struct {
+    const int16_t *lo;  /* device [H][W] or NULL */
+    const uint8_t *len; /* device [H][W] or NULL */
+    int32_t cap;
+} mpv_band;
+
+typedef struct {
+    int32_t num_disp;      /* D: 1 .. MPV_MAX_DISP */
+    int32_t census_radius; /* must be 2 (5x5 census, 24 bits) */
+    int32_t num_paths;     /* P in {1, 2, 4, 8}: the first P directions */
+    int32_t lambda;        /* transition weight, >= 0 */
+    int32_t tau;           /* truncation, >= 1; tau >= num_disp is the untruncated TV */
+    int32_t lr_max_diff;   /* LR tolerance in px (1 = "1 px"); < 0 disables the check */
+    int32_t agg_type;      /* MPV_AGG_U16 or MPV_AGG_I32 (exported sums only) */
+} mpv_params;
+
+/* Human-readable status name; never NULL. */
+const char *mpv_status_string(mpv_status s);
+
+/* Census transform (the cost's per-pixel signature; replaces the paper's SSIM patches of
+ * Section 3.2): bit k of census[y][x] is set when the k-th neighbour of the 5x5 window,
+ * in row-major order skipping the centre, is darker than the centre; neighbour
+ * coordinates are clamped to the image. Output: device uint32 [H][W], bits 24..31 zero. */
+mpv_status mpv_census(const mpv_image *img, uint32_t *census, hipStream_t stream);
+
+/* One pyramid step (Section 3.4): out[y][x] = (sum of the 2x2 block at (2x, 2y) + 2) >> 2,
+ * for an output of floor(W/2) x floor(H/2) pixels, rows packed (pitch = W/2). */
+mpv_status mpv_downsample(const mpv_image *img, uint8_t *out, hipStream_t stream);
+
+/* Matching-cost volume: cost[y][x][j] = popcount(cL(x,y) ^ cR(x-d,y)) for d = lo + j in the
+ * band (24 when x-d < 0), 0xFF in slots past the pixel's band. This is the data term of
+ * eq. e(p,u). Output: device uint8 [H][W][cap]. band may be NULL (full range). */
+mpv_status mpv_cost(const mpv_params *p, const mpv_image *left, const mpv_image *right,
+                    const mpv_band *band, uint8_t *cost, hipStream_t stream);
+
+/* Path energies and their sum (eqs. viterbi, e(p,u)):
+ *   L_r(p,d) = C(p,d) + min_{d' in B(p-r)} [L_r(p-r,d') + lambda*min(|d-d'|, tau)],
+ *   L_r(p,d) = C(p,d) where p-r is outside the image,
+ *   agg[p][j] = sum over the selected directions r of L_r(p, lo+j)    (unnormalised).
+ * Input: the [H][W][cap] cost volume of mpv_cost. path_mask selects a subset of the first
+ * num_paths directions (0 = all of them). Output: device [H][W][cap] of uint16 or int32
+ * per agg_type; slots past a pixel's band hold the type's maximum.
+ * MPV_ERR_OVERFLOW when P * (24 + lambda*min(tau, D-1)) * longest line may exceed the type;
+ * MPV_ERR_UNSUPPORTED when lambda*min(tau, D-1) > 4000. */
+mpv_status mpv_aggregate(const mpv_params *p, const uint8_t *cost, int32_t width, int32_t height,
+                         const mpv_band *band, uint32_t path_mask, void *agg, hipStream_t stream);
+
+/* Winner-take-all and left-right check on an aggregate volume (agg_type selects
+ * uint16 or int32):
+ *   raw(p)   = the smallest in-band d minimising agg(p, d)
+ *   S'(p,d)  = agg(p,d) - min_d agg(p,d)
+ *   right(x,y) = the largest d minimising S'(x+d, y, d) over the d with x+d < W and d in
+ *              B(x+d, y); -1 if there is none (ties go to the nearer surface)
+ *   disp(p)  = raw(p) if x-raw >= 0, right(x-raw, y) >= 0 and |raw - right(x-raw,y)|
+ *              <= lr_max_diff, else -1; lr_max_diff < 0 gives disp = raw.
+ * disp is required; disp_right and disp_raw may be NULL. Requires width <= MPV_MAX_WIDTH. */
+mpv_status mpv_disparity(const mpv_params *p, const void *agg, int32_t width, int32_t height,
+                         const mpv_band *band, int16_t *disp, int16_t *disp_right,
+                         int16_t *disp_raw, hipStream_t stream);
+
+/* Multi-scale fused path (Section 3.4). */
+typedef struct {
+    mpv_params base;     /* num_disp = D of the finest (input) level */
+    int32_t levels;      /* 1 .. MPV_MAX_LEVELS; 1 = plain single-scale MPV */
+    int32_t band_radius; /* R: levels below the top search [c-R, c+R] around c = 2 x parent */
+} mpv_pyramid_params;
+
+typedef struct {
+    int16_t *disp;                      /* required: [H][W] finest, LR-checked */
+    int16_t *disp_raw;                  /* optional: finest raw WTA */
+    int16_t *disp_right;                /* optional: finest right disparity */
+    int16_t *level_raw[MPV_MAX_LEVELS]; /* optional: raw WTA per level, 0 = coarsest */
+} mpv_pyramid_out;
+
+/* Workspace bytes mpv_pyramid needs for this shape; 0 if the parameters are invalid. */
+size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params *p, int32_t width, int32_t height);
+
+/* Level l of L has size floor(W / 2^(L-1-l)) x floor(H / 2^(L-1-l)) and range
+ * D_l = ceil(D / 2^(L-1-l)). The top level (l = 0) searches its full range. Every finer
+ * level searches the band of cap = min(2R+1, D_l) disparities starting at
+ * lo = clamp(2 * raw_{l-1}(min(x/2, W_{l-1}-1), min(y/2, H_{l-1}-1)) - R, 0, D_l - cap).
+ * Each level runs cost -> all P paths -> sum -> WTA -> LR exactly as the unfused calls
+ * do, so the outputs equal mpv_cost + mpv_aggregate + mpv_disparity per level.
+ * Requires 24 + lambda*min(tau, D-1) <= 255, num_paths in {1,2,4,8} and every level at
+ * least 1x1 pixel and at most MPV_MAX_WIDTH wide. */
+mpv_status mpv_pyramid(const mpv_pyramid_params *p, const mpv_image *left, const mpv_image *right,
+                       const mpv_pyramid_out *out, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream);
+
+/* One fused level with a caller-given band (the learned-band path: a network proposes
+ * lo/len per pixel and the finest level searches only there). Same arithmetic and
+ * outputs as one level of mpv_pyramid. band may be NULL (full range). */
+size_t mpv_match_workspace_bytes(const mpv_params *p, int32_t width, int32_t height,
+                                 const mpv_band *band);
+mpv_status mpv_match(const mpv_params *p, const mpv_image *left, const mpv_image *right,
+                     const mpv_band *band, int16_t *disp, int16_t *disp_right, int16_t *disp_raw,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPV_H */

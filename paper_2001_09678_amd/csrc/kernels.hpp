@@ -1,0 +1,619 @@
+// HIP kernels of the MPV stereo matcher for gfx950.
+//
+// Data layout in HBM
+//   images      uint8 [H][pitch]
+//   census      uint32 [H][cpitch], pixel (x, y) at y*cpitch + cmargin + x; the left
+//               margin keeps the cost loads of candidates x-d < 0 inside the buffer
+//   partials    uint8 [P][H][W][capP]: one normalised energy volume per scan direction
+//   bands       int16 lo [H][W], uint8 len [H][W]
+//   disparity   int16 [H][W], -1 = invalid
+//
+// Scan kernels (the directed-path Viterbi of Section 3.2, eq. e(p,u)): one line of one
+// direction per group of LPL lanes; a lane holds 2K disparities of the line as packed
+// 16-bit energies (full range) or one disparity (band). The min over predecessors uses
+// the decomposition of Section 3.3: the envelope of lambda*|d-d'| is built by sweeps
+// along the disparity axis (here as doubling steps s = 1, 2, 4, ... so that a window of
+// tau-1 neighbours takes log2(tau) cross-lane steps), and the truncation at tau is one
+// more candidate, the previous minimum plus lambda*tau. Energies are kept normalised
+// (previous minimum subtracted), so that minimum is 0 and the candidate is lambda*tau.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lane.hpp"
+
+namespace mpvk {
+
+// Band of pixel p, clamped so that any map stays in bounds: 0 <= b0 < D, 1 <= bn <= min(cap, D-b0).
+__device__ __forceinline__ void band_at(const int16_t* lo, const uint8_t* len, size_t p, int D,
+                                        int cap, int& b0, int& bn) {
+  b0 = lo ? min(max((int)lo[p], 0), D - 1) : 0;
+  bn = len ? (int)len[p] : cap;
+  bn = min(max(bn, 1), min(cap, D - b0));
+}
+
+__constant__ int c_dx[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
+__constant__ int c_dy[8] = {0, 0, +1, -1, +1, -1, +1, -1};
+
+// ---------------------------------------------------------------------------------------
+// Census 5x5 and downsampling
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_census(const uint8_t* __restrict__ img, int W, int H,
+                                                int pitch, uint32_t* __restrict__ out,
+                                                int opitch, int omargin) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  const int c = img[(size_t)y * pitch + x];
+  uint32_t v = 0;
+  int bit = 0;
+#pragma unroll
+  for (int dy = -2; dy <= 2; ++dy) {
+    const int yy = min(max(y + dy, 0), H - 1);
+    const uint8_t* row = img + (size_t)yy * pitch;
+#pragma unroll
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (dx == 0 && dy == 0) continue;
+      const int xx = min(max(x + dx, 0), W - 1);
+      v |= (uint32_t)(row[xx] < c) << bit;
+      ++bit;
+    }
+  }
+  out[(size_t)y * opitch + omargin + x] = v;
+}
+
+__global__ __launch_bounds__(256) void k_downsample(const uint8_t* __restrict__ in, int pitch,
+                                                    uint8_t* __restrict__ out, int w, int h) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= w || y >= h) return;
+  const uint8_t* r0 = in + (size_t)(2 * y) * pitch + 2 * x;
+  const uint8_t* r1 = r0 + pitch;
+  out[(size_t)y * w + x] = (uint8_t)((r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
+}
+
+// ---------------------------------------------------------------------------------------
+// Cost volume export: one block per row; both census rows are built in LDS first.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t census_at(const uint8_t* img, int W, int H, int pitch, int x,
+                                              int y) {
+  const int c = img[(size_t)y * pitch + x];
+  uint32_t v = 0;
+  int bit = 0;
+  for (int dy = -2; dy <= 2; ++dy) {
+    const int yy = min(max(y + dy, 0), H - 1);
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (dx == 0 && dy == 0) continue;
+      const int xx = min(max(x + dx, 0), W - 1);
+      v |= (uint32_t)(img[(size_t)yy * pitch + xx] < c) << bit;
+      ++bit;
+    }
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_cost(const uint8_t* __restrict__ L, int lpitch,
+                                              const uint8_t* __restrict__ R, int rpitch, int W,
+                                              int H, const int16_t* __restrict__ lo,
+                                              const uint8_t* __restrict__ len, int cap, int D,
+                                              uint8_t* __restrict__ cost) {
+  extern __shared__ uint32_t s_cen[];  // [2][W]
+  const int y = blockIdx.x;
+  for (int x = threadIdx.x; x < W; x += blockDim.x) {
+    s_cen[x] = census_at(L, W, H, lpitch, x, y);
+    s_cen[W + x] = census_at(R, W, H, rpitch, x, y);
+  }
+  __syncthreads();
+  const size_t n = (size_t)W * cap;
+  uint8_t* row = cost + (size_t)y * n;
+  for (size_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int x = (int)(i / cap), j = (int)(i % cap);
+    const size_t p = (size_t)y * W + x;
+    int b0, bn;
+    band_at(lo, len, p, D, cap, b0, bn);
+    uint8_t c = 0xFF;
+    if (j < bn) {
+      const int d = b0 + j;
+      c = (x - d >= 0) ? (uint8_t)__popc(s_cen[x] ^ s_cen[W + x - d]) : (uint8_t)24;
+    }
+    row[i] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Scan kernels
+// ---------------------------------------------------------------------------------------
+enum { SRC_CENSUS = 0, SRC_COST = 1 };
+enum { OUT_PART = 0, OUT_U16 = 1, OUT_I32 = 2 };
+
+struct ScanArgs {
+  int W, H, D, cap;  // cap: slots per pixel of the cost volume / aggregate export
+  int lambda, tau;   // tau = min(tau, D-1) clamped to >= 1 (same energies, see host)
+  const uint32_t* cl;
+  const uint32_t* cr;
+  int cpitch, cmargin;
+  const uint8_t* cost;
+  const int16_t* lo;
+  const uint8_t* len;
+  uint8_t* part;
+  long long part_stride;  // bytes between direction volumes
+  int capP;               // partial slots per pixel
+  void* agg;              // canonical export [H][W][cap]
+  int first;              // canonical export: this direction writes instead of adding
+  int ndir;
+  int dir[8];
+  int gprefix[9];  // first block of each direction
+};
+
+__device__ __forceinline__ int num_lines(int r, int W, int H) {
+  return c_dy[r] == 0 ? H : (c_dx[r] == 0 ? W : W + H - 1);
+}
+
+// First pixel and length of line i of direction r. Lines start where p - r leaves the image.
+__device__ __forceinline__ void line_info(int r, int i, int W, int H, int& x0, int& y0, int& n) {
+  const int dx = c_dx[r], dy = c_dy[r];
+  if (dy == 0) {
+    y0 = i;
+    x0 = dx > 0 ? 0 : W - 1;
+    n = W;
+  } else if (dx == 0) {
+    x0 = i;
+    y0 = dy > 0 ? 0 : H - 1;
+    n = H;
+  } else {
+    if (i < W) {
+      x0 = i;
+      y0 = dy > 0 ? 0 : H - 1;
+    } else {
+      const int k = i - W + 1;
+      x0 = dx > 0 ? 0 : W - 1;
+      y0 = dy > 0 ? k : H - 1 - k;
+    }
+    const int nx = dx > 0 ? W - x0 : x0 + 1;
+    const int ny = dy > 0 ? H - y0 : y0 + 1;
+    n = min(nx, ny);
+  }
+}
+
+// Block -> (direction, first line of this wave). One wave per block.
+template <int LPL>
+__device__ __forceinline__ void block_line(const ScanArgs& a, int& r, int& ri, int& x0, int& y0,
+                                           int& n, int& nmax) {
+  const int b = blockIdx.x;
+  ri = 0;
+  while (ri + 1 < a.ndir && b >= a.gprefix[ri + 1]) ++ri;
+  r = a.dir[ri];
+  const int g = lane_id() / LPL;
+  const int line = (b - a.gprefix[ri]) * (64 / LPL) + g;
+  if (line < num_lines(r, a.W, a.H)) {
+    line_info(r, line, a.W, a.H, x0, y0, n);
+  } else {
+    x0 = 0;
+    y0 = 0;
+    n = 0;
+  }
+  nmax = __builtin_amdgcn_readfirstlane(n);
+#pragma unroll
+  for (int k = 1; k < 64 / LPL; ++k) nmax = max(nmax, __builtin_amdgcn_readlane(n, k * LPL));
+}
+
+// Packed-pair shift of the disparity axis by s (s = 1 or even s) inside the group.
+// up: value from d - s; down: value from d + s. Lane l holds pairs of d = 2(lK+k), +1.
+template <int LPL, int K>
+__device__ __forceinline__ void shift_pairs_up(const uint32_t (&v)[K], uint32_t (&o)[K], int s) {
+  if (s == 1) {
+    const uint32_t prev = from_prev_lane<LPL>(v[K - 1], INF2);
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = funnel16(v[k], k ? v[k - 1] : prev);
+  } else {
+    const int q = s >> 1;
+    const int loff = q / K, rem = q % K;
+    uint32_t a[K], b[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a[k] = shift_up<LPL>(v[k], loff, INF2);
+      b[k] = shift_up<LPL>(v[k], loff + 1, INF2);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int kk = k - rem;
+      o[k] = kk >= 0 ? a[kk >= 0 ? kk : 0] : b[kk + K >= 0 ? kk + K : 0];
+    }
+  }
+}
+
+template <int LPL, int K>
+__device__ __forceinline__ void shift_pairs_down(const uint32_t (&v)[K], uint32_t (&o)[K], int s) {
+  if (s == 1) {
+    const uint32_t next = from_next_lane<LPL>(v[0], INF2);
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = funnel16(k + 1 < K ? v[k + 1] : next, v[k]);
+  } else {
+    const int q = s >> 1;
+    const int loff = q / K, rem = q % K;
+    uint32_t a[K], b[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a[k] = shift_down<LPL>(v[k], loff, INF2);
+      b[k] = shift_down<LPL>(v[k], loff + 1, INF2);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int kk = k + rem;
+      o[k] = kk < K ? a[kk < K ? kk : 0] : b[kk - K < K ? kk - K : 0];
+    }
+  }
+}
+
+// Full-range scan. Template: LPL lanes per line, K packed pairs per lane (D <= 2*K*LPL),
+// SRC census (fused cost) or a cost volume, OUT normalised uint8 partial or canonical
+// (unnormalised) export. With bands (a.lo != null) a lane's disparity outside the pixel's
+// band is an absent node; partials are then indexed by absolute disparity.
+template <int LPL, int K, int SRC, int OUT>
+__global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
+  const int lane = lane_id();
+  const int l = lane % LPL;
+  int r, ri, x0, y0, n, nmax;
+  block_line<LPL>(a, r, ri, x0, y0, n, nmax);
+  const int dx = c_dx[r], dy = c_dy[r];
+  const uint32_t lt = (uint32_t)(a.lambda * a.tau);
+  const bool banded = a.lo != nullptr;
+  uint32_t P[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) P[k] = 0;
+  uint32_t acc = 0;  // canonical offset: sum of the minima subtracted so far
+  uint8_t* part = a.part + (long long)ri * a.part_stride;
+
+  for (int t = 0; t < nmax; ++t) {
+    const bool act = t < n;
+    const int tt = act ? t : (n > 0 ? n - 1 : 0);
+    const int x = x0 + tt * dx, y = y0 + tt * dy;
+    const size_t p = (size_t)y * a.W + x;
+    int b0 = 0, bn = a.D;
+    if (banded) band_at(a.lo, a.len, p, a.D, a.cap, b0, bn);
+    // ---- matching cost of this pixel, two disparities per pair
+    uint32_t C[K];
+    if constexpr (SRC == SRC_CENSUS) {
+      const uint32_t* crow = a.cr + (size_t)y * a.cpitch + a.cmargin + x;
+      const uint32_t cl = a.cl[(size_t)y * a.cpitch + a.cmargin + x];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int d0 = 2 * (l * K + k);
+        uint32_t c0 = __popc(cl ^ crow[-d0]);
+        uint32_t c1 = __popc(cl ^ crow[-d0 - 1]);
+        c0 = (x - d0 >= 0) ? c0 : 24u;
+        c1 = (x - d0 - 1 >= 0) ? c1 : 24u;
+        c0 = (d0 < a.D && (!banded || (d0 >= b0 && d0 < b0 + bn))) ? c0 : INF16;
+        c1 = (d0 + 1 < a.D && (!banded || (d0 + 1 >= b0 && d0 + 1 < b0 + bn))) ? c1 : INF16;
+        C[k] = c0 | (c1 << 16);
+      }
+    } else {
+      const uint8_t* cp = a.cost + p * a.cap;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int d0 = 2 * (l * K + k);
+        const int j0 = d0 - b0, j1 = d0 + 1 - b0;
+        const uint32_t c0 = (d0 < a.D && j0 >= 0 && j0 < bn) ? (uint32_t)cp[j0] : INF16;
+        const uint32_t c1 = (d0 + 1 < a.D && j1 >= 0 && j1 < bn) ? (uint32_t)cp[j1] : INF16;
+        C[k] = c0 | (c1 << 16);
+      }
+    }
+    // ---- transition: min over predecessors of P(d') + lambda*min(|d-d'|, tau)
+    uint32_t L[K];
+    if (t == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) L[k] = C[k];
+    } else {
+      uint32_t A[K], B[K], T[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) A[k] = B[k] = P[k];
+      for (int s = 1; s < a.tau; s <<= 1) {
+        const uint32_t pen = splat16((uint32_t)(s * a.lambda));
+        shift_pairs_up<LPL, K>(A, T, s);
+#pragma unroll
+        for (int k = 0; k < K; ++k) A[k] = pk_min(A[k], pk_add(T[k], pen));
+        shift_pairs_down<LPL, K>(B, T, s);
+#pragma unroll
+        for (int k = 0; k < K; ++k) B[k] = pk_min(B[k], pk_add(T[k], pen));
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) L[k] = pk_add(C[k], pk_min(pk_min(A[k], B[k]), splat16(lt)));
+    }
+    // ---- normalise by the minimum over the line's disparities
+    uint32_t m = min(lo16(L[0]), hi16(L[0]));
+#pragma unroll
+    for (int k = 1; k < K; ++k) m = min(m, min(lo16(L[k]), hi16(L[k])));
+    m = group_min<LPL>(m);
+#pragma unroll
+    for (int k = 0; k < K; ++k) P[k] = pk_sub(L[k], splat16(m));
+    // ---- outputs
+    if (act) {
+      if constexpr (OUT == OUT_PART) {
+        uint8_t* dst = part + p * a.capP + 2 * l * K;
+        uint32_t w = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint32_t c = pk_min(P[k], 0x00FF00FFu);
+          w |= ((c & 0xFFu) | ((c >> 8) & 0xFF00u)) << (16 * k);
+        }
+        if constexpr (K == 1) {
+          *(uint16_t*)dst = (uint16_t)w;
+        } else {
+          *(uint32_t*)dst = w;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int d = 2 * (l * K + k) + h;
+            const int j = d - b0;
+            if (d < a.D && j >= 0 && j < bn) {
+              const uint32_t v = (h ? hi16(L[k]) : lo16(L[k])) + acc;
+              if constexpr (OUT == OUT_U16) {
+                uint16_t* s = (uint16_t*)a.agg + p * a.cap + j;
+                *s = a.first ? (uint16_t)v : (uint16_t)(*s + v);
+              } else {
+                int32_t* s = (int32_t*)a.agg + p * a.cap + j;
+                *s = a.first ? (int32_t)v : (int32_t)(*s + v);
+              }
+            }
+          }
+        }
+      }
+    }
+    acc += m;
+  }
+}
+
+// Banded scan: each pixel searches cap <= LPL - 2(tau-1) consecutive disparities starting
+// at lo(p); lane j holds d = lo(p) + j. Neighbouring pixels may place their bands
+// anywhere, so the envelope is built in the previous pixel's frame extended by tau-1
+// slots on each side, then lane j of the new pixel picks position j + lo(p) - lo(p-r).
+template <int LPL, int SRC, int OUT>
+__global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
+  const int lane = lane_id();
+  const int j = lane % LPL;
+  const int gbase = lane - j;
+  int r, ri, x0, y0, n, nmax;
+  block_line<LPL>(a, r, ri, x0, y0, n, nmax);
+  const int dx = c_dx[r], dy = c_dy[r];
+  const int e = a.tau - 1;
+  const uint32_t lt = (uint32_t)(a.lambda * a.tau);
+  uint32_t P = INF32;
+  int lo_prev = 0;
+  uint32_t acc = 0;
+  uint8_t* part = a.part + (long long)ri * a.part_stride;
+
+  for (int t = 0; t < nmax; ++t) {
+    const bool act = t < n;
+    const int tt = act ? t : (n > 0 ? n - 1 : 0);
+    const int x = x0 + tt * dx, y = y0 + tt * dy;
+    const size_t p = (size_t)y * a.W + x;
+    int b0, bn;
+    band_at(a.lo, a.len, p, a.D, a.cap, b0, bn);
+    const int d = b0 + j;
+    uint32_t C = INF32;
+    if constexpr (SRC == SRC_CENSUS) {
+      const uint32_t cl = a.cl[(size_t)y * a.cpitch + a.cmargin + x];
+      const int xd = x - min(d, a.D);  // stays within the census margin
+      const uint32_t cr = a.cr[(size_t)y * a.cpitch + a.cmargin + xd];
+      if (j < bn) C = (xd >= 0) ? (uint32_t)__popc(cl ^ cr) : 24u;
+    } else {
+      if (j < bn) C = a.cost[p * a.cap + j];
+    }
+    uint32_t L;
+    if (t == 0) {
+      L = C;
+    } else {
+      uint32_t A = shift_up<LPL>(P, e, INF32);  // extended frame: lane i <-> position i - e
+      uint32_t B = A;
+      for (int s = 1; s < a.tau; s <<= 1) {
+        const uint32_t pen = (uint32_t)(s * a.lambda);
+        A = min(A, shift_up<LPL>(A, s, INF32) + pen);
+        B = min(B, shift_down<LPL>(B, s, INF32) + pen);
+      }
+      const uint32_t E = min(A, B);
+      const int src = j + (b0 - lo_prev) + e;
+      const uint32_t got = (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2,
+                                                                  (int)E);
+      const uint32_t Ev = (src >= 0 && src < LPL) ? got : INF32;
+      L = C + min(Ev, lt);
+    }
+    const uint32_t m = group_min<LPL>(L);
+    P = (j < bn) ? L - m : INF32;
+    if (act) {
+      if constexpr (OUT == OUT_PART) {
+        if (j < a.capP) part[p * a.capP + j] = (uint8_t)min(P, 255u);
+      } else {
+        if (j < bn) {
+          const uint32_t v = L + acc;
+          if constexpr (OUT == OUT_U16) {
+            uint16_t* s = (uint16_t*)a.agg + p * a.cap + j;
+            *s = a.first ? (uint16_t)v : (uint16_t)(*s + v);
+          } else {
+            int32_t* s = (int32_t*)a.agg + p * a.cap + j;
+            *s = a.first ? (int32_t)v : (int32_t)(*s + v);
+          }
+        }
+      }
+    }
+    acc += m;
+    lo_prev = b0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Sum of paths + winner-take-all + right disparity + LR check. One block per image row.
+// ---------------------------------------------------------------------------------------
+enum { IN_PART = 0, IN_U16 = 1, IN_I32 = 2 };
+
+struct RedArgs {
+  int W, H, D;
+  int stride;  // slots per pixel of the input volume(s)
+  int bcap;    // band length where len == null (cap of the band, or D at full range)
+  const int16_t* lo;
+  const uint8_t* len;
+  int absolute;  // slot index = absolute disparity (partials of a banded full-range scan)
+  const uint8_t* part;
+  long long part_stride;
+  int npart;
+  const void* agg;
+  int lr;
+  int16_t* disp;
+  int16_t* right;
+  int16_t* raw;
+};
+
+constexpr int RED_MAXW = 4096;
+
+// Sum of the P normalised partials of SPL consecutive slots starting at q (SPL in {1,2,4}).
+// Every partial is <= 255 and P <= 8, so the 16-bit lanes of a packed sum never carry.
+template <int SPL>
+__device__ __forceinline__ void sum_partials(const uint8_t* q, long long stride, int np,
+                                             uint32_t (&v)[SPL]) {
+  if constexpr (SPL == 1) {
+    uint32_t s = 0;
+    for (int r = 0; r < np; ++r) s += q[r * stride];
+    v[0] = s;
+  } else if constexpr (SPL == 2) {
+    uint32_t s = 0;
+    for (int r = 0; r < np; ++r) {
+      const uint32_t w = *(const uint16_t*)(q + r * stride);
+      s += (w & 0xFFu) | ((w & 0xFF00u) << 8);
+    }
+    v[0] = s & 0xFFFFu;
+    v[1] = s >> 16;
+  } else {
+    uint32_t e = 0, o = 0;
+    for (int r = 0; r < np; ++r) {
+      const uint32_t w = *(const uint32_t*)(q + r * stride);
+      e += w & 0x00FF00FFu;
+      o += (w >> 8) & 0x00FF00FFu;
+    }
+    v[0] = e & 0xFFFFu;
+    v[1] = o & 0xFFFFu;
+    v[2] = e >> 16;
+    v[3] = o >> 16;
+  }
+}
+
+// Right-disparity key: smaller S' first, then the larger disparity (the nearer surface).
+__device__ __forceinline__ unsigned long long rkey(uint32_t sp, int d) {
+  return ((unsigned long long)sp << 9) | (unsigned long long)(511 - d);
+}
+constexpr unsigned long long NOKEY = ~0ull;
+
+template <int LPP, int SPL, int IN>
+__global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
+  __shared__ unsigned long long s_rkey[RED_MAXW];
+  __shared__ int16_t s_dl[RED_MAXW];
+  const int y = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int x = tid; x < a.W; x += 256) s_rkey[x] = NOKEY;
+  __syncthreads();
+  const int lane = lane_id();
+  const int wave = tid >> 6;
+  const int jl = lane % LPP;
+  const int pg = lane / LPP;
+  constexpr int PPW = 64 / LPP;  // pixels per wave step
+  const int xsteps = (a.W + 4 * PPW - 1) / (4 * PPW);
+  for (int it = 0; it < xsteps; ++it) {
+    const int x = (it * 4 + wave) * PPW + pg;
+    const bool xin = x < a.W;
+    const size_t p = (size_t)y * a.W + (xin ? x : a.W - 1);
+    int b0, bn;
+    band_at(a.lo, a.len, p, a.D, a.bcap, b0, bn);
+    const int j0 = jl * SPL;
+    uint32_t v[SPL];
+    if constexpr (IN == IN_PART) {
+      if (j0 < a.stride) {
+        sum_partials<SPL>(a.part + p * a.stride + j0, a.part_stride, a.npart, v);
+      } else {
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) v[s] = 0;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        const int jj = j0 + s;
+        v[s] = 0;
+        if (jj < a.stride) {
+          if constexpr (IN == IN_U16)
+            v[s] = ((const uint16_t*)a.agg)[p * a.stride + jj];
+          else
+            v[s] = (uint32_t)((const int32_t*)a.agg)[p * a.stride + jj];
+        }
+      }
+    }
+    bool valid[SPL];
+    uint32_t vmin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const int jj = j0 + s;
+      valid[s] = jj < a.stride && (a.absolute ? (jj >= b0 && jj < b0 + bn) : jj < bn);
+      if (valid[s]) vmin = min(vmin, v[s]);
+    }
+    const uint32_t ms = group_min<LPP>(vmin);
+    uint32_t jb = 0xFFFFu;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s)
+      if (valid[s] && v[s] == ms) jb = min(jb, (uint32_t)(j0 + s));
+    const int jstar = (int)group_min<LPP>(jb);
+    const int dl = a.absolute ? jstar : b0 + jstar;
+    if (xin) {
+      if (jl == 0) {
+        s_dl[x] = (int16_t)dl;
+        if (a.raw) a.raw[p] = (int16_t)dl;
+      }
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        if (!valid[s]) continue;
+        const int d = a.absolute ? j0 + s : b0 + j0 + s;
+        const int xr = x - d;
+        if (xr >= 0) atomicMin(&s_rkey[xr], rkey(v[s] - ms, d));
+      }
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < a.W; x += 256) {
+    const size_t p = (size_t)y * a.W + x;
+    const unsigned long long k = s_rkey[x];
+    if (a.right) a.right[p] = k == NOKEY ? (int16_t)-1 : (int16_t)(511 - (int)(k & 511ull));
+    const int dl = s_dl[x];
+    int16_t o = (int16_t)dl;
+    if (a.lr >= 0) {
+      o = -1;
+      if (x - dl >= 0) {
+        const unsigned long long kr = s_rkey[x - dl];
+        if (kr != NOKEY) {
+          const int dr = 511 - (int)(kr & 511ull);
+          if (abs(dl - dr) <= a.lr) o = (int16_t)dl;
+        }
+      }
+    }
+    if (a.disp) a.disp[p] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Coarse-to-fine band (Section 3.4): lo = clamp(2 * parent raw WTA - R, 0, Dl - cap)
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_propagate(const int16_t* __restrict__ coarse, int Wc,
+                                                   int Hc, int W, int H, int Dl, int R, int cap,
+                                                   int16_t* __restrict__ lo) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  const int cx = min(x >> 1, Wc - 1), cy = min(y >> 1, Hc - 1);
+  const int c = 2 * (int)coarse[(size_t)cy * Wc + cx];
+  lo[(size_t)y * W + x] = (int16_t)min(max(c - R, 0), Dl - cap);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ p, size_t n, T v) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    p[i] = v;
+}
+
+}  // namespace mpvk

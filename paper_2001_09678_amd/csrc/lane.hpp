@@ -1,0 +1,156 @@
+// Cross-lane building blocks for gfx950 (CDNA4, wave64).
+//
+// A Viterbi line is mapped to a group of LPL consecutive lanes (LPL = 16, 32 or 64), so
+// a wave carries 64/LPL lines. Neighbour exchange along the disparity axis is a lane
+// shift inside the group: DPP row/wave shifts, with lanes that would read outside the
+// group receiving a fill value. Group-wide minima use a rotate butterfly inside each
+// 16-lane row (DPP row_ror 8/4/2/1) and then the gfx950 permlane16/permlane32 swaps to
+// combine rows, which leaves the minimum in every lane of the group.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpvk {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// "Absent node" value of the 16-bit packed energies. Real normalised energies stay
+// below 24 + lambda*tau <= 4024 and an absent node never grows past INF16 + 3*4024,
+// so packed adds never wrap.
+constexpr uint32_t INF16 = 0x3FFFu;
+constexpr uint32_t INF2 = 0x3FFF3FFFu;
+constexpr uint32_t INF32 = 0x3FFFFFFFu;
+
+__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t splat16(uint32_t v) { return v | (v << 16); }
+__device__ __forceinline__ uint32_t lo16(uint32_t v) { return v & 0xFFFFu; }
+__device__ __forceinline__ uint32_t hi16(uint32_t v) { return v >> 16; }
+// (hi << 16) | (lo >> 16): the upper half of `lo` moves down, the lower half of `hi` moves up
+__device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) {
+  return __builtin_amdgcn_alignbit(hi, lo, 16);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// DPP controls (GFX9 encoding)
+constexpr int ROW_SHL1 = 0x101;
+constexpr int ROW_SHR1 = 0x111;
+constexpr int ROW_ROR1 = 0x121, ROW_ROR2 = 0x122, ROW_ROR4 = 0x124, ROW_ROR8 = 0x128;
+constexpr int WAVE_SHL1 = 0x130;
+constexpr int WAVE_SHR1 = 0x138;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Value of lane l-1 of the same group (fill for the group's first lane).
+template <int LPL>
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v, uint32_t fill) {
+  if constexpr (LPL == 16) {
+    return dpp<ROW_SHR1>(fill, v);
+  } else if constexpr (LPL == 64) {
+    return dpp<WAVE_SHR1>(fill, v);
+  } else {
+    uint32_t t = dpp<WAVE_SHR1>(fill, v);
+    return (lane_id() & 31) ? t : fill;
+  }
+}
+
+// Value of lane l+1 of the same group (fill for the group's last lane).
+template <int LPL>
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v, uint32_t fill) {
+  if constexpr (LPL == 16) {
+    return dpp<ROW_SHL1>(fill, v);
+  } else if constexpr (LPL == 64) {
+    return dpp<WAVE_SHL1>(fill, v);
+  } else {
+    uint32_t t = dpp<WAVE_SHL1>(fill, v);
+    return ((lane_id() & 31) != 31) ? t : fill;
+  }
+}
+
+// Value of lane l-n (n > 0: from below; n < 0: from above) of the same group, `fill`
+// where that lane is outside the group. Generic path through ds_bpermute.
+template <int LPL>
+__device__ __forceinline__ uint32_t from_lane_offset(uint32_t v, int n, uint32_t fill) {
+  const int lane = lane_id();
+  const int l = lane % LPL;
+  const int src = l - n;
+  const int got = __builtin_amdgcn_ds_bpermute((lane - n) << 2, (int)v);
+  return (src >= 0 && src < LPL) ? (uint32_t)got : fill;
+}
+
+// Lane shift by a small runtime amount inside 16-lane rows (DPP), any amount otherwise.
+template <int LPL>
+__device__ __forceinline__ uint32_t shift_up(uint32_t v, int n, uint32_t fill) {
+  if constexpr (LPL == 16) {
+    switch (n) {
+      case 0: return v;
+      case 1: return dpp<0x111>(fill, v);
+      case 2: return dpp<0x112>(fill, v);
+      case 3: return dpp<0x113>(fill, v);
+      case 4: return dpp<0x114>(fill, v);
+      case 5: return dpp<0x115>(fill, v);
+      case 6: return dpp<0x116>(fill, v);
+      case 7: return dpp<0x117>(fill, v);
+      case 8: return dpp<0x118>(fill, v);
+      default: return from_lane_offset<LPL>(v, n, fill);
+    }
+  } else {
+    if (n == 0) return v;
+    if (n == 1) return from_prev_lane<LPL>(v, fill);
+    return from_lane_offset<LPL>(v, n, fill);
+  }
+}
+
+template <int LPL>
+__device__ __forceinline__ uint32_t shift_down(uint32_t v, int n, uint32_t fill) {
+  if constexpr (LPL == 16) {
+    switch (n) {
+      case 0: return v;
+      case 1: return dpp<0x101>(fill, v);
+      case 2: return dpp<0x102>(fill, v);
+      case 3: return dpp<0x103>(fill, v);
+      case 4: return dpp<0x104>(fill, v);
+      case 5: return dpp<0x105>(fill, v);
+      case 6: return dpp<0x106>(fill, v);
+      case 7: return dpp<0x107>(fill, v);
+      case 8: return dpp<0x108>(fill, v);
+      default: return from_lane_offset<LPL>(v, -n, fill);
+    }
+  } else {
+    if (n == 0) return v;
+    if (n == 1) return from_next_lane<LPL>(v, fill);
+    return from_lane_offset<LPL>(v, -n, fill);
+  }
+}
+
+// Minimum over the LPL lanes of a group, returned in every lane of the group.
+template <int LPL>
+__device__ __forceinline__ uint32_t group_min(uint32_t v) {
+  v = min(v, dpp<ROW_ROR8>(v, v));
+  v = min(v, dpp<ROW_ROR4>(v, v));
+  v = min(v, dpp<ROW_ROR2>(v, v));
+  v = min(v, dpp<ROW_ROR1>(v, v));
+  if constexpr (LPL >= 32) {
+    auto s = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min((uint32_t)s[0], (uint32_t)s[1]);
+  }
+  if constexpr (LPL >= 64) {
+    auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    v = min((uint32_t)s[0], (uint32_t)s[1]);
+  }
+  return v;
+}
+
+}  // namespace mpvk

@@ -1,0 +1,198 @@
+"""Python face of the HIP MPV library: argument marshalling only.
+
+Every step of the matcher runs in the HIP kernels of ``libmpv.so``; this module allocates
+outputs and workspaces as torch tensors on the current device and passes their pointers
+and ``torch.cuda.current_stream()`` through the C ABI of include/mpv.h. Tensors must be
+CUDA (HIP) tensors; anything else is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as _L
+
+
+@dataclass(frozen=True)
+class MPVParams:
+    """Matcher parameters (eq. e(p,u) transition lambda*min(|d-d'|, tau); Table alg paths)."""
+    num_disp: int = 64
+    num_paths: int = 4
+    lam: int = 8
+    tau: int = 4
+    lr_max_diff: int = 1
+    agg_type: str = "u16"  # exported aggregate type: "u16" or "i32"
+
+    def c(self) -> _L.Params:
+        return _L.Params(self.num_disp, 2, self.num_paths, self.lam, self.tau, self.lr_max_diff,
+                         _L.MPV_AGG_U16 if self.agg_type == "u16" else _L.MPV_AGG_I32)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t
+
+
+def _image(t: torch.Tensor, name: str) -> _L.Image:
+    _dev(t, torch.uint8, name)
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D uint8 tensor with unit column stride")
+    return _L.Image(t.data_ptr(), t.shape[1], t.shape[0], t.stride(0))
+
+
+@dataclass
+class Band:
+    """Per-pixel search band: disparities lo .. lo+len-1 (len None: cap everywhere)."""
+    lo: torch.Tensor           # int16 [H][W]
+    cap: int
+    length: torch.Tensor | None = None  # uint8 [H][W]
+
+    def c(self) -> _L.Band:
+        _dev(self.lo, torch.int16, "band.lo")
+        ln = None
+        if self.length is not None:
+            ln = _dev(self.length, torch.uint8, "band.length").data_ptr()
+        return _L.Band(self.lo.contiguous().data_ptr(), ln, self.cap)
+
+
+def _band(band: Band | None):
+    return None if band is None else C.byref(band.c())
+
+
+def census(img: torch.Tensor) -> torch.Tensor:
+    im = _image(img, "img")
+    out = torch.empty((im.height, im.width), dtype=torch.int32, device=img.device)
+    _L.check(_L.lib().mpv_census(C.byref(im), out.data_ptr(), _stream()), "mpv_census")
+    return out
+
+
+def downsample(img: torch.Tensor) -> torch.Tensor:
+    im = _image(img, "img")
+    out = torch.empty((im.height // 2, im.width // 2), dtype=torch.uint8, device=img.device)
+    _L.check(_L.lib().mpv_downsample(C.byref(im), out.data_ptr(), _stream()), "mpv_downsample")
+    return out
+
+
+def cost(left: torch.Tensor, right: torch.Tensor, params: MPVParams, band: Band | None = None):
+    li, ri = _image(left, "left"), _image(right, "right")
+    cap = params.num_disp if band is None else band.cap
+    out = torch.empty((li.height, li.width, cap), dtype=torch.uint8, device=left.device)
+    p = params.c()
+    _L.check(_L.lib().mpv_cost(C.byref(p), C.byref(li), C.byref(ri), _band(band), out.data_ptr(),
+                               _stream()), "mpv_cost")
+    return out
+
+
+def aggregate(cost_vol: torch.Tensor, params: MPVParams, band: Band | None = None,
+              path_mask: int = 0) -> torch.Tensor:
+    """Unnormalised sum of the selected path energies. uint16 sums are returned in an
+    int16 tensor holding the same bits (view as uint16 to read them)."""
+    _dev(cost_vol, torch.uint8, "cost")
+    cost_vol = cost_vol.contiguous()
+    h, w, cap = cost_vol.shape
+    dt = torch.int16 if params.agg_type == "u16" else torch.int32
+    out = torch.empty((h, w, cap), dtype=dt, device=cost_vol.device)
+    p = params.c()
+    _L.check(_L.lib().mpv_aggregate(C.byref(p), cost_vol.data_ptr(), w, h, _band(band), path_mask,
+                                    out.data_ptr(), _stream()), "mpv_aggregate")
+    return out
+
+
+def disparity(agg: torch.Tensor, params: MPVParams, band: Band | None = None):
+    """WTA + right disparity + LR check on an aggregate volume. Returns (disp, right, raw)."""
+    want = torch.int16 if params.agg_type == "u16" else torch.int32
+    _dev(agg, want, "agg")
+    agg = agg.contiguous()
+    h, w, _ = agg.shape
+    outs = [torch.empty((h, w), dtype=torch.int16, device=agg.device) for _ in range(3)]
+    p = params.c()
+    _L.check(_L.lib().mpv_disparity(C.byref(p), agg.data_ptr(), w, h, _band(band),
+                                    outs[0].data_ptr(), outs[1].data_ptr(), outs[2].data_ptr(),
+                                    _stream()), "mpv_disparity")
+    return tuple(outs)
+
+
+def match_workspace_bytes(params: MPVParams, width: int, height: int, band: Band | None = None) -> int:
+    p = params.c()
+    return int(_L.lib().mpv_match_workspace_bytes(C.byref(p), width, height, _band(band)))
+
+
+def match(left, right, params: MPVParams, band: Band | None = None, workspace=None, want_all=False):
+    """One fused level (cost -> all paths -> sum -> WTA -> LR)."""
+    li, ri = _image(left, "left"), _image(right, "right")
+    need = match_workspace_bytes(params, li.width, li.height, band)
+    if need == 0:
+        raise _L.MPVError(_L.MPV_ERR_INVALID_ARG, "mpv_match_workspace_bytes")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=left.device)
+    disp = torch.empty((li.height, li.width), dtype=torch.int16, device=left.device)
+    right_d = torch.empty_like(disp) if want_all else None
+    raw = torch.empty_like(disp) if want_all else None
+    p = params.c()
+    _L.check(_L.lib().mpv_match(C.byref(p), C.byref(li), C.byref(ri), _band(band), disp.data_ptr(),
+                                None if right_d is None else right_d.data_ptr(),
+                                None if raw is None else raw.data_ptr(),
+                                workspace.data_ptr(), workspace.numel(), _stream()), "mpv_match")
+    return (disp, right_d, raw) if want_all else disp
+
+
+def pyramid_params(params: MPVParams, levels: int, radius: int) -> _L.PyramidParams:
+    return _L.PyramidParams(params.c(), levels, radius)
+
+
+def pyramid_workspace_bytes(params: MPVParams, levels: int, radius: int, width: int, height: int) -> int:
+    pp = pyramid_params(params, levels, radius)
+    return int(_L.lib().mpv_pyramid_workspace_bytes(C.byref(pp), width, height))
+
+
+class Pyramid:
+    """Multi-scale MPV (Section 3.4) on one pair shape, with its workspace held for reuse.
+
+    ``levels=1`` is plain single-scale MPV. Calling the object enqueues the whole path on the
+    current stream and returns the finest LR-checked disparity (int16, -1 invalid)."""
+
+    def __init__(self, params: MPVParams, width: int, height: int, levels: int = 3, radius: int = 4,
+                 device="cuda", keep_levels: bool = False):
+        self.params, self.width, self.height = params, width, height
+        self.levels, self.radius = levels, radius
+        self._pp = pyramid_params(params, levels, radius)
+        need = int(_L.lib().mpv_pyramid_workspace_bytes(C.byref(self._pp), width, height))
+        if need == 0:
+            raise _L.MPVError(_L.MPV_ERR_INVALID_ARG, "mpv_pyramid_workspace_bytes")
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
+        self.disp = torch.empty((height, width), dtype=torch.int16, device=device)
+        self.raw = torch.empty_like(self.disp)
+        self.right = torch.empty_like(self.disp)
+        self.level_raw = []
+        if keep_levels:
+            for l in range(levels):
+                s = levels - 1 - l
+                self.level_raw.append(torch.empty((height >> s, width >> s), dtype=torch.int16, device=device))
+        self._out = _L.PyramidOut(self.disp.data_ptr(), self.raw.data_ptr(), self.right.data_ptr())
+        for l, t in enumerate(self.level_raw):
+            self._out.level_raw[l] = t.data_ptr()
+
+    def __call__(self, left: torch.Tensor, right: torch.Tensor) -> torch.Tensor:
+        li, ri = _image(left, "left"), _image(right, "right")
+        if (li.width, li.height) != (self.width, self.height):
+            raise ValueError("pair shape differs from the shape this Pyramid was built for")
+        _L.check(_L.lib().mpv_pyramid(C.byref(self._pp), C.byref(li), C.byref(ri), C.byref(self._out),
+                                      self.workspace.data_ptr(), self.workspace.numel(), _stream()),
+                 "mpv_pyramid")
+        return self.disp
+
+
+def pyramid(left, right, params: MPVParams, levels=3, radius=4, keep_levels=False):
+    h, w = left.shape
+    pyr = Pyramid(params, w, h, levels, radius, device=left.device, keep_levels=keep_levels)
+    pyr(left, right)
+    return pyr

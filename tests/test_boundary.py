@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+entry point include/mpv.h declares, and rejects bad arguments before enqueueing work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2001_09678_amd import build, _lib
+    build.build(force=False)
+    return _lib
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "mpv.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpv_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = header_functions()
+    assert "mpv_pyramid" in names and "mpv_cost" in names and "mpv_aggregate" in names
+    assert "mpv_disparity" in names
+    raw = C.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+
+
+def test_status_strings(L):
+    lib = L.lib()
+    for s, name in enumerate(["MPV_OK", "MPV_ERR_INVALID_ARG", "MPV_ERR_UNSUPPORTED",
+                              "MPV_ERR_WORKSPACE", "MPV_ERR_OVERFLOW", "MPV_ERR_DEVICE"]):
+        assert lib.mpv_status_string(s).decode() == name
+    assert lib.mpv_status_string(99).decode() == "MPV_ERR_UNKNOWN"
+
+
+def _params(L, **kw):
+    d = dict(num_disp=64, census_radius=2, num_paths=4, lambda_=8, tau=4, lr_max_diff=1, agg_type=0)
+    d.update(kw)
+    return L.Params(**d)
+
+
+def test_validation_before_enqueue(L):
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    img = L.Image(fake, 32, 16, 32)
+    bad_img = L.Image(fake, 32, 16, 8)  # pitch < width
+    assert lib.mpv_census(None, fake, None) == L.MPV_ERR_INVALID_ARG
+    assert lib.mpv_census(C.byref(bad_img), fake, None) == L.MPV_ERR_INVALID_ARG
+    assert lib.mpv_cost(None, C.byref(img), C.byref(img), None, fake, None) == L.MPV_ERR_INVALID_ARG
+    for kw, st in [(dict(num_disp=0), L.MPV_ERR_INVALID_ARG), (dict(num_disp=257), L.MPV_ERR_INVALID_ARG),
+                   (dict(num_paths=3), L.MPV_ERR_INVALID_ARG), (dict(census_radius=3), L.MPV_ERR_UNSUPPORTED),
+                   (dict(tau=0), L.MPV_ERR_INVALID_ARG), (dict(lambda_=-1), L.MPV_ERR_INVALID_ARG),
+                   (dict(agg_type=7), L.MPV_ERR_INVALID_ARG)]:
+        p = _params(L, **kw)
+        assert lib.mpv_cost(C.byref(p), C.byref(img), C.byref(img), None, fake, None) == st, kw
+    # mismatched pair shapes
+    other = L.Image(fake, 31, 16, 32)
+    p = _params(L)
+    assert lib.mpv_cost(C.byref(p), C.byref(img), C.byref(other), None, fake, None) == L.MPV_ERR_INVALID_ARG
+    # a band wider than the range
+    band = L.Band(fake, None, 65)
+    assert lib.mpv_cost(C.byref(p), C.byref(img), C.byref(img), C.byref(band), fake, None) == L.MPV_ERR_INVALID_ARG
+
+
+def test_overflow_detected(L):
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    # 8 paths * 24 * 1280 > 65535: uint16 sums cannot hold 1280-wide lines
+    p = _params(L, num_disp=128, num_paths=8, agg_type=L.MPV_AGG_U16)
+    assert lib.mpv_aggregate(C.byref(p), fake, 1280, 720, None, 0, fake, None) == L.MPV_ERR_OVERFLOW
+    # the 320x240, 4-path workload fits uint16
+    p = _params(L, num_disp=64, num_paths=4, agg_type=L.MPV_AGG_U16)
+    assert lib.mpv_aggregate(C.byref(p), None, 320, 240, None, 0, fake, None) == L.MPV_ERR_INVALID_ARG
+
+
+def test_fused_limits(L):
+    lib = L.lib()
+    # 24 + lambda*min(tau, D-1) must fit the uint8 partial energies of the fused path
+    ok = L.PyramidParams(_params(L, num_disp=128, num_paths=8), 3, 4)
+    big = L.PyramidParams(_params(L, num_disp=128, num_paths=8, lambda_=60, tau=4), 3, 4)
+    assert lib.mpv_pyramid_workspace_bytes(C.byref(ok), 1280, 720) > 0
+    assert lib.mpv_pyramid_workspace_bytes(C.byref(big), 1280, 720) == 0
+    # too many levels for the image
+    deep = L.PyramidParams(_params(L, num_disp=128, num_paths=8), 4, 4)
+    assert lib.mpv_pyramid_workspace_bytes(C.byref(deep), 6, 6) == 0
+    # workspace too small is reported before any launch
+    fake = C.c_void_p(0x1000)
+    img = L.Image(fake, 1280, 720, 1280)
+    out = L.PyramidOut(fake, None, None)
+    assert lib.mpv_pyramid(C.byref(ok), C.byref(img), C.byref(img), C.byref(out), fake, 16, None) == L.MPV_ERR_WORKSPACE
+
+
+def test_workspace_model(L):
+    """Workspace = images of the coarse levels + per-level raw maps + band map + census of both
+    views + one uint8 energy volume per path (the largest level)."""
+    lib = L.lib()
+    pp = L.PyramidParams(_params(L, num_disp=128, num_paths=8), 1, 4)
+    ws = lib.mpv_pyramid_workspace_bytes(C.byref(pp), 1280, 720)
+    assert ws >= 8 * 1280 * 720 * 128
+    assert ws < 8 * 1280 * 720 * 128 + 32 * 2**20
