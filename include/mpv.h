@@ -175,6 +175,22 @@ mpv_status mpv_match(const mpv_params *p, const mpv_image *left, const mpv_image
                      const mpv_band *band, int16_t *disp, int16_t *disp_right, int16_t *disp_raw,
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Measurement hook (per-kernel timing without a profiler). Stages of one level: */
+#define MPV_STAGE_DOWNSAMPLE 0
+#define MPV_STAGE_CENSUS 1
+#define MPV_STAGE_SCAN 2      /* all P directions of one level, one launch */
+#define MPV_STAGE_REDUCE 3    /* sum + WTA + right disparity + LR of one level */
+#define MPV_STAGE_PROPAGATE 4
+#define MPV_NUM_STAGES 5
+
+/* While set, every later launch of `stage` at pyramid level `level` (0 = coarsest; the
+ * single level of mpv_match is level 0; -1 = any level) is bracketed by
+ * hipEventRecord(before) and hipEventRecord(after) on the launch stream. NULL events clear
+ * the hook. Process-wide host state, not synchronised: set it from the thread that
+ * enqueues, between calls. The events are the caller's; the library never creates or
+ * destroys them. */
+mpv_status mpv_set_timing_events(int32_t stage, int32_t level, hipEvent_t before, hipEvent_t after);
+
 #ifdef __cplusplus
 }
 #endif

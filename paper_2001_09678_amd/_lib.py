@@ -13,6 +13,7 @@ MPV_AGG_U16, MPV_AGG_I32 = 0, 1
 MPV_MAX_LEVELS = 4
 MPV_MAX_DISP = 256
 MPV_MAX_WIDTH = 4096
+STAGE_DOWNSAMPLE, STAGE_CENSUS, STAGE_SCAN, STAGE_REDUCE, STAGE_PROPAGATE = range(5)
 
 
 class Image(C.Structure):
@@ -69,6 +70,7 @@ def lib():
             "mpv_match_workspace_bytes": ([C.POINTER(Params), i32, i32, C.POINTER(Band)], S),
             "mpv_match": ([C.POINTER(Params), C.POINTER(Image), C.POINTER(Image), C.POINTER(Band),
                            P, P, P, P, S, P], i32),
+            "mpv_set_timing_events": ([i32, i32, P, P], i32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)

@@ -20,6 +20,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+#include <type_traits>
+
 #include "lane.hpp"
 
 namespace mpvk {
@@ -140,6 +143,7 @@ struct ScanArgs {
   int capP;               // partial slots per pixel
   void* agg;              // canonical export [H][W][cap]
   int first;              // canonical export: this direction writes instead of adding
+  uint8_t* sink;          // 256 B: stores of steps past a line's end land here
   int ndir;
   int dir[8];
   int gprefix[9];  // first block of each direction
@@ -175,26 +179,98 @@ __device__ __forceinline__ void line_info(int r, int i, int W, int H, int& x0, i
   }
 }
 
-// Block -> (direction, first line of this wave). One wave per block.
+// One Viterbi line: first pixel, step, length (group-uniform).
+struct Line {
+  int x0, y0, dx, dy, n;
+};
+
+// Pixel of step t (clamped to the line so that finished or empty lines stay in bounds).
+__device__ __forceinline__ size_t line_pixel(const Line& ln, int t, int W, int& x, int& y) {
+  const int tt = t < ln.n ? t : (ln.n > 0 ? ln.n - 1 : 0);
+  x = ln.x0 + tt * ln.dx;
+  y = ln.y0 + tt * ln.dy;
+  return (size_t)y * W + x;
+}
+
+// Block -> (direction, this group's line). One wave per block; nmax = longest line of the wave.
 template <int LPL>
-__device__ __forceinline__ void block_line(const ScanArgs& a, int& r, int& ri, int& x0, int& y0,
-                                           int& n, int& nmax) {
+__device__ __forceinline__ void block_line(const ScanArgs& a, int& r, int& ri, Line& ln, int& nmax) {
   const int b = blockIdx.x;
   ri = 0;
   while (ri + 1 < a.ndir && b >= a.gprefix[ri + 1]) ++ri;
   r = a.dir[ri];
+  ln.dx = c_dx[r];
+  ln.dy = c_dy[r];
   const int g = lane_id() / LPL;
   const int line = (b - a.gprefix[ri]) * (64 / LPL) + g;
   if (line < num_lines(r, a.W, a.H)) {
-    line_info(r, line, a.W, a.H, x0, y0, n);
+    line_info(r, line, a.W, a.H, ln.x0, ln.y0, ln.n);
   } else {
-    x0 = 0;
-    y0 = 0;
-    n = 0;
+    ln.x0 = 0;
+    ln.y0 = 0;
+    ln.n = 0;
   }
-  nmax = __builtin_amdgcn_readfirstlane(n);
+  nmax = __builtin_amdgcn_readfirstlane(ln.n);
 #pragma unroll
-  for (int k = 1; k < 64 / LPL; ++k) nmax = max(nmax, __builtin_amdgcn_readlane(n, k * LPL));
+  for (int k = 1; k < 64 / LPL; ++k) nmax = max(nmax, __builtin_amdgcn_readlane(ln.n, k * LPL));
+}
+
+// Compile-time loop: f(std::integral_constant<int, 0>) ... f(<N-1>).
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Lane K of each LPL-lane group, broadcast to the group (K < 16).
+template <int LPL, int K>
+__device__ __forceinline__ int group_bcast(int v) {
+  if constexpr (LPL == 64)
+    return __builtin_amdgcn_readlane(v, K);
+  else if constexpr (LPL == 32)
+    return __builtin_amdgcn_ds_swizzle(v, K << 5);
+  else
+    return __builtin_amdgcn_ds_swizzle(v, 0x10 | (K << 5));
+}
+
+// Per-step line data, staged a chunk at a time: lane k of a group holds step t0+k as one
+// packed word (left census in bits 0..23, band start in bits 24..31; D <= 256) plus, for
+// variable-length bands, the band length. Words are broadcast to the group PREFETCH steps
+// ahead of use, together with the per-lane right-census loads of that step.
+constexpr int CHUNK = 16;
+constexpr int PREFETCH = 4;
+
+// 32-bit offsets of step t's pixel along a line (clamped to the line).
+struct LineAddr {
+  int n;
+  int x0, dx;  // x
+  int p0, dp;  // y*W + x
+  int c0, dc;  // census offset y*cpitch + cmargin + x
+  __device__ __forceinline__ int tt(int t) const { return min(t, max(n - 1, 0)); }
+};
+
+__device__ __forceinline__ LineAddr line_addr(const ScanArgs& a, const Line& ln) {
+  LineAddr la;
+  la.n = ln.n;
+  la.x0 = ln.x0;
+  la.dx = ln.dx;
+  la.p0 = ln.y0 * a.W + ln.x0;
+  la.dp = ln.dy * a.W + ln.dx;
+  la.c0 = ln.y0 * a.cpitch + a.cmargin + ln.x0;
+  la.dc = ln.dy * a.cpitch + ln.dx;
+  return la;
+}
+
+template <bool BANDED, int SRC>
+__device__ __forceinline__ uint2 load_chunk(const ScanArgs& a, const LineAddr& la, int t0, int k) {
+  const int tt = la.tt(t0 + k);
+  int b0 = 0, bn = a.D;
+  if constexpr (BANDED) band_at(a.lo, a.len, (size_t)(la.p0 + tt * la.dp), a.D, a.cap, b0, bn);
+  const uint32_t cl = SRC == SRC_CENSUS ? a.cl[la.c0 + tt * la.dc] : 0u;
+  return make_uint2(cl | ((uint32_t)b0 << 24), (uint32_t)bn);
 }
 
 // Packed-pair shift of the disparity axis by s (s = 1 or even s) inside the group.
@@ -245,124 +321,243 @@ __device__ __forceinline__ void shift_pairs_down(const uint32_t (&v)[K], uint32_
   }
 }
 
+// Compile-time version of the packed-pair shifts (S = 1 or even S).
+template <int LPL, int K, int S>
+__device__ __forceinline__ void shift_pairs_up_c(const uint32_t (&v)[K], uint32_t (&o)[K]) {
+  if constexpr (S == 1) {
+    const uint32_t prev = from_prev_lane<LPL>(v[K - 1], INF2);
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = funnel16(v[k], k ? v[k - 1] : prev);
+  } else {
+    constexpr int q = S / 2, loff = q / K, rem = q % K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k - rem >= 0)
+        o[k] = shift_up_c<LPL, loff>(v[k - rem >= 0 ? k - rem : 0], INF2);
+      else
+        o[k] = shift_up_c<LPL, loff + 1>(v[k - rem + K], INF2);
+    }
+  }
+}
+
+template <int LPL, int K, int S>
+__device__ __forceinline__ void shift_pairs_down_c(const uint32_t (&v)[K], uint32_t (&o)[K]) {
+  if constexpr (S == 1) {
+    const uint32_t next = from_next_lane<LPL>(v[0], INF2);
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = funnel16(k + 1 < K ? v[k + 1] : next, v[k]);
+  } else {
+    constexpr int q = S / 2, loff = q / K, rem = q % K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k + rem < K)
+        o[k] = shift_down_c<LPL, loff>(v[k + rem < K ? k + rem : 0], INF2);
+      else
+        o[k] = shift_down_c<LPL, loff + 1>(v[k + rem - K], INF2);
+    }
+  }
+}
+
+// Envelope min_{|k|<tau} P(d+k) + lambda|k| of packed pairs by doubling sweeps
+// (TAU > 0: compile-time tau; TAU == 0: runtime tau).
+template <int LPL, int K, int TAU>
+__device__ __forceinline__ void pair_envelope(const uint32_t (&P)[K], uint32_t (&E)[K], int tau,
+                                              int lambda) {
+  uint32_t A[K], B[K], T[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) A[q] = B[q] = P[q];
+  if constexpr (TAU > 0) {
+    static_for<ceil_log2(TAU)>([&](auto ic) {
+      constexpr int S = 1 << decltype(ic)::value;
+      const uint32_t pen = splat16((uint32_t)(S * lambda));
+      shift_pairs_up_c<LPL, K, S>(A, T);
+#pragma unroll
+      for (int q = 0; q < K; ++q) A[q] = pk_min(A[q], pk_add(T[q], pen));
+      shift_pairs_down_c<LPL, K, S>(B, T);
+#pragma unroll
+      for (int q = 0; q < K; ++q) B[q] = pk_min(B[q], pk_add(T[q], pen));
+    });
+  } else {
+    for (int s = 1; s < tau; s <<= 1) {
+      const uint32_t pen = splat16((uint32_t)(s * lambda));
+      shift_pairs_up<LPL, K>(A, T, s);
+#pragma unroll
+      for (int q = 0; q < K; ++q) A[q] = pk_min(A[q], pk_add(T[q], pen));
+      shift_pairs_down<LPL, K>(B, T, s);
+#pragma unroll
+      for (int q = 0; q < K; ++q) B[q] = pk_min(B[q], pk_add(T[q], pen));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) E[q] = pk_min(A[q], B[q]);
+}
+
+// Band envelope in the previous pixel's frame extended by tau-1 lanes on each side.
+template <int LPL, int TAU>
+__device__ __forceinline__ uint32_t band_envelope(uint32_t P, int tau, int lambda) {
+  if constexpr (TAU > 0) {
+    uint32_t A = shift_up_c<LPL, TAU - 1>(P, INF32);
+    uint32_t B = A;
+    static_for<ceil_log2(TAU)>([&](auto ic) {
+      constexpr int S = 1 << decltype(ic)::value;
+      const uint32_t pen = (uint32_t)(S * lambda);
+      A = min(A, shift_up_c<LPL, S>(A, INF32) + pen);
+      B = min(B, shift_down_c<LPL, S>(B, INF32) + pen);
+    });
+    return min(A, B);
+  } else {
+    uint32_t A = shift_up<LPL>(P, tau - 1, INF32);
+    uint32_t B = A;
+    for (int s = 1; s < tau; s <<= 1) {
+      const uint32_t pen = (uint32_t)(s * lambda);
+      A = min(A, shift_up<LPL>(A, s, INF32) + pen);
+      B = min(B, shift_down<LPL>(B, s, INF32) + pen);
+    }
+    return min(A, B);
+  }
+}
+
+template <int OUT>
+__device__ __forceinline__ void export_canonical(void* agg, size_t idx, uint32_t v, int first) {
+  if constexpr (OUT == OUT_U16) {
+    uint16_t* s = (uint16_t*)agg + idx;
+    *s = first ? (uint16_t)v : (uint16_t)(*s + v);
+  } else {
+    int32_t* s = (int32_t*)agg + idx;
+    *s = first ? (int32_t)v : (int32_t)(*s + v);
+  }
+}
+
 // Full-range scan. Template: LPL lanes per line, K packed pairs per lane (D <= 2*K*LPL),
 // SRC census (fused cost) or a cost volume, OUT normalised uint8 partial or canonical
-// (unnormalised) export. With bands (a.lo != null) a lane's disparity outside the pixel's
-// band is an absent node; partials are then indexed by absolute disparity.
-template <int LPL, int K, int SRC, int OUT>
+// (unnormalised) export, TAU compile-time tau (0: runtime). BANDED: a lane's disparity
+// outside the pixel's band is an absent node; partials are then indexed by absolute
+// disparity.
+template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
 __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
   const int lane = lane_id();
   const int l = lane % LPL;
-  int r, ri, x0, y0, n, nmax;
-  block_line<LPL>(a, r, ri, x0, y0, n, nmax);
-  const int dx = c_dx[r], dy = c_dy[r];
+  const int kk = l % CHUNK;
+  int r, ri, nmax;
+  Line ln;
+  block_line<LPL>(a, r, ri, ln, nmax);
+  const LineAddr la = line_addr(a, ln);
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
-  const bool banded = a.lo != nullptr;
   uint32_t P[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) P[k] = 0;
   uint32_t acc = 0;  // canonical offset: sum of the minima subtracted so far
   uint8_t* part = a.part + (long long)ri * a.part_stride;
 
-  for (int t = 0; t < nmax; ++t) {
-    const bool act = t < n;
-    const int tt = act ? t : (n > 0 ? n - 1 : 0);
-    const int x = x0 + tt * dx, y = y0 + tt * dy;
-    const size_t p = (size_t)y * a.W + x;
-    int b0 = 0, bn = a.D;
-    if (banded) band_at(a.lo, a.len, p, a.D, a.cap, b0, bn);
-    // ---- matching cost of this pixel, two disparities per pair
-    uint32_t C[K];
+  uint32_t ring[PREFETCH][2 * K];  // right census of the lane's 2K candidates
+  uint32_t bw[PREFETCH];           // broadcast step words
+  int bl[PREFETCH];                // broadcast band lengths
+  auto fetch = [&](int t, uint32_t (&dst)[2 * K]) {
     if constexpr (SRC == SRC_CENSUS) {
-      const uint32_t* crow = a.cr + (size_t)y * a.cpitch + a.cmargin + x;
-      const uint32_t cl = a.cl[(size_t)y * a.cpitch + a.cmargin + x];
+      const uint32_t* crow = a.cr + (la.c0 + la.tt(t) * la.dc);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int d0 = 2 * (l * K + k);
-        uint32_t c0 = __popc(cl ^ crow[-d0]);
-        uint32_t c1 = __popc(cl ^ crow[-d0 - 1]);
-        c0 = (x - d0 >= 0) ? c0 : 24u;
-        c1 = (x - d0 - 1 >= 0) ? c1 : 24u;
-        c0 = (d0 < a.D && (!banded || (d0 >= b0 && d0 < b0 + bn))) ? c0 : INF16;
-        c1 = (d0 + 1 < a.D && (!banded || (d0 + 1 >= b0 && d0 + 1 < b0 + bn))) ? c1 : INF16;
-        C[k] = c0 | (c1 << 16);
-      }
-    } else {
-      const uint8_t* cp = a.cost + p * a.cap;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int d0 = 2 * (l * K + k);
-        const int j0 = d0 - b0, j1 = d0 + 1 - b0;
-        const uint32_t c0 = (d0 < a.D && j0 >= 0 && j0 < bn) ? (uint32_t)cp[j0] : INF16;
-        const uint32_t c1 = (d0 + 1 < a.D && j1 >= 0 && j1 < bn) ? (uint32_t)cp[j1] : INF16;
-        C[k] = c0 | (c1 << 16);
+        dst[2 * k] = crow[-d0];
+        dst[2 * k + 1] = crow[-d0 - 1];
       }
     }
-    // ---- transition: min over predecessors of P(d') + lambda*min(|d-d'|, tau)
-    uint32_t L[K];
-    if (t == 0) {
+  };
+  uint2 cur = load_chunk<BANDED, SRC>(a, la, 0, kk);
+  static_for<PREFETCH>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
+    if constexpr (BANDED) bl[q] = group_bcast<LPL, q>((int)cur.y);
+    fetch(q, ring[q]);
+  });
+
+  for (int t0 = 0; t0 < nmax; t0 += CHUNK) {
+    const uint2 nxt = load_chunk<BANDED, SRC>(a, la, t0 + CHUNK, kk);
+    static_for<CHUNK>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int slot = k % PREFETCH;
+      const int t = t0 + k;
+      const int tt = la.tt(t);
+      const int x = la.x0 + tt * la.dx;
+      const size_t p = (size_t)(la.p0 + tt * la.dp);
+      const uint32_t w = bw[slot];
+      const int b0 = BANDED ? (int)(w >> 24) : 0;
+      const int bn = BANDED ? bl[slot] : a.D;
+      uint32_t cr[2 * K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) L[k] = C[k];
-    } else {
-      uint32_t A[K], B[K], T[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) A[k] = B[k] = P[k];
-      for (int s = 1; s < a.tau; s <<= 1) {
-        const uint32_t pen = splat16((uint32_t)(s * a.lambda));
-        shift_pairs_up<LPL, K>(A, T, s);
-#pragma unroll
-        for (int k = 0; k < K; ++k) A[k] = pk_min(A[k], pk_add(T[k], pen));
-        shift_pairs_down<LPL, K>(B, T, s);
-#pragma unroll
-        for (int k = 0; k < K; ++k) B[k] = pk_min(B[k], pk_add(T[k], pen));
+      for (int q = 0; q < 2 * K; ++q) cr[q] = ring[slot][q];
+      {  // step t + PREFETCH: broadcast its word and issue its census loads
+        constexpr int kn = (k + PREFETCH) % CHUNK;
+        const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
+        bw[slot] = (uint32_t)group_bcast<LPL, kn>((int)src.x);
+        if constexpr (BANDED) bl[slot] = group_bcast<LPL, kn>((int)src.y);
+        fetch(t + PREFETCH, ring[slot]);
       }
+      // ---- matching cost of this pixel, two disparities per pair
+      uint32_t C[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) L[k] = pk_add(C[k], pk_min(pk_min(A[k], B[k]), splat16(lt)));
-    }
-    // ---- normalise by the minimum over the line's disparities
-    uint32_t m = min(lo16(L[0]), hi16(L[0]));
+      for (int q = 0; q < K; ++q) {
+        const int d0 = 2 * (l * K + q);
+        uint32_t c0, c1;
+        if constexpr (SRC == SRC_CENSUS) {
+          const uint32_t cl = w & 0xFFFFFFu;
+          c0 = (x - d0 >= 0) ? (uint32_t)__popc(cl ^ cr[2 * q]) : 24u;
+          c1 = (x - d0 - 1 >= 0) ? (uint32_t)__popc(cl ^ cr[2 * q + 1]) : 24u;
+        } else {
+          const uint8_t* cp = a.cost + p * a.cap;
+          const int j0 = min(max(d0 - b0, 0), a.cap - 1), j1 = min(max(d0 + 1 - b0, 0), a.cap - 1);
+          c0 = cp[j0];
+          c1 = cp[j1];
+        }
+        const bool in0 = d0 < a.D && (!BANDED || (d0 >= b0 && d0 < b0 + bn));
+        const bool in1 = d0 + 1 < a.D && (!BANDED || (d0 + 1 >= b0 && d0 + 1 < b0 + bn));
+        C[q] = (in0 ? c0 : INF16) | ((in1 ? c1 : INF16) << 16);
+      }
+      // ---- transition: min over predecessors of P(d') + lambda*min(|d-d'|, tau)
+      uint32_t E[K], L[K];
+      pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda);
+      const uint32_t mcap = t == 0 ? 0u : splat16(lt);  // the first pixel has no predecessor
 #pragma unroll
-    for (int k = 1; k < K; ++k) m = min(m, min(lo16(L[k]), hi16(L[k])));
-    m = group_min<LPL>(m);
+      for (int q = 0; q < K; ++q) L[q] = pk_add(C[q], pk_min(E[q], mcap));
+      // ---- normalise by the minimum over the line's disparities
+      uint32_t m = min(lo16(L[0]), hi16(L[0]));
 #pragma unroll
-    for (int k = 0; k < K; ++k) P[k] = pk_sub(L[k], splat16(m));
-    // ---- outputs
-    if (act) {
+      for (int q = 1; q < K; ++q) m = min(m, min(lo16(L[q]), hi16(L[q])));
+      m = group_min<LPL>(m);
+#pragma unroll
+      for (int q = 0; q < K; ++q) P[q] = pk_sub(L[q], splat16(m));
+      // ---- outputs
       if constexpr (OUT == OUT_PART) {
-        uint8_t* dst = part + p * a.capP + 2 * l * K;
-        uint32_t w = 0;
+        uint8_t* dst = t < la.n ? part + p * a.capP + 2 * l * K : a.sink + 4 * lane;
+        uint32_t v = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const uint32_t c = pk_min(P[k], 0x00FF00FFu);
-          w |= ((c & 0xFFu) | ((c >> 8) & 0xFF00u)) << (16 * k);
+        for (int q = 0; q < K; ++q) {
+          const uint32_t c = pk_min(P[q], 0x00FF00FFu);
+          v |= ((c & 0xFFu) | ((c >> 8) & 0xFF00u)) << (16 * q);
         }
         if constexpr (K == 1) {
-          *(uint16_t*)dst = (uint16_t)w;
+          *(uint16_t*)dst = (uint16_t)v;
         } else {
-          *(uint32_t*)dst = w;
+          *(uint32_t*)dst = v;
         }
       } else {
+        if (t < la.n) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+          for (int q = 0; q < K; ++q) {
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int d = 2 * (l * K + k) + h;
-            const int j = d - b0;
-            if (d < a.D && j >= 0 && j < bn) {
-              const uint32_t v = (h ? hi16(L[k]) : lo16(L[k])) + acc;
-              if constexpr (OUT == OUT_U16) {
-                uint16_t* s = (uint16_t*)a.agg + p * a.cap + j;
-                *s = a.first ? (uint16_t)v : (uint16_t)(*s + v);
-              } else {
-                int32_t* s = (int32_t*)a.agg + p * a.cap + j;
-                *s = a.first ? (int32_t)v : (int32_t)(*s + v);
-              }
+            for (int h = 0; h < 2; ++h) {
+              const int d = 2 * (l * K + q) + h;
+              const int j = d - b0;
+              if (d < a.D && j >= 0 && j < bn)
+                export_canonical<OUT>(a.agg, p * a.cap + j, (h ? hi16(L[q]) : lo16(L[q])) + acc,
+                                      a.first);
             }
           }
         }
       }
-    }
-    acc += m;
+      acc += m;
+    });
+    cur = nxt;
   }
 }
 
@@ -370,14 +565,17 @@ __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
 // at lo(p); lane j holds d = lo(p) + j. Neighbouring pixels may place their bands
 // anywhere, so the envelope is built in the previous pixel's frame extended by tau-1
 // slots on each side, then lane j of the new pixel picks position j + lo(p) - lo(p-r).
-template <int LPL, int SRC, int OUT>
+// VAR: per-pixel band lengths (otherwise every pixel has len = cap).
+template <int LPL, int SRC, int OUT, int TAU, bool VAR>
 __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
   const int lane = lane_id();
   const int j = lane % LPL;
+  const int kk = j % CHUNK;
   const int gbase = lane - j;
-  int r, ri, x0, y0, n, nmax;
-  block_line<LPL>(a, r, ri, x0, y0, n, nmax);
-  const int dx = c_dx[r], dy = c_dy[r];
+  int r, ri, nmax;
+  Line ln;
+  block_line<LPL>(a, r, ri, ln, nmax);
+  const LineAddr la = line_addr(a, ln);
   const int e = a.tau - 1;
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
   uint32_t P = INF32;
@@ -385,61 +583,72 @@ __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
   uint32_t acc = 0;
   uint8_t* part = a.part + (long long)ri * a.part_stride;
 
-  for (int t = 0; t < nmax; ++t) {
-    const bool act = t < n;
-    const int tt = act ? t : (n > 0 ? n - 1 : 0);
-    const int x = x0 + tt * dx, y = y0 + tt * dy;
-    const size_t p = (size_t)y * a.W + x;
-    int b0, bn;
-    band_at(a.lo, a.len, p, a.D, a.cap, b0, bn);
-    const int d = b0 + j;
-    uint32_t C = INF32;
+  uint32_t ring[PREFETCH];  // right census of this lane's candidate
+  uint32_t bw[PREFETCH];    // broadcast step words (left census | band start << 24)
+  int bl[PREFETCH];         // broadcast band lengths
+  auto fetch = [&](int t, uint32_t w) -> uint32_t {
     if constexpr (SRC == SRC_CENSUS) {
-      const uint32_t cl = a.cl[(size_t)y * a.cpitch + a.cmargin + x];
-      const int xd = x - min(d, a.D);  // stays within the census margin
-      const uint32_t cr = a.cr[(size_t)y * a.cpitch + a.cmargin + xd];
-      if (j < bn) C = (xd >= 0) ? (uint32_t)__popc(cl ^ cr) : 24u;
+      const int b0 = (int)(w >> 24);
+      return a.cr[la.c0 + la.tt(t) * la.dc - min(b0 + j, a.D)];  // stays within the margin
     } else {
-      if (j < bn) C = a.cost[p * a.cap + j];
+      return 0u;
     }
-    uint32_t L;
-    if (t == 0) {
-      L = C;
-    } else {
-      uint32_t A = shift_up<LPL>(P, e, INF32);  // extended frame: lane i <-> position i - e
-      uint32_t B = A;
-      for (int s = 1; s < a.tau; s <<= 1) {
-        const uint32_t pen = (uint32_t)(s * a.lambda);
-        A = min(A, shift_up<LPL>(A, s, INF32) + pen);
-        B = min(B, shift_down<LPL>(B, s, INF32) + pen);
+  };
+  uint2 cur = load_chunk<true, SRC>(a, la, 0, kk);
+  static_for<PREFETCH>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
+    if constexpr (VAR) bl[q] = group_bcast<LPL, q>((int)cur.y);
+    ring[q] = fetch(q, bw[q]);
+  });
+
+  for (int t0 = 0; t0 < nmax; t0 += CHUNK) {
+    const uint2 nxt = load_chunk<true, SRC>(a, la, t0 + CHUNK, kk);
+    static_for<CHUNK>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int slot = k % PREFETCH;
+      const int t = t0 + k;
+      const int tt = la.tt(t);
+      const int x = la.x0 + tt * la.dx;
+      const size_t p = (size_t)(la.p0 + tt * la.dp);
+      const uint32_t w = bw[slot];
+      const int b0 = (int)(w >> 24);
+      const int bn = VAR ? bl[slot] : a.cap;
+      const uint32_t crv = ring[slot];
+      {  // step t + PREFETCH: broadcast its word and issue its census load
+        constexpr int kn = (k + PREFETCH) % CHUNK;
+        const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
+        const uint32_t wn = (uint32_t)group_bcast<LPL, kn>((int)src.x);
+        if constexpr (VAR) bl[slot] = group_bcast<LPL, kn>((int)src.y);
+        bw[slot] = wn;
+        ring[slot] = fetch(t + PREFETCH, wn);
       }
-      const uint32_t E = min(A, B);
-      const int src = j + (b0 - lo_prev) + e;
-      const uint32_t got = (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2,
-                                                                  (int)E);
-      const uint32_t Ev = (src >= 0 && src < LPL) ? got : INF32;
-      L = C + min(Ev, lt);
-    }
-    const uint32_t m = group_min<LPL>(L);
-    P = (j < bn) ? L - m : INF32;
-    if (act) {
-      if constexpr (OUT == OUT_PART) {
-        if (j < a.capP) part[p * a.capP + j] = (uint8_t)min(P, 255u);
+      uint32_t C;
+      if constexpr (SRC == SRC_CENSUS) {
+        // written as a sum so that the popcount is always evaluated (no branch)
+        const uint32_t pc = (uint32_t)__popc((w & 0xFFFFFFu) ^ crv);
+        C = ((x - b0 - j >= 0) ? pc : 24u) + ((j < bn) ? 0u : INF32);
       } else {
-        if (j < bn) {
-          const uint32_t v = L + acc;
-          if constexpr (OUT == OUT_U16) {
-            uint16_t* s = (uint16_t*)a.agg + p * a.cap + j;
-            *s = a.first ? (uint16_t)v : (uint16_t)(*s + v);
-          } else {
-            int32_t* s = (int32_t*)a.agg + p * a.cap + j;
-            *s = a.first ? (int32_t)v : (int32_t)(*s + v);
-          }
-        }
+        C = (j < bn) ? (uint32_t)a.cost[p * a.cap + min(j, a.cap - 1)] : INF32;
       }
-    }
-    acc += m;
-    lo_prev = b0;
+      const uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda);  // lane i <-> position i - e
+      const int src = j + (b0 - lo_prev) + e;
+      const uint32_t got =
+          (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, (int)E);
+      const uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
+      const uint32_t L = C + (t == 0 ? 0u : min(Ev, lt));
+      const uint32_t m = group_min<LPL>(L);
+      P = (j < bn) ? L - m : INF32;
+      if constexpr (OUT == OUT_PART) {
+        uint8_t* dst = t < la.n ? part + p * a.capP + j : a.sink + lane;
+        *dst = (uint8_t)min(P, 255u);
+      } else {
+        if (t < la.n && j < bn) export_canonical<OUT>(a.agg, p * a.cap + j, L + acc, a.first);
+      }
+      acc += m;
+      lo_prev = b0;
+    });
+    cur = nxt;
   }
 }
 
@@ -590,6 +799,99 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
           const int dr = 511 - (int)(kr & 511ull);
           if (abs(dl - dr) <= a.lr) o = (int16_t)dl;
         }
+      }
+    }
+    if (a.disp) a.disp[p] = o;
+  }
+}
+
+// Fused-path reduce over the P uint8 partial volumes: a lane owns 16 consecutive slots of
+// one pixel (one 16-byte load per partial), LPP = stride/16 lanes per pixel, 64/LPP
+// pixels per wave step. Sums fit 16 bits (P * 255), so two slots share a register.
+// need_lr = false (intermediate pyramid levels) writes the raw winner only.
+template <int LPP>
+__global__ __launch_bounds__(256) void k_reduce_part(RedArgs a, int need_lr) {
+  __shared__ uint32_t s_rkey[RED_MAXW];
+  __shared__ int16_t s_dl[RED_MAXW];
+  constexpr uint32_t NOK = 0xFFFFFFFFu;
+  const int y = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (need_lr) {
+    for (int x = tid; x < a.W; x += 256) s_rkey[x] = NOK;
+    __syncthreads();
+  }
+  const int lane = lane_id();
+  const int wave = tid >> 6;
+  const int jl = lane % LPP;
+  const int j0 = jl * 16;
+  constexpr int PPW = 64 / LPP;  // pixels per wave step
+  const int xsteps = (a.W + 4 * PPW - 1) / (4 * PPW);
+  for (int it = 0; it < xsteps; ++it) {
+    const int x = (it * 4 + wave) * PPW + lane / LPP;
+    const bool xin = x < a.W;
+    const size_t p = (size_t)y * a.W + (xin ? x : a.W - 1);
+    int b0, bn;
+    band_at(a.lo, a.len, p, a.D, a.bcap, b0, bn);
+    // s[2q]: slots 4q (lo), 4q+2 (hi); s[2q+1]: slots 4q+1 (lo), 4q+3 (hi)
+    uint32_t sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint8_t* q0 = a.part + p * a.stride + j0;
+    for (int r = 0; r < a.npart; ++r) {
+      const uint4 w = *(const uint4*)(q0 + r * a.part_stride);
+      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        sm[2 * q] += ws[q] & 0x00FF00FFu;
+        sm[2 * q + 1] += (ws[q] >> 8) & 0x00FF00FFu;
+      }
+    }
+    uint32_t v[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[4 * q + 0] = sm[2 * q] & 0xFFFFu;
+      v[4 * q + 1] = sm[2 * q + 1] & 0xFFFFu;
+      v[4 * q + 2] = sm[2 * q] >> 16;
+      v[4 * q + 3] = sm[2 * q + 1] >> 16;
+    }
+    uint32_t best = NOK;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int jj = j0 + i;
+      const bool ok = a.absolute ? (jj >= b0 && jj < b0 + bn) : jj < bn;
+      best = min(best, ok ? (v[i] << 9) | (uint32_t)jj : NOK);
+    }
+    best = small_group_min<LPP>(best);
+    const uint32_t ms = best >> 9;
+    const int jstar = (int)(best & 511u);
+    const int dl = a.absolute ? jstar : b0 + jstar;
+    if (xin) {
+      if (jl == 0) {
+        if (a.raw) a.raw[p] = (int16_t)dl;
+        if (need_lr) s_dl[x] = (int16_t)dl;
+      }
+      if (need_lr) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int jj = j0 + i;
+          const bool ok = a.absolute ? (jj >= b0 && jj < b0 + bn) : jj < bn;
+          const int d = a.absolute ? jj : b0 + jj;
+          if (ok && x - d >= 0) atomicMin(&s_rkey[x - d], ((v[i] - ms) << 9) | (uint32_t)(511 - d));
+        }
+      }
+    }
+  }
+  if (!need_lr) return;
+  __syncthreads();
+  for (int x = tid; x < a.W; x += 256) {
+    const size_t p = (size_t)y * a.W + x;
+    const uint32_t k = s_rkey[x];
+    if (a.right) a.right[p] = k == NOK ? (int16_t)-1 : (int16_t)(511 - (int)(k & 511u));
+    const int dl = s_dl[x];
+    int16_t o = (int16_t)dl;
+    if (a.lr >= 0) {
+      o = -1;
+      if (x - dl >= 0) {
+        const uint32_t kr = s_rkey[x - dl];
+        if (kr != NOK && abs(dl - (511 - (int)(kr & 511u))) <= a.lr) o = (int16_t)dl;
       }
     }
     if (a.disp) a.disp[p] = o;

@@ -135,6 +135,33 @@ __device__ __forceinline__ uint32_t shift_down(uint32_t v, int n, uint32_t fill)
   }
 }
 
+// Compile-time lane shifts: value of lane l-N (up) / l+N (down) of the same group.
+template <int LPL, int N>
+__device__ __forceinline__ uint32_t shift_up_c(uint32_t v, uint32_t fill) {
+  if constexpr (N == 0)
+    return v;
+  else if constexpr (LPL == 16)
+    return dpp<0x110 + N>(fill, v);  // row_shr:N
+  else if constexpr (N == 1)
+    return from_prev_lane<LPL>(v, fill);
+  else
+    return from_lane_offset<LPL>(v, N, fill);
+}
+
+template <int LPL, int N>
+__device__ __forceinline__ uint32_t shift_down_c(uint32_t v, uint32_t fill) {
+  if constexpr (N == 0)
+    return v;
+  else if constexpr (LPL == 16)
+    return dpp<0x100 + N>(fill, v);  // row_shl:N
+  else if constexpr (N == 1)
+    return from_next_lane<LPL>(v, fill);
+  else
+    return from_lane_offset<LPL>(v, -N, fill);
+}
+
+constexpr int ceil_log2(int v) { return v <= 1 ? 0 : 1 + ceil_log2((v + 1) / 2); }
+
 // Minimum over the LPL lanes of a group, returned in every lane of the group.
 template <int LPL>
 __device__ __forceinline__ uint32_t group_min(uint32_t v) {
@@ -150,6 +177,16 @@ __device__ __forceinline__ uint32_t group_min(uint32_t v) {
     auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
     v = min((uint32_t)s[0], (uint32_t)s[1]);
   }
+  return v;
+}
+
+// Minimum over aligned groups of N lanes (N = 1, 2, 4, 8, 16), in every lane of the group.
+template <int N>
+__device__ __forceinline__ uint32_t small_group_min(uint32_t v) {
+  if constexpr (N >= 2) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
+  if constexpr (N >= 4) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
+  if constexpr (N >= 8) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));
+  if constexpr (N >= 16) v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));
   return v;
 }
 

@@ -50,6 +50,28 @@ mpv_status launched() {
   return hipGetLastError() == hipSuccess ? MPV_OK : MPV_ERR_DEVICE;
 }
 
+// ---- timing hook -------------------------------------------------------------------------
+struct TimingHook {
+  int level = -2;  // -2: unset
+  hipEvent_t before = nullptr, after = nullptr;
+};
+TimingHook g_hook[MPV_NUM_STAGES];
+
+struct HookScope {  // records the stage's events around the launches made in its lifetime
+  const TimingHook* h;
+  hipStream_t s;
+  HookScope(int stage, int level, hipStream_t st) : h(nullptr), s(st) {
+    const TimingHook& t = g_hook[stage];
+    if (t.before && (t.level == -1 || t.level == level)) {
+      h = &t;
+      (void)hipEventRecord(t.before, s);
+    }
+  }
+  ~HookScope() {
+    if (h) (void)hipEventRecord(h->after, s);
+  }
+};
+
 // ---- scan layout -------------------------------------------------------------------------
 struct FullLayout {
   int LPL, K;
@@ -109,26 +131,73 @@ int plan_dirs(ScanArgs& a, const int* dirs, int ndir, int LPL) {
   return blocks;
 }
 
+// tau (already reduced to min(tau, D-1)) is a compile-time parameter for 1..4 on the fused
+// path, so the envelope is a fixed sequence of DPP shifts; other values, and the unfused
+// export path, take the runtime-tau kernels.
+template <int SRC, int OUT, int TAU, bool BANDED>
+void launch_full_t(const ScanArgs& a, int LPL, int K, int blocks, hipStream_t s) {
+  if (LPL == 16)
+    hipLaunchKernelGGL((k_scan_full<16, 1, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
+  else if (LPL == 32)
+    hipLaunchKernelGGL((k_scan_full<32, 1, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
+  else if (K == 1)
+    hipLaunchKernelGGL((k_scan_full<64, 1, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_scan_full<64, 2, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
+}
+
+template <int SRC, int OUT, bool BANDED>
+void launch_full_b(const ScanArgs& a, int LPL, int K, int blocks, hipStream_t s) {
+  if constexpr (OUT == OUT_PART) {
+    switch (a.tau) {
+      case 1: launch_full_t<SRC, OUT, 1, BANDED>(a, LPL, K, blocks, s); return;
+      case 2: launch_full_t<SRC, OUT, 2, BANDED>(a, LPL, K, blocks, s); return;
+      case 3: launch_full_t<SRC, OUT, 3, BANDED>(a, LPL, K, blocks, s); return;
+      case 4: launch_full_t<SRC, OUT, 4, BANDED>(a, LPL, K, blocks, s); return;
+      default: break;
+    }
+  }
+  launch_full_t<SRC, OUT, 0, BANDED>(a, LPL, K, blocks, s);
+}
+
 template <int SRC, int OUT>
 void launch_full(const ScanArgs& a, int LPL, int K, int blocks, hipStream_t s) {
-  if (LPL == 16)
-    hipLaunchKernelGGL((k_scan_full<16, 1, SRC, OUT>), dim3(blocks), dim3(64), 0, s, a);
-  else if (LPL == 32)
-    hipLaunchKernelGGL((k_scan_full<32, 1, SRC, OUT>), dim3(blocks), dim3(64), 0, s, a);
-  else if (K == 1)
-    hipLaunchKernelGGL((k_scan_full<64, 1, SRC, OUT>), dim3(blocks), dim3(64), 0, s, a);
+  if (a.lo)
+    launch_full_b<SRC, OUT, true>(a, LPL, K, blocks, s);
   else
-    hipLaunchKernelGGL((k_scan_full<64, 2, SRC, OUT>), dim3(blocks), dim3(64), 0, s, a);
+    launch_full_b<SRC, OUT, false>(a, LPL, K, blocks, s);
+}
+
+template <int SRC, int OUT, int TAU, bool VAR>
+void launch_band_v(const ScanArgs& a, int LPL, int blocks, hipStream_t s) {
+  if (LPL == 16)
+    hipLaunchKernelGGL((k_scan_band<16, SRC, OUT, TAU, VAR>), dim3(blocks), dim3(64), 0, s, a);
+  else if (LPL == 32)
+    hipLaunchKernelGGL((k_scan_band<32, SRC, OUT, TAU, VAR>), dim3(blocks), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_scan_band<64, SRC, OUT, TAU, VAR>), dim3(blocks), dim3(64), 0, s, a);
+}
+
+template <int SRC, int OUT, int TAU>
+void launch_band_t(const ScanArgs& a, int LPL, int blocks, hipStream_t s) {
+  if (a.len)
+    launch_band_v<SRC, OUT, TAU, true>(a, LPL, blocks, s);
+  else
+    launch_band_v<SRC, OUT, TAU, false>(a, LPL, blocks, s);
 }
 
 template <int SRC, int OUT>
 void launch_band(const ScanArgs& a, int LPL, int blocks, hipStream_t s) {
-  if (LPL == 16)
-    hipLaunchKernelGGL((k_scan_band<16, SRC, OUT>), dim3(blocks), dim3(64), 0, s, a);
-  else if (LPL == 32)
-    hipLaunchKernelGGL((k_scan_band<32, SRC, OUT>), dim3(blocks), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_scan_band<64, SRC, OUT>), dim3(blocks), dim3(64), 0, s, a);
+  if constexpr (OUT == OUT_PART) {
+    switch (a.tau) {
+      case 1: launch_band_t<SRC, OUT, 1>(a, LPL, blocks, s); return;
+      case 2: launch_band_t<SRC, OUT, 2>(a, LPL, blocks, s); return;
+      case 3: launch_band_t<SRC, OUT, 3>(a, LPL, blocks, s); return;
+      case 4: launch_band_t<SRC, OUT, 4>(a, LPL, blocks, s); return;
+      default: break;
+    }
+  }
+  launch_band_t<SRC, OUT, 0>(a, LPL, blocks, s);
 }
 
 template <int IN>
@@ -146,11 +215,21 @@ void launch_reduce(const RedArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_reduce<64, 4, IN>), dim3(a.H), dim3(256), 0, s, a);
 }
 
+void launch_reduce_part(const RedArgs& a, int need_lr, hipStream_t s) {
+  switch (a.stride / 16) {
+    case 1: hipLaunchKernelGGL(k_reduce_part<1>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
+    case 2: hipLaunchKernelGGL(k_reduce_part<2>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
+    case 4: hipLaunchKernelGGL(k_reduce_part<4>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
+    case 8: hipLaunchKernelGGL(k_reduce_part<8>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
+    default: hipLaunchKernelGGL(k_reduce_part<16>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
+  }
+}
+
 dim3 pix_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
 
 // ---- one fused level -------------------------------------------------------------------
 struct LevelWs {
-  size_t census_off, part_off, total;
+  size_t sink_off, census_off, part_off, total;
   int cpitch, cmargin;
   ScanChoice sc;
 };
@@ -161,9 +240,10 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band) {
   const int dpad = full_layout(p->num_disp).dpad();
   w.cmargin = (int)align_up((size_t)std::max(dpad, p->num_disp) + 1, 16);
   w.cpitch = w.cmargin + W;
-  w.census_off = 0;
+  w.sink_off = 0;
+  w.census_off = ALIGN;
   const size_t cen = align_up((size_t)H * w.cpitch * sizeof(uint32_t));
-  w.part_off = 2 * cen;
+  w.part_off = w.census_off + 2 * cen;
   w.total = w.part_off + align_up((size_t)p->num_paths * H * W * w.sc.capP);
   return w;
 }
@@ -171,15 +251,18 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band) {
 // census(L), census(R) -> all P directions -> reduce. disp may be null (intermediate level).
 mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const uint8_t* R,
                      int rpitch, int W, int H, const mpv_band* band, int16_t* disp,
-                     int16_t* right, int16_t* raw, uint8_t* ws, hipStream_t s) {
+                     int16_t* right, int16_t* raw, uint8_t* ws, int level, hipStream_t s) {
   const LevelWs lw = level_ws(p, W, H, band);
   uint32_t* cl = (uint32_t*)(ws + lw.census_off);
   uint32_t* cr = cl + align_up((size_t)H * lw.cpitch * sizeof(uint32_t)) / sizeof(uint32_t);
   uint8_t* part = ws + lw.part_off;
-  hipLaunchKernelGGL(k_census, pix_grid(W, H), dim3(256), 0, s, L, W, H, lpitch, cl, lw.cpitch,
-                     lw.cmargin);
-  hipLaunchKernelGGL(k_census, pix_grid(W, H), dim3(256), 0, s, R, W, H, rpitch, cr, lw.cpitch,
-                     lw.cmargin);
+  {
+    HookScope hs(MPV_STAGE_CENSUS, level, s);
+    hipLaunchKernelGGL(k_census, pix_grid(W, H), dim3(256), 0, s, L, W, H, lpitch, cl, lw.cpitch,
+                       lw.cmargin);
+    hipLaunchKernelGGL(k_census, pix_grid(W, H), dim3(256), 0, s, R, W, H, rpitch, cr, lw.cpitch,
+                       lw.cmargin);
+  }
   ScanArgs a{};
   a.W = W;
   a.H = H;
@@ -194,15 +277,19 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
   a.lo = band ? band->lo : nullptr;
   a.len = (band && band->lo) ? band->len : nullptr;
   a.part = part;
+  a.sink = ws + lw.sink_off;
   a.capP = lw.sc.capP;
   a.part_stride = (long long)H * W * lw.sc.capP;
   int dirs[8];
   for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
   const int blocks = plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
-  if (lw.sc.banded_kernel)
-    launch_band<SRC_CENSUS, OUT_PART>(a, lw.sc.LPL, blocks, s);
-  else
-    launch_full<SRC_CENSUS, OUT_PART>(a, lw.sc.LPL, lw.sc.K, blocks, s);
+  {
+    HookScope hs(MPV_STAGE_SCAN, level, s);
+    if (lw.sc.banded_kernel)
+      launch_band<SRC_CENSUS, OUT_PART>(a, lw.sc.LPL, blocks, s);
+    else
+      launch_full<SRC_CENSUS, OUT_PART>(a, lw.sc.LPL, lw.sc.K, blocks, s);
+  }
   RedArgs ra{};
   ra.W = W;
   ra.H = H;
@@ -219,7 +306,10 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
   ra.disp = disp;
   ra.right = right;
   ra.raw = raw;
-  launch_reduce<IN_PART>(ra, s);
+  {
+    HookScope hs(MPV_STAGE_REDUCE, level, s);
+    launch_reduce_part(ra, (disp || right) ? 1 : 0, s);
+  }
   return launched();
 }
 
@@ -430,7 +520,7 @@ mpv_status mpv_match(const mpv_params* p, const mpv_image* left, const mpv_image
   const size_t need = level_ws(p, left->width, left->height, band).total;
   if (!workspace || workspace_bytes < need) return MPV_ERR_WORKSPACE;
   return run_level(p, left->data, left->pitch, right->data, right->pitch, left->width,
-                   left->height, band, disp, disp_right, disp_raw, (uint8_t*)workspace, stream);
+                   left->height, band, disp, disp_right, disp_raw, (uint8_t*)workspace, 0, stream);
 }
 
 size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params* p, int32_t W, int32_t H) {
@@ -462,6 +552,7 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
   for (int l = L - 2; l >= 0; --l) {
     uint8_t* dl = ws + w.img_off[l];
     uint8_t* dr = dl + (size_t)g.W[l] * g.H[l];
+    HookScope hs(MPV_STAGE_DOWNSAMPLE, l, stream);
     hipLaunchKernelGGL(k_downsample, pix_grid(g.W[l], g.H[l]), dim3(256), 0, stream, li[l + 1],
                        lp[l + 1], dl, g.W[l], g.H[l]);
     hipLaunchKernelGGL(k_downsample, pix_grid(g.W[l], g.H[l]), dim3(256), 0, stream, ri[l + 1],
@@ -479,6 +570,7 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     if (l > 0) {
       const int16_t* prev = out->level_raw[l - 1] ? out->level_raw[l - 1]
                                                   : (const int16_t*)(ws + w.raw_off[l - 1]);
+      HookScope hs(MPV_STAGE_PROPAGATE, l, stream);
       hipLaunchKernelGGL(k_propagate, pix_grid(g.W[l], g.H[l]), dim3(256), 0, stream, prev,
                          g.W[l - 1], g.H[l - 1], g.W[l], g.H[l], g.D[l], p->band_radius, g.cap[l],
                          lo);
@@ -488,7 +580,7 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     if (last && out->disp_raw && !out->level_raw[l]) raw = out->disp_raw;
     st = run_level(&lpar, li[l], lp[l], ri[l], rp[l], g.W[l], g.H[l], l > 0 ? &b : nullptr,
                    last ? out->disp : nullptr, last ? out->disp_right : nullptr, raw,
-                   ws + w.level_off, stream);
+                   ws + w.level_off, l, stream);
     if (st) return st;
     if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
       if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),
@@ -496,6 +588,16 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
         return MPV_ERR_DEVICE;
   }
   return launched();
+}
+
+mpv_status mpv_set_timing_events(int32_t stage, int32_t level, hipEvent_t before, hipEvent_t after) {
+  if (stage < 0 || stage >= MPV_NUM_STAGES || level < -1 || level >= MPV_MAX_LEVELS)
+    return MPV_ERR_INVALID_ARG;
+  if ((before == nullptr) != (after == nullptr)) return MPV_ERR_INVALID_ARG;
+  g_hook[stage].level = before ? level : -2;
+  g_hook[stage].before = before;
+  g_hook[stage].after = after;
+  return MPV_OK;
 }
 
 }  // extern "C"
