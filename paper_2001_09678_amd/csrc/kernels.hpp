@@ -41,12 +41,20 @@ __constant__ int c_dy[8] = {0, 0, +1, -1, +1, -1, +1, -1};
 // ---------------------------------------------------------------------------------------
 // Census 5x5 and downsampling
 // ---------------------------------------------------------------------------------------
+// Two views per launch: blockIdx.z = 0 uses (img, out), 1 uses (img2, out2).
 __global__ __launch_bounds__(256) void k_census(const uint8_t* __restrict__ img, int W, int H,
                                                 int pitch, uint32_t* __restrict__ out,
-                                                int opitch, int omargin) {
+                                                int opitch, int omargin,
+                                                const uint8_t* __restrict__ img2, int pitch2,
+                                                uint32_t* __restrict__ out2) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= W || y >= H) return;
+  if (blockIdx.z) {
+    img = img2;
+    pitch = pitch2;
+    out = out2;
+  }
   const int c = img[(size_t)y * pitch + x];
   uint32_t v = 0;
   int bit = 0;
@@ -66,10 +74,17 @@ __global__ __launch_bounds__(256) void k_census(const uint8_t* __restrict__ img,
 }
 
 __global__ __launch_bounds__(256) void k_downsample(const uint8_t* __restrict__ in, int pitch,
-                                                    uint8_t* __restrict__ out, int w, int h) {
+                                                    uint8_t* __restrict__ out, int w, int h,
+                                                    const uint8_t* __restrict__ in2, int pitch2,
+                                                    uint8_t* __restrict__ out2) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= w || y >= h) return;
+  if (blockIdx.z) {
+    in = in2;
+    pitch = pitch2;
+    out = out2;
+  }
   const uint8_t* r0 = in + (size_t)(2 * y) * pitch + 2 * x;
   const uint8_t* r1 = r0 + pitch;
   out[(size_t)y * w + x] = (uint8_t)((r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
@@ -143,7 +158,8 @@ struct ScanArgs {
   int capP;               // partial slots per pixel
   void* agg;              // canonical export [H][W][cap]
   int first;              // canonical export: this direction writes instead of adding
-  uint8_t* sink;          // 256 B: stores of steps past a line's end land here
+  // stores of steps past a line's end go to a 256 B sink right after the last direction's
+  // volume, (ndir - ri) * part_stride bytes from direction ri's volume
   int ndir;
   int dir[8];
   int gprefix[9];  // first block of each direction
@@ -244,12 +260,21 @@ constexpr int CHUNK = 16;
 constexpr int PREFETCH = 4;
 
 // 32-bit offsets of step t's pixel along a line (clamped to the line).
+// 32-bit load at a byte offset from a uniform base (lets the compiler use scalar-base
+// addressing with a 32-bit vector offset)
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t* base, uint32_t idx) {
+  return *(const uint32_t*)((const char*)base + (idx << 2));
+}
+
 struct LineAddr {
   int n;
   int x0, dx;  // x
   int p0, dp;  // y*W + x
   int c0, dc;  // census offset y*cpitch + cmargin + x
   __device__ __forceinline__ int tt(int t) const { return min(t, max(n - 1, 0)); }
+  // offsets are non-negative and below 2^32: unsigned 32-bit, added to uniform bases
+  __device__ __forceinline__ uint32_t pix(int t) const { return (uint32_t)(p0 + tt(t) * dp); }
+  __device__ __forceinline__ uint32_t cen(int t) const { return (uint32_t)(c0 + tt(t) * dc); }
 };
 
 __device__ __forceinline__ LineAddr line_addr(const ScanArgs& a, const Line& ln) {
@@ -268,8 +293,8 @@ template <bool BANDED, int SRC>
 __device__ __forceinline__ uint2 load_chunk(const ScanArgs& a, const LineAddr& la, int t0, int k) {
   const int tt = la.tt(t0 + k);
   int b0 = 0, bn = a.D;
-  if constexpr (BANDED) band_at(a.lo, a.len, (size_t)(la.p0 + tt * la.dp), a.D, a.cap, b0, bn);
-  const uint32_t cl = SRC == SRC_CENSUS ? a.cl[la.c0 + tt * la.dc] : 0u;
+  if constexpr (BANDED) band_at(a.lo, a.len, (size_t)la.pix(t0 + k), a.D, a.cap, b0, bn);
+  const uint32_t cl = SRC == SRC_CENSUS ? ld_u32(a.cl, la.cen(t0 + k)) : 0u;
   return make_uint2(cl | ((uint32_t)b0 << 24), (uint32_t)bn);
 }
 
@@ -417,6 +442,84 @@ __device__ __forceinline__ uint32_t band_envelope(uint32_t P, int tau, int lambd
   }
 }
 
+// Complement-encoded packed-pair shifts (zero fill = absent) and envelope, compile-time TAU.
+template <int LPL, int K, int S>
+__device__ __forceinline__ void zshift_pairs_up(const uint32_t (&v)[K], uint32_t (&o)[K]) {
+  if constexpr (S == 1) {
+    const uint32_t prev = (uint32_t)zshift_up<LPL, 1>((int)v[K - 1]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = funnel16(v[k], k ? v[k - 1] : prev);
+  } else {
+    constexpr int q = S / 2, loff = q / K, rem = q % K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k - rem >= 0)
+        o[k] = (uint32_t)zshift_up<LPL, loff>((int)v[k - rem >= 0 ? k - rem : 0]);
+      else
+        o[k] = (uint32_t)zshift_up<LPL, loff + 1>((int)v[k - rem + K]);
+    }
+  }
+}
+
+template <int LPL, int K, int S>
+__device__ __forceinline__ void zshift_pairs_down(const uint32_t (&v)[K], uint32_t (&o)[K]) {
+  if constexpr (S == 1) {
+    const uint32_t next = (uint32_t)zshift_down<LPL, 1>((int)v[0]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = funnel16(k + 1 < K ? v[k + 1] : next, v[k]);
+  } else {
+    constexpr int q = S / 2, loff = q / K, rem = q % K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k + rem < K)
+        o[k] = (uint32_t)zshift_down<LPL, loff>((int)v[k + rem < K ? k + rem : 0]);
+      else
+        o[k] = (uint32_t)zshift_down<LPL, loff + 1>((int)v[k + rem - K]);
+    }
+  }
+}
+
+// max over |k| < TAU of u(d+k) - lambda|k| for packed complement pairs.
+template <int LPL, int K, int TAU>
+__device__ __forceinline__ void pair_envelope_c(const uint32_t (&Pu)[K], uint32_t (&E)[K],
+                                                int lambda) {
+  uint32_t A[K], B[K], X[K], T[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) A[q] = B[q] = Pu[q];
+  static_for<ceil_log2(TAU)>([&](auto ic) {
+    constexpr int S = 1 << decltype(ic)::value;
+    const uint32_t pen = splat16((uint32_t)(S * lambda));
+#pragma unroll
+    for (int q = 0; q < K; ++q) X[q] = pk_sub_i(A[q], pen);
+    zshift_pairs_up<LPL, K, S>(X, T);
+#pragma unroll
+    for (int q = 0; q < K; ++q) A[q] = pk_max_i(A[q], T[q]);
+#pragma unroll
+    for (int q = 0; q < K; ++q) X[q] = pk_sub_i(B[q], pen);
+    zshift_pairs_down<LPL, K, S>(X, T);
+#pragma unroll
+    for (int q = 0; q < K; ++q) B[q] = pk_max_i(B[q], T[q]);
+  });
+#pragma unroll
+  for (int q = 0; q < K; ++q) E[q] = pk_max_i(A[q], B[q]);
+}
+
+// Complement-encoded band envelope for compile-time TAU (u = INF32 - value, absent = 0):
+// max over |k| < TAU of u(i+k) - lambda|k| in the previous pixel's frame extended by
+// TAU-1 lanes on each side. Absent nodes stay <= 0 < every present node.
+template <int LPL, int TAU>
+__device__ __forceinline__ int band_envelope_c(int Pu, int lambda) {
+  int A = zshift_up<LPL, TAU - 1>(Pu);
+  int B = A;
+  static_for<ceil_log2(TAU)>([&](auto ic) {
+    constexpr int S = 1 << decltype(ic)::value;
+    const int pen = S * lambda;
+    A = max(A, zshift_up<LPL, S>(A - pen));
+    B = max(B, zshift_down<LPL, S>(B - pen));
+  });
+  return max(A, B);
+}
+
 template <int OUT>
 __device__ __forceinline__ void export_canonical(void* agg, size_t idx, uint32_t v, int first) {
   if constexpr (OUT == OUT_U16) {
@@ -448,18 +551,19 @@ __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
   for (int k = 0; k < K; ++k) P[k] = 0;
   uint32_t acc = 0;  // canonical offset: sum of the minima subtracted so far
   uint8_t* part = a.part + (long long)ri * a.part_stride;
+  const uint32_t sink = (uint32_t)((a.ndir - ri) * a.part_stride);
 
   uint32_t ring[PREFETCH][2 * K];  // right census of the lane's 2K candidates
   uint32_t bw[PREFETCH];           // broadcast step words
   int bl[PREFETCH];                // broadcast band lengths
   auto fetch = [&](int t, uint32_t (&dst)[2 * K]) {
     if constexpr (SRC == SRC_CENSUS) {
-      const uint32_t* crow = a.cr + (la.c0 + la.tt(t) * la.dc);
+      const uint32_t c = la.cen(t);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int d0 = 2 * (l * K + k);
-        dst[2 * k] = crow[-d0];
-        dst[2 * k + 1] = crow[-d0 - 1];
+        const uint32_t d0 = 2 * (l * K + k);
+        dst[2 * k] = ld_u32(a.cr, c - d0);
+        dst[2 * k + 1] = ld_u32(a.cr, c - d0 - 1);
       }
     }
   };
@@ -479,7 +583,7 @@ __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
       const int t = t0 + k;
       const int tt = la.tt(t);
       const int x = la.x0 + tt * la.dx;
-      const size_t p = (size_t)(la.p0 + tt * la.dp);
+      const uint32_t p = la.pix(t);
       const uint32_t w = bw[slot];
       const int b0 = BANDED ? (int)(w >> 24) : 0;
       const int bn = BANDED ? bl[slot] : a.D;
@@ -504,7 +608,7 @@ __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
           c0 = (x - d0 >= 0) ? (uint32_t)__popc(cl ^ cr[2 * q]) : 24u;
           c1 = (x - d0 - 1 >= 0) ? (uint32_t)__popc(cl ^ cr[2 * q + 1]) : 24u;
         } else {
-          const uint8_t* cp = a.cost + p * a.cap;
+          const uint8_t* cp = a.cost + (size_t)p * a.cap;
           const int j0 = min(max(d0 - b0, 0), a.cap - 1), j1 = min(max(d0 + 1 - b0, 0), a.cap - 1);
           c0 = cp[j0];
           c1 = cp[j1];
@@ -513,26 +617,51 @@ __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
         const bool in1 = d0 + 1 < a.D && (!BANDED || (d0 + 1 >= b0 && d0 + 1 < b0 + bn));
         C[q] = (in0 ? c0 : INF16) | ((in1 ? c1 : INF16) << 16);
       }
-      // ---- transition: min over predecessors of P(d') + lambda*min(|d-d'|, tau)
-      uint32_t E[K], L[K];
-      pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda);
-      const uint32_t mcap = t == 0 ? 0u : splat16(lt);  // the first pixel has no predecessor
+      // ---- transition: min over predecessors of P(d') + lambda*min(|d-d'|, tau),
+      //      then normalise by the minimum over the line's disparities
+      uint32_t L[K];
+      uint32_t m;
+      if constexpr (TAU > 0) {
+        // complement encoding (u = INF16 - value per half, absent <= 0): max instead of min
+        uint32_t E[K];
+        pair_envelope_c<LPL, K, TAU>(P, E, a.lambda);
+        const uint32_t cap = t == 0 ? INF2 : splat16(INF16 - lt);
+        int mu = -32768;
 #pragma unroll
-      for (int q = 0; q < K; ++q) L[q] = pk_add(C[q], pk_min(E[q], mcap));
-      // ---- normalise by the minimum over the line's disparities
-      uint32_t m = min(lo16(L[0]), hi16(L[0]));
+        for (int q = 0; q < K; ++q) {
+          L[q] = pk_sub_i(pk_max_i(E[q], cap), C[q]);
+          mu = max(mu, max(lo16s(L[q]), hi16s(L[q])));
+        }
+        mu = group_max<LPL>(mu);
+        m = INF16 - (uint32_t)mu;
+        const uint32_t off = splat16(m);
 #pragma unroll
-      for (int q = 1; q < K; ++q) m = min(m, min(lo16(L[q]), hi16(L[q])));
-      m = group_min<LPL>(m);
+        for (int q = 0; q < K; ++q) {
+          P[q] = pk_add_i(L[q], off);              // next state, complement encoded
+          L[q] = pk_sub_i(INF2, L[q]);             // energies relative to the previous minimum
+        }
+      } else {
+        uint32_t E[K];
+        pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda);
+        const uint32_t mcap = t == 0 ? 0u : splat16(lt);  // the first pixel has no predecessor
 #pragma unroll
-      for (int q = 0; q < K; ++q) P[q] = pk_sub(L[q], splat16(m));
+        for (int q = 0; q < K; ++q) L[q] = pk_add(C[q], pk_min(E[q], mcap));
+        m = min(lo16(L[0]), hi16(L[0]));
+#pragma unroll
+        for (int q = 1; q < K; ++q) m = min(m, min(lo16(L[q]), hi16(L[q])));
+        m = group_min<LPL>(m);
+#pragma unroll
+        for (int q = 0; q < K; ++q) P[q] = pk_sub(L[q], splat16(m));
+      }
       // ---- outputs
       if constexpr (OUT == OUT_PART) {
-        uint8_t* dst = t < la.n ? part + p * a.capP + 2 * l * K : a.sink + 4 * lane;
+        // past the line's end the store goes to a sink behind the last direction's volume
+        uint8_t* dst = part + (t < la.n ? p * (uint32_t)a.capP + 2 * l * K : sink + 4 * lane);
         uint32_t v = 0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-          const uint32_t c = pk_min(P[q], 0x00FF00FFu);
+          const uint32_t nq = TAU > 0 ? pk_sub(L[q], splat16(m)) : P[q];  // L - min, >= 0
+          const uint32_t c = pk_min(nq, 0x00FF00FFu);
           v |= ((c & 0xFFu) | ((c >> 8) & 0xFF00u)) << (16 * q);
         }
         if constexpr (K == 1) {
@@ -549,7 +678,7 @@ __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
               const int d = 2 * (l * K + q) + h;
               const int j = d - b0;
               if (d < a.D && j >= 0 && j < bn)
-                export_canonical<OUT>(a.agg, p * a.cap + j, (h ? hi16(L[q]) : lo16(L[q])) + acc,
+                export_canonical<OUT>(a.agg, (size_t)p * a.cap + j, (h ? hi16(L[q]) : lo16(L[q])) + acc,
                                       a.first);
             }
           }
@@ -578,10 +707,12 @@ __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
   const LineAddr la = line_addr(a, ln);
   const int e = a.tau - 1;
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
-  uint32_t P = INF32;
+  uint32_t P = INF32;  // normalised energies of the previous pixel (runtime-tau path)
+  int Pu = 0;          // the same in complement encoding (compile-time-tau path)
   int lo_prev = 0;
   uint32_t acc = 0;
   uint8_t* part = a.part + (long long)ri * a.part_stride;
+  const uint32_t sink = (uint32_t)((a.ndir - ri) * a.part_stride);
 
   uint32_t ring[PREFETCH];  // right census of this lane's candidate
   uint32_t bw[PREFETCH];    // broadcast step words (left census | band start << 24)
@@ -589,7 +720,7 @@ __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
   auto fetch = [&](int t, uint32_t w) -> uint32_t {
     if constexpr (SRC == SRC_CENSUS) {
       const int b0 = (int)(w >> 24);
-      return a.cr[la.c0 + la.tt(t) * la.dc - min(b0 + j, a.D)];  // stays within the margin
+      return ld_u32(a.cr, la.cen(t) - (uint32_t)min(b0 + j, a.D));  // stays within the margin
     } else {
       return 0u;
     }
@@ -610,7 +741,7 @@ __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
       const int t = t0 + k;
       const int tt = la.tt(t);
       const int x = la.x0 + tt * la.dx;
-      const size_t p = (size_t)(la.p0 + tt * la.dp);
+      const uint32_t p = la.pix(t);
       const uint32_t w = bw[slot];
       const int b0 = (int)(w >> 24);
       const int bn = VAR ? bl[slot] : a.cap;
@@ -629,21 +760,35 @@ __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
         const uint32_t pc = (uint32_t)__popc((w & 0xFFFFFFu) ^ crv);
         C = ((x - b0 - j >= 0) ? pc : 24u) + ((j < bn) ? 0u : INF32);
       } else {
-        C = (j < bn) ? (uint32_t)a.cost[p * a.cap + min(j, a.cap - 1)] : INF32;
+        C = (j < bn) ? (uint32_t)a.cost[(size_t)p * a.cap + min(j, a.cap - 1)] : INF32;
       }
-      const uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda);  // lane i <-> position i - e
+      uint32_t L, m;
       const int src = j + (b0 - lo_prev) + e;
-      const uint32_t got =
-          (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, (int)E);
-      const uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
-      const uint32_t L = C + (t == 0 ? 0u : min(Ev, lt));
-      const uint32_t m = group_min<LPL>(L);
-      P = (j < bn) ? L - m : INF32;
-      if constexpr (OUT == OUT_PART) {
-        uint8_t* dst = t < la.n ? part + p * a.capP + j : a.sink + lane;
-        *dst = (uint8_t)min(P, 255u);
+      if constexpr (TAU > 0) {
+        // complement encoding: Pu = INF32 - P (absent 0), larger is better
+        const int E = band_envelope_c<LPL, TAU>(Pu, a.lambda);  // lane i <-> position i - e
+        const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
+        const int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
+        const int Mu = t == 0 ? (int)INF32 : max(Ev, (int)(INF32 - lt));
+        const int Lu = (j < bn) ? Mu - (int)C : 0;
+        const int mu = group_max<LPL>(Lu);
+        L = (j < bn) ? INF32 - (uint32_t)Lu : INF32;
+        m = INF32 - (uint32_t)mu;
+        Pu = (j < bn) ? Lu + ((int)INF32 - mu) : 0;
+        P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;
       } else {
-        if (t < la.n && j < bn) export_canonical<OUT>(a.agg, p * a.cap + j, L + acc, a.first);
+        const uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda);  // lane i <-> position i - e
+        const uint32_t got =
+            (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, (int)E);
+        const uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
+        L = C + (t == 0 ? 0u : min(Ev, lt));
+        m = group_min<LPL>(L);
+        P = (j < bn) ? L - m : INF32;
+      }
+      if constexpr (OUT == OUT_PART) {
+        part[t < la.n ? p * (uint32_t)a.capP + j : sink + lane] = (uint8_t)min(P, 255u);
+      } else {
+        if (t < la.n && j < bn) export_canonical<OUT>(a.agg, (size_t)p * a.cap + j, L + acc, a.first);
       }
       acc += m;
       lo_prev = b0;

@@ -31,6 +31,19 @@ __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
 __device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) {
   return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
 }
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_max_i(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2, a),
+                                                                __builtin_bit_cast(i16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_sub_i(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, a) - __builtin_bit_cast(i16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_add_i(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, a) + __builtin_bit_cast(i16x2, b));
+}
+__device__ __forceinline__ int lo16s(uint32_t v) { return (int)(short)(v & 0xFFFFu); }
+__device__ __forceinline__ int hi16s(uint32_t v) { return (int)v >> 16; }
 __device__ __forceinline__ uint32_t splat16(uint32_t v) { return v | (v << 16); }
 __device__ __forceinline__ uint32_t lo16(uint32_t v) { return v & 0xFFFFu; }
 __device__ __forceinline__ uint32_t hi16(uint32_t v) { return v >> 16; }
@@ -176,6 +189,70 @@ __device__ __forceinline__ uint32_t group_min(uint32_t v) {
   if constexpr (LPL >= 64) {
     auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
     v = min((uint32_t)s[0], (uint32_t)s[1]);
+  }
+  return v;
+}
+
+// ---- complement-encoded energies: u = INF - value, absent node = 0, best = largest.
+// DPP shifts fill with 0 (hardware bound_ctrl), i.e. with "absent".
+template <int CTRL>
+__device__ __forceinline__ int dpp0(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+
+// Value of lane l-N (up) / l+N (down) of the same group, 0 outside the group.
+template <int LPL, int N>
+__device__ __forceinline__ int zshift_up(int v) {
+  if constexpr (N == 0) {
+    return v;
+  } else if constexpr (LPL == 16) {
+    return dpp0<0x110 + N>(v);  // row_shr:N
+  } else if constexpr (N == 1 && LPL == 64) {
+    return dpp0<WAVE_SHR1>(v);
+  } else if constexpr (N == 1) {
+    const int t = dpp0<WAVE_SHR1>(v);
+    return (lane_id() & 31) ? t : 0;
+  } else {
+    const int lane = lane_id();
+    const int src = lane % LPL - N;
+    const int got = __builtin_amdgcn_ds_bpermute((lane - N) << 2, v);
+    return src >= 0 ? got : 0;
+  }
+}
+
+template <int LPL, int N>
+__device__ __forceinline__ int zshift_down(int v) {
+  if constexpr (N == 0) {
+    return v;
+  } else if constexpr (LPL == 16) {
+    return dpp0<0x100 + N>(v);  // row_shl:N
+  } else if constexpr (N == 1 && LPL == 64) {
+    return dpp0<WAVE_SHL1>(v);
+  } else if constexpr (N == 1) {
+    const int t = dpp0<WAVE_SHL1>(v);
+    return ((lane_id() & 31) != 31) ? t : 0;
+  } else {
+    const int lane = lane_id();
+    const int src = lane % LPL + N;
+    const int got = __builtin_amdgcn_ds_bpermute((lane + N) << 2, v);
+    return src < LPL ? got : 0;
+  }
+}
+
+// Maximum over the LPL lanes of a group (signed), in every lane of the group.
+template <int LPL>
+__device__ __forceinline__ int group_max(int v) {
+  v = max(v, dpp0<ROW_ROR8>(v));
+  v = max(v, dpp0<ROW_ROR4>(v));
+  v = max(v, dpp0<ROW_ROR2>(v));
+  v = max(v, dpp0<ROW_ROR1>(v));
+  if constexpr (LPL >= 32) {
+    auto s = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = max((int)s[0], (int)s[1]);
+  }
+  if constexpr (LPL >= 64) {
+    auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    v = max((int)s[0], (int)s[1]);
   }
   return v;
 }

@@ -229,7 +229,7 @@ dim3 pix_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
 
 // ---- one fused level -------------------------------------------------------------------
 struct LevelWs {
-  size_t sink_off, census_off, part_off, total;
+  size_t census_off, part_off, total;
   int cpitch, cmargin;
   ScanChoice sc;
 };
@@ -240,11 +240,11 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band) {
   const int dpad = full_layout(p->num_disp).dpad();
   w.cmargin = (int)align_up((size_t)std::max(dpad, p->num_disp) + 1, 16);
   w.cpitch = w.cmargin + W;
-  w.sink_off = 0;
-  w.census_off = ALIGN;
+  w.census_off = 0;
   const size_t cen = align_up((size_t)H * w.cpitch * sizeof(uint32_t));
   w.part_off = w.census_off + 2 * cen;
-  w.total = w.part_off + align_up((size_t)p->num_paths * H * W * w.sc.capP);
+  // partial volumes, then a 256 B sink for stores past a line's end
+  w.total = w.part_off + align_up((size_t)p->num_paths * H * W * w.sc.capP) + ALIGN;
   return w;
 }
 
@@ -258,10 +258,10 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
   uint8_t* part = ws + lw.part_off;
   {
     HookScope hs(MPV_STAGE_CENSUS, level, s);
-    hipLaunchKernelGGL(k_census, pix_grid(W, H), dim3(256), 0, s, L, W, H, lpitch, cl, lw.cpitch,
-                       lw.cmargin);
-    hipLaunchKernelGGL(k_census, pix_grid(W, H), dim3(256), 0, s, R, W, H, rpitch, cr, lw.cpitch,
-                       lw.cmargin);
+    dim3 g = pix_grid(W, H);
+    g.z = 2;
+    hipLaunchKernelGGL(k_census, g, dim3(256), 0, s, L, W, H, lpitch, cl, lw.cpitch, lw.cmargin,
+                       R, rpitch, cr);
   }
   ScanArgs a{};
   a.W = W;
@@ -277,12 +277,13 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
   a.lo = band ? band->lo : nullptr;
   a.len = (band && band->lo) ? band->len : nullptr;
   a.part = part;
-  a.sink = ws + lw.sink_off;
+
   a.capP = lw.sc.capP;
   a.part_stride = (long long)H * W * lw.sc.capP;
   int dirs[8];
   for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
   const int blocks = plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
+
   {
     HookScope hs(MPV_STAGE_SCAN, level, s);
     if (lw.sc.banded_kernel)
@@ -390,7 +391,8 @@ const char* mpv_status_string(mpv_status s) {
 mpv_status mpv_census(const mpv_image* img, uint32_t* census, hipStream_t stream) {
   if (!valid_image(img) || !census) return MPV_ERR_INVALID_ARG;
   hipLaunchKernelGGL(k_census, pix_grid(img->width, img->height), dim3(256), 0, stream, img->data,
-                     img->width, img->height, img->pitch, census, img->width, 0);
+                     img->width, img->height, img->pitch, census, img->width, 0, img->data,
+                     img->pitch, census);
   return launched();
 }
 
@@ -399,7 +401,7 @@ mpv_status mpv_downsample(const mpv_image* img, uint8_t* out, hipStream_t stream
   const int w = img->width / 2, h = img->height / 2;
   if (w < 1 || h < 1) return MPV_ERR_INVALID_ARG;
   hipLaunchKernelGGL(k_downsample, pix_grid(w, h), dim3(256), 0, stream, img->data, img->pitch,
-                     out, w, h);
+                     out, w, h, img->data, img->pitch, out);
   return launched();
 }
 
@@ -553,10 +555,10 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     uint8_t* dl = ws + w.img_off[l];
     uint8_t* dr = dl + (size_t)g.W[l] * g.H[l];
     HookScope hs(MPV_STAGE_DOWNSAMPLE, l, stream);
-    hipLaunchKernelGGL(k_downsample, pix_grid(g.W[l], g.H[l]), dim3(256), 0, stream, li[l + 1],
-                       lp[l + 1], dl, g.W[l], g.H[l]);
-    hipLaunchKernelGGL(k_downsample, pix_grid(g.W[l], g.H[l]), dim3(256), 0, stream, ri[l + 1],
-                       rp[l + 1], dr, g.W[l], g.H[l]);
+    dim3 gd = pix_grid(g.W[l], g.H[l]);
+    gd.z = 2;
+    hipLaunchKernelGGL(k_downsample, gd, dim3(256), 0, stream, li[l + 1], lp[l + 1], dl, g.W[l],
+                       g.H[l], ri[l + 1], rp[l + 1], dr);
     li[l] = dl;
     ri[l] = dr;
     lp[l] = rp[l] = g.W[l];
