@@ -137,11 +137,22 @@ mpv_status mpv_disparity(const mpv_params *p, const void *agg, int32_t width, in
                          const mpv_band *band, int16_t *disp, int16_t *disp_right,
                          int16_t *disp_raw, hipStream_t stream);
 
+/* Launch schedule of the fused path. Every schedule gives bit-identical results; they
+ * differ only in speed (an autotuner picks one per workload). Zero = library default. */
+typedef struct {
+    int32_t waves_per_block; /* scan blocks hold 1, 2 or 4 independent waves */
+    int32_t full_lanes;      /* full-range scans: lanes per line (16, 32, 64) if the range fits
+                                2 packed pairs per lane, else the default layout */
+    int32_t band_lanes;      /* banded scans: lanes per line (16, 32, 64) if the band fits */
+    int32_t order;           /* batched scans: 0 = pair by pair, 1 = longest lines first */
+} mpv_schedule;
+
 /* Multi-scale fused path (Section 3.4). */
 typedef struct {
     mpv_params base;     /* num_disp = D of the finest (input) level */
     int32_t levels;      /* 1 .. MPV_MAX_LEVELS; 1 = plain single-scale MPV */
     int32_t band_radius; /* R: levels below the top search [c-R, c+R] around c = 2 x parent */
+    mpv_schedule sched;  /* launch schedule (zeros = defaults) */
 } mpv_pyramid_params;
 
 typedef struct {
@@ -174,6 +185,36 @@ size_t mpv_match_workspace_bytes(const mpv_params *p, int32_t width, int32_t hei
 mpv_status mpv_match(const mpv_params *p, const mpv_image *left, const mpv_image *right,
                      const mpv_band *band, int16_t *disp, int16_t *disp_right, int16_t *disp_raw,
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Batched multi-scale matching of many pairs of different sizes and ranges (the analogue
+ * of the paper's frame pipelining, Section 3.7): every stage of every level runs as one
+ * launch over all pairs (a device descriptor table maps blocks to pairs), pairs share
+ * lambda/tau/P/levels/R and the schedule of the mpv_pyramid_params, and each pair has its
+ * own D (its num_disp) and its own workspace region, so each output equals mpv_pyramid of
+ * that pair alone. Usage: create (host only) -> workspace_bytes -> bind (uploads the
+ * descriptor tables into the workspace and synchronises `stream`) -> run / run_graph any
+ * number of times. The items' images and outputs must stay allocated while the batch
+ * lives; their contents may change between runs. The handle is host memory owned by the
+ * library until mpv_batch_destroy. */
+typedef struct mpv_batch_s *mpv_batch;
+typedef struct {
+    mpv_image left, right; /* device images of one pair */
+    int32_t num_disp;      /* D of this pair, 1 .. MPV_MAX_DISP */
+    int16_t *disp;         /* required: [H][W] LR-checked disparity */
+    int16_t *disp_right;   /* optional: right disparity */
+    int16_t *disp_raw;     /* optional: raw WTA */
+} mpv_batch_item;
+
+mpv_status mpv_batch_create(const mpv_pyramid_params *p, const mpv_batch_item *items, int32_t n,
+                            mpv_batch *out);
+size_t mpv_batch_workspace_bytes(mpv_batch b);
+mpv_status mpv_batch_bind(mpv_batch b, void *workspace, size_t workspace_bytes, hipStream_t stream);
+/* Enqueue the whole batch (about 4 launches per level) on `stream`. */
+mpv_status mpv_batch_run(mpv_batch b, hipStream_t stream);
+/* Same work as one hipGraph: captured on a private stream at the first call, then replayed
+ * on `stream` with one hipGraphLaunch per call. */
+mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t stream);
+void mpv_batch_destroy(mpv_batch b);
 
 /* Measurement hook (per-kernel timing without a profiler). Stages of one level: */
 #define MPV_STAGE_DOWNSAMPLE 0

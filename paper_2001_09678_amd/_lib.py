@@ -30,8 +30,19 @@ class Params(C.Structure):
                 ("agg_type", C.c_int32)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("full_lanes", C.c_int32), ("band_lanes", C.c_int32),
+                ("order", C.c_int32)]
+
+
 class PyramidParams(C.Structure):
-    _fields_ = [("base", Params), ("levels", C.c_int32), ("band_radius", C.c_int32)]
+    _fields_ = [("base", Params), ("levels", C.c_int32), ("band_radius", C.c_int32),
+                ("sched", Schedule)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("left", Image), ("right", Image), ("num_disp", C.c_int32), ("disp", C.c_void_p),
+                ("disp_right", C.c_void_p), ("disp_raw", C.c_void_p)]
 
 
 class PyramidOut(C.Structure):
@@ -71,6 +82,12 @@ def lib():
             "mpv_match": ([C.POINTER(Params), C.POINTER(Image), C.POINTER(Image), C.POINTER(Band),
                            P, P, P, P, S, P], i32),
             "mpv_set_timing_events": ([i32, i32, P, P], i32),
+            "mpv_batch_create": ([C.POINTER(PyramidParams), C.POINTER(BatchItem), i32, C.POINTER(P)], i32),
+            "mpv_batch_workspace_bytes": ([P], S),
+            "mpv_batch_bind": ([P, P, S, P], i32),
+            "mpv_batch_run": ([P, P], i32),
+            "mpv_batch_run_graph": ([P, P], i32),
+            "mpv_batch_destroy": ([P], None),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)

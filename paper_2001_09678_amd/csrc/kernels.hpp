@@ -20,10 +20,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <utility>
 #include <type_traits>
 
 #include "lane.hpp"
+#include "types.hpp"
 
 namespace mpvk {
 
@@ -35,13 +37,14 @@ __device__ __forceinline__ void band_at(const int16_t* lo, const uint8_t* len, s
   bn = min(max(bn, 1), min(cap, D - b0));
 }
 
-__constant__ int c_dx[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
-__constant__ int c_dy[8] = {0, 0, +1, -1, +1, -1, +1, -1};
+static __constant__ int c_dx[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
+static __constant__ int c_dy[8] = {0, 0, +1, -1, +1, -1, +1, -1};
 
 // ---------------------------------------------------------------------------------------
 // Census 5x5 and downsampling
 // ---------------------------------------------------------------------------------------
 // Two views per launch: blockIdx.z = 0 uses (img, out), 1 uses (img2, out2).
+#ifdef MPV_MISC_KERNELS
 __global__ __launch_bounds__(256) void k_census(const uint8_t* __restrict__ img, int W, int H,
                                                 int pitch, uint32_t* __restrict__ out,
                                                 int opitch, int omargin,
@@ -72,7 +75,10 @@ __global__ __launch_bounds__(256) void k_census(const uint8_t* __restrict__ img,
   }
   out[(size_t)y * opitch + omargin + x] = v;
 }
+#endif
 
+
+#ifdef MPV_MISC_KERNELS
 __global__ __launch_bounds__(256) void k_downsample(const uint8_t* __restrict__ in, int pitch,
                                                     uint8_t* __restrict__ out, int w, int h,
                                                     const uint8_t* __restrict__ in2, int pitch2,
@@ -89,6 +95,8 @@ __global__ __launch_bounds__(256) void k_downsample(const uint8_t* __restrict__ 
   const uint8_t* r1 = r0 + pitch;
   out[(size_t)y * w + x] = (uint8_t)((r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
 }
+#endif
+
 
 // ---------------------------------------------------------------------------------------
 // Cost volume export: one block per row; both census rows are built in LDS first.
@@ -110,6 +118,7 @@ __device__ __forceinline__ uint32_t census_at(const uint8_t* img, int W, int H, 
   return v;
 }
 
+#ifdef MPV_MISC_KERNELS
 __global__ __launch_bounds__(256) void k_cost(const uint8_t* __restrict__ L, int lpitch,
                                               const uint8_t* __restrict__ R, int rpitch, int W,
                                               int H, const int16_t* __restrict__ lo,
@@ -137,33 +146,35 @@ __global__ __launch_bounds__(256) void k_cost(const uint8_t* __restrict__ L, int
     row[i] = c;
   }
 }
+#endif
+
 
 // ---------------------------------------------------------------------------------------
 // Scan kernels
 // ---------------------------------------------------------------------------------------
-enum { SRC_CENSUS = 0, SRC_COST = 1 };
-enum { OUT_PART = 0, OUT_U16 = 1, OUT_I32 = 2 };
 
-struct ScanArgs {
-  int W, H, D, cap;  // cap: slots per pixel of the cost volume / aggregate export
-  int lambda, tau;   // tau = min(tau, D-1) clamped to >= 1 (same energies, see host)
-  const uint32_t* cl;
-  const uint32_t* cr;
-  int cpitch, cmargin;
-  const uint8_t* cost;
-  const int16_t* lo;
-  const uint8_t* len;
-  uint8_t* part;
-  long long part_stride;  // bytes between direction volumes
-  int capP;               // partial slots per pixel
-  void* agg;              // canonical export [H][W][cap]
-  int first;              // canonical export: this direction writes instead of adding
-  // stores of steps past a line's end go to a 256 B sink right after the last direction's
-  // volume, (ndir - ri) * part_stride bytes from direction ri's volume
-  int ndir;
-  int dir[8];
-  int gprefix[9];  // first block of each direction
-};
+
+
+
+
+
+// Descriptor index of global unit u (binary search; all lanes agree).
+__device__ __forceinline__ int batch_find(const int* first, int nseg, int u) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Wave index of this wave in a launch whose blocks hold blockDim.x / 64 waves.
+__device__ __forceinline__ int wave_unit() {
+  return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+}
 
 __device__ __forceinline__ int num_lines(int r, int W, int H) {
   return c_dy[r] == 0 ? H : (c_dx[r] == 0 ? W : W + H - 1);
@@ -208,10 +219,10 @@ __device__ __forceinline__ size_t line_pixel(const Line& ln, int t, int W, int& 
   return (size_t)y * W + x;
 }
 
-// Block -> (direction, this group's line). One wave per block; nmax = longest line of the wave.
+// Wave unit b of a descriptor -> (direction, this group's line); nmax = longest line of the wave.
 template <int LPL>
-__device__ __forceinline__ void block_line(const ScanArgs& a, int& r, int& ri, Line& ln, int& nmax) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void block_line(const ScanArgs& a, int b, int& r, int& ri, Line& ln,
+                                           int& nmax) {
   ri = 0;
   while (ri + 1 < a.ndir && b >= a.gprefix[ri + 1]) ++ri;
   r = a.dir[ri];
@@ -537,21 +548,21 @@ __device__ __forceinline__ void export_canonical(void* agg, size_t idx, uint32_t
 // outside the pixel's band is an absent node; partials are then indexed by absolute
 // disparity.
 template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
-__global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
+__device__ __forceinline__ void scan_full_wave(const ScanArgs& a, int unit) {
   const int lane = lane_id();
   const int l = lane % LPL;
   const int kk = l % CHUNK;
   int r, ri, nmax;
   Line ln;
-  block_line<LPL>(a, r, ri, ln, nmax);
+  block_line<LPL>(a, unit, r, ri, ln, nmax);
   const LineAddr la = line_addr(a, ln);
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
   uint32_t P[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) P[k] = 0;
   uint32_t acc = 0;  // canonical offset: sum of the minima subtracted so far
-  uint8_t* part = a.part + (long long)ri * a.part_stride;
-  const uint32_t sink = (uint32_t)((a.ndir - ri) * a.part_stride);
+  uint8_t* part = a.part + (long long)(a.dir_base + ri) * a.part_stride;
+  const uint32_t sink = (uint32_t)((a.npd - a.dir_base - ri) * a.part_stride);
 
   uint32_t ring[PREFETCH][2 * K];  // right census of the lane's 2K candidates
   uint32_t bw[PREFETCH];           // broadcast step words
@@ -696,14 +707,14 @@ __global__ __launch_bounds__(64) void k_scan_full(ScanArgs a) {
 // slots on each side, then lane j of the new pixel picks position j + lo(p) - lo(p-r).
 // VAR: per-pixel band lengths (otherwise every pixel has len = cap).
 template <int LPL, int SRC, int OUT, int TAU, bool VAR>
-__global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
+__device__ __forceinline__ void scan_band_wave(const ScanArgs& a, int unit) {
   const int lane = lane_id();
   const int j = lane % LPL;
   const int kk = j % CHUNK;
   const int gbase = lane - j;
   int r, ri, nmax;
   Line ln;
-  block_line<LPL>(a, r, ri, ln, nmax);
+  block_line<LPL>(a, unit, r, ri, ln, nmax);
   const LineAddr la = line_addr(a, ln);
   const int e = a.tau - 1;
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
@@ -711,8 +722,8 @@ __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
   int Pu = 0;          // the same in complement encoding (compile-time-tau path)
   int lo_prev = 0;
   uint32_t acc = 0;
-  uint8_t* part = a.part + (long long)ri * a.part_stride;
-  const uint32_t sink = (uint32_t)((a.ndir - ri) * a.part_stride);
+  uint8_t* part = a.part + (long long)(a.dir_base + ri) * a.part_stride;
+  const uint32_t sink = (uint32_t)((a.npd - a.dir_base - ri) * a.part_stride);
 
   uint32_t ring[PREFETCH];  // right census of this lane's candidate
   uint32_t bw[PREFETCH];    // broadcast step words (left census | band start << 24)
@@ -797,29 +808,44 @@ __global__ __launch_bounds__(64) void k_scan_band(ScanArgs a) {
   }
 }
 
+// Scan kernels: one descriptor (kernel argument) or a batch of descriptors (device table).
+// Blocks hold blockDim.x / 64 independent waves; waves past the work exit at once.
+template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
+__global__ __launch_bounds__(256) void k_scan_full(ScanArgs a) {
+  const int u = wave_unit();
+  if (u < a.gprefix[a.ndir]) scan_full_wave<LPL, K, SRC, OUT, TAU, BANDED>(a, u);
+}
+
+template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
+__global__ __launch_bounds__(256) void k_scan_full_batch(Batch<ScanArgs> b) {
+  const int u = wave_unit();
+  if (u >= b.first[b.nseg]) return;
+  const int s = batch_find(b.first, b.nseg, u);
+  scan_full_wave<LPL, K, SRC, OUT, TAU, BANDED>(b.desc[s], u - b.first[s]);
+}
+
+template <int LPL, int SRC, int OUT, int TAU, bool VAR>
+__global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
+  const int u = wave_unit();
+  if (u < a.gprefix[a.ndir]) scan_band_wave<LPL, SRC, OUT, TAU, VAR>(a, u);
+}
+
+template <int LPL, int SRC, int OUT, int TAU, bool VAR>
+__global__ __launch_bounds__(256) void k_scan_band_batch(Batch<ScanArgs> b) {
+  const int u = wave_unit();
+  if (u >= b.first[b.nseg]) return;
+  const int s = batch_find(b.first, b.nseg, u);
+  scan_band_wave<LPL, SRC, OUT, TAU, VAR>(b.desc[s], u - b.first[s]);
+}
+
 // ---------------------------------------------------------------------------------------
 // Sum of paths + winner-take-all + right disparity + LR check. One block per image row.
 // ---------------------------------------------------------------------------------------
-enum { IN_PART = 0, IN_U16 = 1, IN_I32 = 2 };
 
-struct RedArgs {
-  int W, H, D;
-  int stride;  // slots per pixel of the input volume(s)
-  int bcap;    // band length where len == null (cap of the band, or D at full range)
-  const int16_t* lo;
-  const uint8_t* len;
-  int absolute;  // slot index = absolute disparity (partials of a banded full-range scan)
-  const uint8_t* part;
-  long long part_stride;
-  int npart;
-  const void* agg;
-  int lr;
-  int16_t* disp;
-  int16_t* right;
-  int16_t* raw;
-};
 
-constexpr int RED_MAXW = 4096;
+
+
+
 
 // Sum of the P normalised partials of SPL consecutive slots starting at q (SPL in {1,2,4}).
 // Every partial is <= 255 and P <= 8, so the 16-bit lanes of a packed sum never carry.
@@ -955,11 +981,10 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
 // pixels per wave step. Sums fit 16 bits (P * 255), so two slots share a register.
 // need_lr = false (intermediate pyramid levels) writes the raw winner only.
 template <int LPP>
-__global__ __launch_bounds__(256) void k_reduce_part(RedArgs a, int need_lr) {
+__device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int need_lr) {
   __shared__ uint32_t s_rkey[RED_MAXW];
   __shared__ int16_t s_dl[RED_MAXW];
   constexpr uint32_t NOK = 0xFFFFFFFFu;
-  const int y = blockIdx.x;
   const int tid = threadIdx.x;
   if (need_lr) {
     for (int x = tid; x < a.W; x += 256) s_rkey[x] = NOK;
@@ -1043,9 +1068,23 @@ __global__ __launch_bounds__(256) void k_reduce_part(RedArgs a, int need_lr) {
   }
 }
 
+template <int LPP>
+__global__ __launch_bounds__(256) void k_reduce_part(RedArgs a, int need_lr) {
+  reduce_part_row<LPP>(a, blockIdx.x, need_lr);
+}
+
+// Batched: one block per image row of every pair; need_lr is per descriptor (a.lr_need).
+template <int LPP>
+__global__ __launch_bounds__(256) void k_reduce_part_batch(Batch<RedArgs> b) {
+  const int u = blockIdx.x;
+  const int s = batch_find(b.first, b.nseg, u);
+  reduce_part_row<LPP>(b.desc[s], u - b.first[s], b.desc[s].need_lr);
+}
+
 // ---------------------------------------------------------------------------------------
 // Coarse-to-fine band (Section 3.4): lo = clamp(2 * parent raw WTA - R, 0, Dl - cap)
 // ---------------------------------------------------------------------------------------
+#ifdef MPV_MISC_KERNELS
 __global__ __launch_bounds__(256) void k_propagate(const int16_t* __restrict__ coarse, int Wc,
                                                    int Hc, int W, int H, int Dl, int R, int cap,
                                                    int16_t* __restrict__ lo) {
@@ -1056,6 +1095,61 @@ __global__ __launch_bounds__(256) void k_propagate(const int16_t* __restrict__ c
   const int c = 2 * (int)coarse[(size_t)cy * Wc + cx];
   lo[(size_t)y * W + x] = (int16_t)min(max(c - R, 0), Dl - cap);
 }
+#endif
+
+
+// ---------------------------------------------------------------------------------------
+// Batched per-pixel stages: a descriptor per pair, 64x4-pixel tiles, both views per pair.
+// ---------------------------------------------------------------------------------------
+
+
+__device__ __forceinline__ bool batch_pixel(const Batch<PixArgs>& b, const PixArgs*& a, int& view,
+                                            int& x, int& y) {
+  const int u = blockIdx.x;
+  const int s = batch_find(b.first, b.nseg, u);
+  a = &b.desc[s];
+  int t = u - b.first[s];
+  view = t >= a->tiles;
+  t -= view * a->tiles;
+  x = (t % a->tiles_x) * 64 + (threadIdx.x & 63);
+  y = (t / a->tiles_x) * 4 + (threadIdx.x >> 6);
+  return x < a->W && y < a->H;
+}
+
+#ifdef MPV_MISC_KERNELS
+__global__ __launch_bounds__(256) void k_census_batch(Batch<PixArgs> b) {
+  const PixArgs* a;
+  int v, x, y;
+  if (!batch_pixel(b, a, v, x, y)) return;
+  ((uint32_t*)a->out[v])[(size_t)y * a->opitch + a->omargin + x] =
+      census_at(a->in[v], a->W, a->H, a->in_pitch[v], x, y);
+}
+#endif
+
+
+#ifdef MPV_MISC_KERNELS
+__global__ __launch_bounds__(256) void k_downsample_batch(Batch<PixArgs> b) {
+  const PixArgs* a;
+  int v, x, y;
+  if (!batch_pixel(b, a, v, x, y)) return;
+  const uint8_t* r0 = a->in[v] + (size_t)(2 * y) * a->in_pitch[v] + 2 * x;
+  const uint8_t* r1 = r0 + a->in_pitch[v];
+  ((uint8_t*)a->out[v])[(size_t)y * a->W + x] = (uint8_t)((r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
+}
+#endif
+
+
+#ifdef MPV_MISC_KERNELS
+__global__ __launch_bounds__(256) void k_propagate_batch(Batch<PixArgs> b) {
+  const PixArgs* a;
+  int v, x, y;
+  if (!batch_pixel(b, a, v, x, y)) return;
+  const int cx = min(x >> 1, a->Wc - 1), cy = min(y >> 1, a->Hc - 1);
+  const int c = 2 * (int)a->coarse[(size_t)cy * a->Wc + cx];
+  a->lo[(size_t)y * a->W + x] = (int16_t)min(max(c - a->R, 0), a->Dl - a->cap);
+}
+#endif
+
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T* __restrict__ p, size_t n, T v) {

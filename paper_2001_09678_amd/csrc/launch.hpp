@@ -1,0 +1,52 @@
+// Host-callable launchers. Every kernel template is instantiated in exactly one
+// translation unit (kern_*.hip); the API code (mpv.hip) only calls these functions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "types.hpp"
+
+namespace mpvl {
+using mpvk::Batch;
+using mpvk::PixArgs;
+using mpvk::RedArgs;
+using mpvk::ScanArgs;
+
+// Full-range scan layouts (lanes per line, packed pairs per lane) with kernels.
+bool full_layout_ok(int LPL, int K);
+
+// Scans. `a.tau` is the reduced tau; fused partial-output scans (SRC_CENSUS, OUT_PART)
+// have compile-time versions for tau 1, 2 and 4, everything else uses runtime tau.
+// wpb = waves per block (1, 2 or 4).
+void scan_full(const ScanArgs& a, int LPL, int K, int src, int out, bool banded, int wpb,
+               hipStream_t s);
+void scan_full_batch(const Batch<ScanArgs>& b, int units, int LPL, int K, int tau, bool banded,
+                     int wpb, hipStream_t s);
+void scan_band(const ScanArgs& a, int LPL, int src, int out, bool var, int wpb, hipStream_t s);
+void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, bool var, int wpb,
+                     hipStream_t s);
+
+// Sum + WTA (+ right disparity + LR when need_lr) over P uint8 partial volumes.
+void reduce_part(const RedArgs& a, int need_lr, hipStream_t s);
+void reduce_part_batch(const Batch<RedArgs>& b, int rows, int stride, hipStream_t s);
+// WTA + right disparity + LR over an exported uint16 / int32 aggregate volume.
+void reduce_agg(const RedArgs& a, int in, hipStream_t s);
+
+// Census of one or two views (R == nullptr: one view).
+void census(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int H,
+            uint32_t* cl, uint32_t* cr, int opitch, int omargin, hipStream_t s);
+// 2x2 downsample of one or two views to w x h (in2 == nullptr: one view).
+void downsample(const uint8_t* in, int pitch, uint8_t* out, const uint8_t* in2, int pitch2,
+                uint8_t* out2, int w, int h, hipStream_t s);
+void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int H,
+          const int16_t* lo, const uint8_t* len, int cap, int D, uint8_t* cost, hipStream_t s);
+void propagate(const int16_t* coarse, int Wc, int Hc, int W, int H, int Dl, int R, int cap,
+               int16_t* lo, hipStream_t s);
+void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s);
+void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
+
+// Batched per-pixel stages: `blocks` = sum over descriptors of their tiles (x2 for two views).
+void census_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
+void downsample_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
+void propagate_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
+
+}  // namespace mpvl

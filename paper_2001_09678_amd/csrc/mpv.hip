@@ -1,16 +1,19 @@
 // C-ABI entry points of the MPV stereo library (declared in include/mpv.h).
 //
 // Host code only validates, sizes the caller's workspace, picks a kernel variant and
-// enqueues on the caller's stream; it never allocates and never synchronises.
+// enqueues on the caller's stream through the launchers of launch.hpp; it never
+// allocates device memory and synchronises only in mpv_batch_bind.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <new>
+#include <vector>
 
 #include "../../include/mpv.h"
-#include "kernels.hpp"
+#include "launch.hpp"
 
 using namespace mpvk;
 
@@ -40,15 +43,21 @@ mpv_status check_params(const mpv_params* p, bool fused) {
   return MPV_OK;
 }
 
+mpv_status check_sched(const mpv_schedule& s) {
+  const bool wpb = s.waves_per_block == 0 || s.waves_per_block == 1 || s.waves_per_block == 2 ||
+                   s.waves_per_block == 4;
+  const bool fl = s.full_lanes == 0 || s.full_lanes == 16 || s.full_lanes == 32 || s.full_lanes == 64;
+  const bool bl = s.band_lanes == 0 || s.band_lanes == 16 || s.band_lanes == 32 || s.band_lanes == 64;
+  return (wpb && fl && bl && (s.order == 0 || s.order == 1)) ? MPV_OK : MPV_ERR_INVALID_ARG;
+}
+
 mpv_status check_band(const mpv_band* b, int D) {
   if (!b || !b->lo) return MPV_OK;
   if (b->cap < 1 || b->cap > D) return MPV_ERR_INVALID_ARG;
   return MPV_OK;
 }
 
-mpv_status launched() {
-  return hipGetLastError() == hipSuccess ? MPV_OK : MPV_ERR_DEVICE;
-}
+mpv_status launched() { return hipGetLastError() == hipSuccess ? MPV_OK : MPV_ERR_DEVICE; }
 
 // ---- timing hook -------------------------------------------------------------------------
 struct TimingHook {
@@ -77,15 +86,24 @@ struct FullLayout {
   int LPL, K;
   int dpad() const { return 2 * K * LPL; }
 };
-FullLayout full_layout(int D) {
+FullLayout full_layout(int D, int lanes) {
+  if (lanes) {
+    const int K = (D + 2 * lanes - 1) / (2 * lanes);
+    if (mpvl::full_layout_ok(lanes, K)) return {lanes, K};
+  }
   if (D <= 32) return {16, 1};
   if (D <= 64) return {32, 1};
   if (D <= 128) return {64, 1};
   return {64, 2};
 }
-// Smallest lane group that holds a band of `cap` plus tau-1 neighbours on each side; 0 if none.
-int band_lanes(int cap, int te) {
+// Widest padded range any layout may use for D (sizes the census margin).
+int max_dpad(int D) { return std::max(2 * 64 * ((D + 127) / 128), 64); }
+
+// Smallest lane group that holds a band of `cap` plus tau-1 neighbours on each side (or the
+// requested one if it fits); 0 if none.
+int band_lanes(int cap, int te, int want) {
   const int need = cap + 2 * (te - 1);
+  if (want && need <= want) return want;
   if (need <= 16) return 16;
   if (need <= 32) return 32;
   if (need <= 64) return 64;
@@ -97,148 +115,62 @@ struct ScanChoice {
   int LPL, K;
   int capP;  // partial slots per pixel
   bool absolute;
+  bool masked;  // full-range kernel with band masks
 };
-ScanChoice choose_scan(int D, const mpv_band* band, int tau) {
+ScanChoice choose_scan(int D, const mpv_band* band, int tau, const mpv_schedule& sc) {
   const int te = tau_eff(tau, D);
   if (band && band->lo) {
-    const int lpl = band_lanes(band->cap, te);
-    if (lpl) return {true, lpl, 1, lpl, false};
-    FullLayout f = full_layout(D);
-    return {false, f.LPL, f.K, f.dpad(), true};
+    const int lpl = band_lanes(band->cap, te, sc.band_lanes);
+    if (lpl) return {true, lpl, 1, lpl, false, false};
+    FullLayout f = full_layout(D, sc.full_lanes);
+    return {false, f.LPL, f.K, f.dpad(), true, true};
   }
-  FullLayout f = full_layout(D);
-  return {false, f.LPL, f.K, f.dpad(), false};
+  FullLayout f = full_layout(D, sc.full_lanes);
+  return {false, f.LPL, f.K, f.dpad(), false, false};
 }
 
-int num_lines_host(int r, int W, int H) {
-  static const int dx[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
-  static const int dy[8] = {0, 0, +1, -1, +1, -1, +1, -1};
-  return dy[r] == 0 ? H : (dx[r] == 0 ? W : W + H - 1);
+const int kDX[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
+const int kDY[8] = {0, 0, +1, -1, +1, -1, +1, -1};
+int num_lines_host(int r, int W, int H) { return kDY[r] == 0 ? H : (kDX[r] == 0 ? W : W + H - 1); }
+int line_len_host(int r, int W, int H) {
+  return kDY[r] == 0 ? W : (kDX[r] == 0 ? H : std::min(W, H));
 }
 
-// Fill direction list + block prefix; returns the number of blocks.
+// Fill the direction list and wave prefix of a descriptor; returns its number of waves.
 int plan_dirs(ScanArgs& a, const int* dirs, int ndir, int LPL) {
   a.ndir = ndir;
-  int blocks = 0;
+  int waves = 0;
   for (int i = 0; i < ndir; ++i) {
     a.dir[i] = dirs[i];
-    a.gprefix[i] = blocks;
-    const int lines = num_lines_host(dirs[i], a.W, a.H);
-    blocks += (lines + (64 / LPL) - 1) / (64 / LPL);
+    a.gprefix[i] = waves;
+    waves += (num_lines_host(dirs[i], a.W, a.H) + (64 / LPL) - 1) / (64 / LPL);
   }
-  a.gprefix[ndir] = blocks;
+  a.gprefix[ndir] = waves;
   for (int i = ndir; i < 8; ++i) a.dir[i] = 0;
-  return blocks;
+  return waves;
 }
 
-// tau (already reduced to min(tau, D-1)) is a compile-time parameter for 1..4 on the fused
-// path, so the envelope is a fixed sequence of DPP shifts; other values, and the unfused
-// export path, take the runtime-tau kernels.
-template <int SRC, int OUT, int TAU, bool BANDED>
-void launch_full_t(const ScanArgs& a, int LPL, int K, int blocks, hipStream_t s) {
-  if (LPL == 16)
-    hipLaunchKernelGGL((k_scan_full<16, 1, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
-  else if (LPL == 32)
-    hipLaunchKernelGGL((k_scan_full<32, 1, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
-  else if (K == 1)
-    hipLaunchKernelGGL((k_scan_full<64, 1, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
+int wpb_of(const mpv_schedule& s) { return s.waves_per_block ? s.waves_per_block : 1; }
+
+void launch_scan(const ScanArgs& a, const ScanChoice& c, int src, int out, const mpv_schedule& s,
+                 hipStream_t st) {
+  if (c.banded_kernel)
+    mpvl::scan_band(a, c.LPL, src, out, a.len != nullptr, wpb_of(s), st);
   else
-    hipLaunchKernelGGL((k_scan_full<64, 2, SRC, OUT, TAU, BANDED>), dim3(blocks), dim3(64), 0, s, a);
+    mpvl::scan_full(a, c.LPL, c.K, src, out, c.masked, wpb_of(s), st);
 }
 
-template <int SRC, int OUT, bool BANDED>
-void launch_full_b(const ScanArgs& a, int LPL, int K, int blocks, hipStream_t s) {
-  if constexpr (OUT == OUT_PART) {
-    switch (a.tau) {
-      case 1: launch_full_t<SRC, OUT, 1, BANDED>(a, LPL, K, blocks, s); return;
-      case 2: launch_full_t<SRC, OUT, 2, BANDED>(a, LPL, K, blocks, s); return;
-      case 3: launch_full_t<SRC, OUT, 3, BANDED>(a, LPL, K, blocks, s); return;
-      case 4: launch_full_t<SRC, OUT, 4, BANDED>(a, LPL, K, blocks, s); return;
-      default: break;
-    }
-  }
-  launch_full_t<SRC, OUT, 0, BANDED>(a, LPL, K, blocks, s);
-}
-
-template <int SRC, int OUT>
-void launch_full(const ScanArgs& a, int LPL, int K, int blocks, hipStream_t s) {
-  if (a.lo)
-    launch_full_b<SRC, OUT, true>(a, LPL, K, blocks, s);
-  else
-    launch_full_b<SRC, OUT, false>(a, LPL, K, blocks, s);
-}
-
-template <int SRC, int OUT, int TAU, bool VAR>
-void launch_band_v(const ScanArgs& a, int LPL, int blocks, hipStream_t s) {
-  if (LPL == 16)
-    hipLaunchKernelGGL((k_scan_band<16, SRC, OUT, TAU, VAR>), dim3(blocks), dim3(64), 0, s, a);
-  else if (LPL == 32)
-    hipLaunchKernelGGL((k_scan_band<32, SRC, OUT, TAU, VAR>), dim3(blocks), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_scan_band<64, SRC, OUT, TAU, VAR>), dim3(blocks), dim3(64), 0, s, a);
-}
-
-template <int SRC, int OUT, int TAU>
-void launch_band_t(const ScanArgs& a, int LPL, int blocks, hipStream_t s) {
-  if (a.len)
-    launch_band_v<SRC, OUT, TAU, true>(a, LPL, blocks, s);
-  else
-    launch_band_v<SRC, OUT, TAU, false>(a, LPL, blocks, s);
-}
-
-template <int SRC, int OUT>
-void launch_band(const ScanArgs& a, int LPL, int blocks, hipStream_t s) {
-  if constexpr (OUT == OUT_PART) {
-    switch (a.tau) {
-      case 1: launch_band_t<SRC, OUT, 1>(a, LPL, blocks, s); return;
-      case 2: launch_band_t<SRC, OUT, 2>(a, LPL, blocks, s); return;
-      case 3: launch_band_t<SRC, OUT, 3>(a, LPL, blocks, s); return;
-      case 4: launch_band_t<SRC, OUT, 4>(a, LPL, blocks, s); return;
-      default: break;
-    }
-  }
-  launch_band_t<SRC, OUT, 0>(a, LPL, blocks, s);
-}
-
-template <int IN>
-void launch_reduce(const RedArgs& a, hipStream_t s) {
-  const int st = a.stride;
-  if (st <= 16)
-    hipLaunchKernelGGL((k_reduce<16, 1, IN>), dim3(a.H), dim3(256), 0, s, a);
-  else if (st <= 32)
-    hipLaunchKernelGGL((k_reduce<32, 1, IN>), dim3(a.H), dim3(256), 0, s, a);
-  else if (st <= 64)
-    hipLaunchKernelGGL((k_reduce<64, 1, IN>), dim3(a.H), dim3(256), 0, s, a);
-  else if (st <= 128)
-    hipLaunchKernelGGL((k_reduce<64, 2, IN>), dim3(a.H), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_reduce<64, 4, IN>), dim3(a.H), dim3(256), 0, s, a);
-}
-
-void launch_reduce_part(const RedArgs& a, int need_lr, hipStream_t s) {
-  switch (a.stride / 16) {
-    case 1: hipLaunchKernelGGL(k_reduce_part<1>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-    case 2: hipLaunchKernelGGL(k_reduce_part<2>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-    case 4: hipLaunchKernelGGL(k_reduce_part<4>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-    case 8: hipLaunchKernelGGL(k_reduce_part<8>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-    default: hipLaunchKernelGGL(k_reduce_part<16>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-  }
-}
-
-dim3 pix_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
-
-// ---- one fused level -------------------------------------------------------------------
+// ---- one fused level ---------------------------------------------------------------------
 struct LevelWs {
   size_t census_off, part_off, total;
   int cpitch, cmargin;
   ScanChoice sc;
 };
 
-LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band) {
+LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const mpv_schedule& s) {
   LevelWs w{};
-  w.sc = choose_scan(p->num_disp, band, p->tau);
-  const int dpad = full_layout(p->num_disp).dpad();
-  w.cmargin = (int)align_up((size_t)std::max(dpad, p->num_disp) + 1, 16);
+  w.sc = choose_scan(p->num_disp, band, p->tau, s);
+  w.cmargin = (int)align_up((size_t)std::max(max_dpad(p->num_disp), p->num_disp) + 1, 16);
   w.cpitch = w.cmargin + W;
   w.census_off = 0;
   const size_t cen = align_up((size_t)H * w.cpitch * sizeof(uint32_t));
@@ -248,21 +180,8 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band) {
   return w;
 }
 
-// census(L), census(R) -> all P directions -> reduce. disp may be null (intermediate level).
-mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const uint8_t* R,
-                     int rpitch, int W, int H, const mpv_band* band, int16_t* disp,
-                     int16_t* right, int16_t* raw, uint8_t* ws, int level, hipStream_t s) {
-  const LevelWs lw = level_ws(p, W, H, band);
-  uint32_t* cl = (uint32_t*)(ws + lw.census_off);
-  uint32_t* cr = cl + align_up((size_t)H * lw.cpitch * sizeof(uint32_t)) / sizeof(uint32_t);
-  uint8_t* part = ws + lw.part_off;
-  {
-    HookScope hs(MPV_STAGE_CENSUS, level, s);
-    dim3 g = pix_grid(W, H);
-    g.z = 2;
-    hipLaunchKernelGGL(k_census, g, dim3(256), 0, s, L, W, H, lpitch, cl, lw.cpitch, lw.cmargin,
-                       R, rpitch, cr);
-  }
+ScanArgs level_scan_args(const mpv_params* p, int W, int H, const mpv_band* band,
+                         const LevelWs& lw, uint8_t* ws) {
   ScanArgs a{};
   a.W = W;
   a.H = H;
@@ -270,46 +189,67 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
   a.cap = (band && band->lo) ? band->cap : p->num_disp;
   a.lambda = p->lambda;
   a.tau = tau_eff(p->tau, p->num_disp);
-  a.cl = cl;
-  a.cr = cr;
+  if (ws) {
+    a.cl = (const uint32_t*)(ws + lw.census_off);
+    a.cr = a.cl + align_up((size_t)H * lw.cpitch * sizeof(uint32_t)) / sizeof(uint32_t);
+    a.part = ws + lw.part_off;
+  }
   a.cpitch = lw.cpitch;
   a.cmargin = lw.cmargin;
   a.lo = band ? band->lo : nullptr;
   a.len = (band && band->lo) ? band->len : nullptr;
-  a.part = part;
-
   a.capP = lw.sc.capP;
   a.part_stride = (long long)H * W * lw.sc.capP;
-  int dirs[8];
-  for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
-  const int blocks = plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
+  a.dir_base = 0;
+  a.npd = p->num_paths;
+  return a;
+}
 
-  {
-    HookScope hs(MPV_STAGE_SCAN, level, s);
-    if (lw.sc.banded_kernel)
-      launch_band<SRC_CENSUS, OUT_PART>(a, lw.sc.LPL, blocks, s);
-    else
-      launch_full<SRC_CENSUS, OUT_PART>(a, lw.sc.LPL, lw.sc.K, blocks, s);
-  }
+RedArgs level_red_args(const mpv_params* p, const ScanArgs& a, const LevelWs& lw, int16_t* disp,
+                       int16_t* right, int16_t* raw) {
   RedArgs ra{};
-  ra.W = W;
-  ra.H = H;
+  ra.W = a.W;
+  ra.H = a.H;
   ra.D = p->num_disp;
   ra.stride = lw.sc.capP;
   ra.bcap = a.cap;
   ra.lo = a.lo;
   ra.len = a.len;
   ra.absolute = lw.sc.absolute ? 1 : 0;
-  ra.part = part;
+  ra.part = a.part;
   ra.part_stride = a.part_stride;
   ra.npart = p->num_paths;
   ra.lr = p->lr_max_diff;
+  ra.need_lr = (disp || right) ? 1 : 0;
   ra.disp = disp;
   ra.right = right;
   ra.raw = raw;
+  return ra;
+}
+
+// census(L), census(R) -> all P directions -> reduce. disp may be null (intermediate level).
+mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const uint8_t* R,
+                     int rpitch, int W, int H, const mpv_band* band, int16_t* disp,
+                     int16_t* right, int16_t* raw, uint8_t* ws, int level,
+                     const mpv_schedule& sched, hipStream_t s) {
+  const LevelWs lw = level_ws(p, W, H, band, sched);
+  ScanArgs a = level_scan_args(p, W, H, band, lw, ws);
+  {
+    HookScope hs(MPV_STAGE_CENSUS, level, s);
+    mpvl::census(L, lpitch, R, rpitch, W, H, (uint32_t*)a.cl, (uint32_t*)a.cr, lw.cpitch,
+                 lw.cmargin, s);
+  }
+  int dirs[8];
+  for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
+  plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
+  {
+    HookScope hs(MPV_STAGE_SCAN, level, s);
+    launch_scan(a, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
+  }
+  const RedArgs ra = level_red_args(p, a, lw, disp, right, raw);
   {
     HookScope hs(MPV_STAGE_REDUCE, level, s);
-    launch_reduce_part(ra, (disp || right) ? 1 : 0, s);
+    mpvl::reduce_part(ra, ra.need_lr, s);
   }
   return launched();
 }
@@ -319,10 +259,13 @@ struct PyrGeom {
   int W[MPV_MAX_LEVELS], H[MPV_MAX_LEVELS], D[MPV_MAX_LEVELS], cap[MPV_MAX_LEVELS];
 };
 
-mpv_status pyr_geom(const mpv_pyramid_params* p, int W, int H, PyrGeom& g) {
+mpv_status pyr_geom(const mpv_pyramid_params* p, int D, int W, int H, PyrGeom& g) {
   if (!p) return MPV_ERR_INVALID_ARG;
-  mpv_status st = check_params(&p->base, true);
+  mpv_params base = p->base;
+  base.num_disp = D;
+  mpv_status st = check_params(&base, true);
   if (st) return st;
+  if ((st = check_sched(p->sched))) return st;
   if (p->levels < 1 || p->levels > MPV_MAX_LEVELS || p->band_radius < 0) return MPV_ERR_INVALID_ARG;
   if (W < 1 || H < 1 || W > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
   g.L = p->levels;
@@ -330,7 +273,7 @@ mpv_status pyr_geom(const mpv_pyramid_params* p, int W, int H, PyrGeom& g) {
     const int sh = g.L - 1 - l;
     g.W[l] = W >> sh;
     g.H[l] = H >> sh;
-    g.D[l] = (p->base.num_disp + (1 << sh) - 1) >> sh;
+    g.D[l] = (D + (1 << sh) - 1) >> sh;
     if (g.W[l] < 1 || g.H[l] < 1) return MPV_ERR_INVALID_ARG;
     g.cap[l] = l == 0 ? g.D[l] : std::min(2 * p->band_radius + 1, g.D[l]);
   }
@@ -344,6 +287,12 @@ struct PyrWs {
   size_t level_off;  // census + partials, reused per level
   size_t total;
 };
+
+mpv_params level_params(const mpv_pyramid_params* p, int Dl) {
+  mpv_params lp = p->base;
+  lp.num_disp = Dl;
+  return lp;
+}
 
 PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g) {
   PyrWs w{};
@@ -361,15 +310,251 @@ PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g) {
   w.level_off = off;
   size_t lvl = 0;
   for (int l = 0; l < g.L; ++l) {
-    mpv_params lp = p->base;
-    lp.num_disp = g.D[l];
+    const mpv_params lp = level_params(p, g.D[l]);
     mpv_band b{nullptr, nullptr, g.cap[l]};
     int16_t dummy;
     if (l > 0) b.lo = &dummy;  // only presence matters for sizing
-    lvl = std::max(lvl, level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr).total);
+    lvl = std::max(lvl, level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched).total);
   }
   w.total = off + lvl;
   return w;
+}
+
+}  // namespace
+
+// =========================================================================================
+// Batch planner
+// =========================================================================================
+struct mpv_batch_s {
+  mpv_pyramid_params p;
+  struct Pair {
+    mpv_batch_item item;
+    PyrGeom g;
+    PyrWs w;
+    size_t off;  // workspace region of this pair (after the tables)
+  };
+  std::vector<Pair> pairs;
+  size_t table_bytes = 0;  // descriptor tables at the start of the workspace
+  size_t total = 0;
+  uint8_t* ws = nullptr;
+  enum Kind { DOWN, CENSUS, PROP, SCAN_FULL, SCAN_BAND, REDUCE };
+  struct Launch {
+    Kind kind;
+    int level;
+    size_t desc_off, first_off;  // in the table area
+    int nseg, units;             // units: waves (scans), blocks (others)
+    int LPL, K, tau, stride;
+    bool masked;
+  };
+  std::vector<Launch> launches;  // execution order
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Descriptor tables and segment prefixes appended to a host image of the table area.
+struct TableBuilder {
+  std::vector<uint8_t> bytes;
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    const size_t off = align_up(bytes.size(), 16);
+    bytes.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+// Plan every launch of a batch. With ws == nullptr the pointers are left null and only the
+// table size matters.
+void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
+  b.launches.clear();
+  const int L = b.p.levels;
+  const mpv_schedule& sc = b.p.sched;
+  const int n = (int)b.pairs.size();
+  auto region = [&](const mpv_batch_s::Pair& pr) -> uint8_t* {
+    return ws ? ws + b.table_bytes + pr.off : nullptr;
+  };
+  auto add_pix = [&](mpv_batch_s::Kind kind, int level, std::vector<PixArgs>& d, int views) {
+    std::vector<int> first;
+    int blocks = 0;
+    for (auto& a : d) {
+      a.tiles_x = (a.W + 63) / 64;
+      a.tiles = a.tiles_x * ((a.H + 3) / 4);
+      first.push_back(blocks);
+      blocks += a.tiles * views;
+    }
+    first.push_back(blocks);
+    mpv_batch_s::Launch ln{};
+    ln.kind = kind;
+    ln.level = level;
+    ln.desc_off = tb.put(d);
+    ln.first_off = tb.put(first);
+    ln.nseg = (int)d.size();
+    ln.units = blocks;
+    b.launches.push_back(ln);
+  };
+  auto img_at = [&](const mpv_batch_s::Pair& pr, int l, int v, int& pitch) -> const uint8_t* {
+    if (l == L - 1) {
+      const mpv_image& im = v ? pr.item.right : pr.item.left;
+      pitch = im.pitch;
+      return im.data;
+    }
+    pitch = pr.g.W[l];
+    uint8_t* r = region(pr);
+    return r ? r + pr.w.img_off[l] + (size_t)v * pr.g.W[l] * pr.g.H[l] : nullptr;
+  };
+  // image pyramids, finest to coarsest
+  for (int l = L - 2; l >= 0; --l) {
+    std::vector<PixArgs> d;
+    for (auto& pr : b.pairs) {
+      PixArgs a{};
+      a.W = pr.g.W[l];
+      a.H = pr.g.H[l];
+      for (int v = 0; v < 2; ++v) {
+        a.in[v] = img_at(pr, l + 1, v, a.in_pitch[v]);
+        int dummy;
+        a.out[v] = (void*)img_at(pr, l, v, dummy);
+      }
+      d.push_back(a);
+    }
+    add_pix(mpv_batch_s::DOWN, l, d, 2);
+  }
+  for (int l = 0; l < L; ++l) {
+    const bool last = l == L - 1;
+    std::vector<PixArgs> cd;
+    std::vector<ScanArgs> sargs(n);
+    std::vector<LevelWs> lws(n);
+    for (int i = 0; i < n; ++i) {
+      auto& pr = b.pairs[i];
+      uint8_t* r = region(pr);
+      const mpv_params lp = level_params(&b.p, pr.g.D[l]);
+      static int16_t dummy_lo;
+      mpv_band band{l > 0 ? (r ? (const int16_t*)(r + pr.w.lo_off) : &dummy_lo) : nullptr, nullptr,
+                    pr.g.cap[l]};
+      lws[i] = level_ws(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, sc);
+      sargs[i] = level_scan_args(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, lws[i],
+                                 r ? r + pr.w.level_off : nullptr);
+      if (!r) sargs[i].lo = nullptr;
+      PixArgs a{};
+      a.W = pr.g.W[l];
+      a.H = pr.g.H[l];
+      for (int v = 0; v < 2; ++v) a.in[v] = img_at(pr, l, v, a.in_pitch[v]);
+      a.out[0] = (void*)sargs[i].cl;
+      a.out[1] = (void*)sargs[i].cr;
+      a.opitch = lws[i].cpitch;
+      a.omargin = lws[i].cmargin;
+      cd.push_back(a);
+    }
+    add_pix(mpv_batch_s::CENSUS, l, cd, 2);
+    if (l > 0) {
+      std::vector<PixArgs> pd;
+      for (auto& pr : b.pairs) {
+        uint8_t* r = region(pr);
+        PixArgs a{};
+        a.W = pr.g.W[l];
+        a.H = pr.g.H[l];
+        a.coarse = r ? (const int16_t*)(r + pr.w.raw_off[l - 1]) : nullptr;
+        a.Wc = pr.g.W[l - 1];
+        a.Hc = pr.g.H[l - 1];
+        a.Dl = pr.g.D[l];
+        a.R = b.p.band_radius;
+        a.cap = pr.g.cap[l];
+        a.lo = r ? (int16_t*)(r + pr.w.lo_off) : nullptr;
+        pd.push_back(a);
+      }
+      add_pix(mpv_batch_s::PROP, l, pd, 1);
+    }
+    // scans: pairs grouped by kernel variant, one descriptor per (pair, direction)
+    struct Key {
+      bool band;
+      int LPL, K, tau;
+      bool masked;
+      bool operator==(const Key& o) const {
+        return band == o.band && LPL == o.LPL && K == o.K && tau == o.tau && masked == o.masked;
+      }
+    };
+    auto key_of = [&](int i) {
+      const ScanChoice& c = lws[i].sc;
+      return Key{c.banded_kernel, c.LPL, c.K, sargs[i].tau, c.masked};
+    };
+    std::vector<Key> keys;
+    for (int i = 0; i < n; ++i)
+      if (std::find(keys.begin(), keys.end(), key_of(i)) == keys.end()) keys.push_back(key_of(i));
+    for (const Key& k : keys) {
+      struct Item {
+        ScanArgs a;
+        int len;
+      };
+      std::vector<Item> items;
+      for (int i = 0; i < n; ++i) {
+        if (!(key_of(i) == k)) continue;
+        for (int r = 0; r < b.p.base.num_paths; ++r) {
+          ScanArgs a = sargs[i];
+          a.dir_base = r;
+          plan_dirs(a, &r, 1, k.LPL);
+          items.push_back({a, line_len_host(r, a.W, a.H)});
+        }
+      }
+      if (sc.order == 1)  // longest lines first: the last waves to start are the short ones
+        std::stable_sort(items.begin(), items.end(),
+                         [](const Item& x, const Item& y) { return x.len > y.len; });
+      std::vector<ScanArgs> d;
+      std::vector<int> first;
+      int waves = 0;
+      for (auto& it : items) {
+        d.push_back(it.a);
+        first.push_back(waves);
+        waves += it.a.gprefix[1];
+      }
+      first.push_back(waves);
+      mpv_batch_s::Launch ln{};
+      ln.kind = k.band ? mpv_batch_s::SCAN_BAND : mpv_batch_s::SCAN_FULL;
+      ln.level = l;
+      ln.desc_off = tb.put(d);
+      ln.first_off = tb.put(first);
+      ln.nseg = (int)d.size();
+      ln.units = waves;
+      ln.LPL = k.LPL;
+      ln.K = k.K;
+      ln.tau = k.tau;
+      ln.masked = k.masked;
+      b.launches.push_back(ln);
+    }
+    // reduce: pairs grouped by partial stride
+    std::vector<int> strides;
+    for (int i = 0; i < n; ++i)
+      if (std::find(strides.begin(), strides.end(), lws[i].sc.capP) == strides.end())
+        strides.push_back(lws[i].sc.capP);
+    for (int st : strides) {
+      std::vector<RedArgs> d;
+      std::vector<int> first;
+      int rows = 0;
+      for (int i = 0; i < n; ++i) {
+        if (lws[i].sc.capP != st) continue;
+        auto& pr = b.pairs[i];
+        uint8_t* r = region(pr);
+        const mpv_params lp = level_params(&b.p, pr.g.D[l]);
+        int16_t* raw = r ? (int16_t*)(r + pr.w.raw_off[l]) : nullptr;
+        RedArgs ra = level_red_args(&lp, sargs[i], lws[i], last ? pr.item.disp : nullptr,
+                                    last ? pr.item.disp_right : nullptr, raw);
+        if (last && pr.item.disp_raw) ra.raw = pr.item.disp_raw;
+        d.push_back(ra);
+        first.push_back(rows);
+        rows += ra.H;
+      }
+      first.push_back(rows);
+      mpv_batch_s::Launch ln{};
+      ln.kind = mpv_batch_s::REDUCE;
+      ln.level = l;
+      ln.desc_off = tb.put(d);
+      ln.first_off = tb.put(first);
+      ln.nseg = (int)d.size();
+      ln.units = rows;
+      ln.stride = st;
+      b.launches.push_back(ln);
+    }
+  }
 }
 
 }  // namespace
@@ -390,9 +575,8 @@ const char* mpv_status_string(mpv_status s) {
 
 mpv_status mpv_census(const mpv_image* img, uint32_t* census, hipStream_t stream) {
   if (!valid_image(img) || !census) return MPV_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(k_census, pix_grid(img->width, img->height), dim3(256), 0, stream, img->data,
-                     img->width, img->height, img->pitch, census, img->width, 0, img->data,
-                     img->pitch, census);
+  mpvl::census(img->data, img->pitch, nullptr, 0, img->width, img->height, census, nullptr,
+               img->width, 0, stream);
   return launched();
 }
 
@@ -400,8 +584,7 @@ mpv_status mpv_downsample(const mpv_image* img, uint8_t* out, hipStream_t stream
   if (!valid_image(img) || !out) return MPV_ERR_INVALID_ARG;
   const int w = img->width / 2, h = img->height / 2;
   if (w < 1 || h < 1) return MPV_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(k_downsample, pix_grid(w, h), dim3(256), 0, stream, img->data, img->pitch,
-                     out, w, h, img->data, img->pitch, out);
+  mpvl::downsample(img->data, img->pitch, out, nullptr, 0, nullptr, w, h, stream);
   return launched();
 }
 
@@ -415,10 +598,9 @@ mpv_status mpv_cost(const mpv_params* p, const mpv_image* left, const mpv_image*
   const int W = left->width, H = left->height;
   if (W > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
   const bool banded = band && band->lo;
-  const int cap = banded ? band->cap : p->num_disp;
-  hipLaunchKernelGGL(k_cost, dim3(H), dim3(256), 2 * W * sizeof(uint32_t), stream, left->data,
-                     left->pitch, right->data, right->pitch, W, H, banded ? band->lo : nullptr,
-                     banded ? band->len : nullptr, cap, p->num_disp, cost);
+  mpvl::cost(left->data, left->pitch, right->data, right->pitch, W, H, banded ? band->lo : nullptr,
+             banded ? band->len : nullptr, banded ? band->cap : p->num_disp, p->num_disp, cost,
+             stream);
   return launched();
 }
 
@@ -439,14 +621,13 @@ mpv_status mpv_aggregate(const mpv_params* p, const uint8_t* cost, int32_t W, in
   const double bound = (double)nd * (banded ? 24 + lt : 24) * std::max(W, H);
   if (bound > (p->agg_type == MPV_AGG_U16 ? 65535.0 : 2147483647.0)) return MPV_ERR_OVERFLOW;
   const size_t n = (size_t)W * H * cap;
-  const int fb = (int)std::min<size_t>((n + 255) / 256, 65536);
   if (p->agg_type == MPV_AGG_U16)
-    hipLaunchKernelGGL(k_fill<uint16_t>, dim3(fb), dim3(256), 0, stream, (uint16_t*)agg, n,
-                       (uint16_t)0xFFFF);
+    mpvl::fill_u16((uint16_t*)agg, n, 0xFFFF, stream);
   else
-    hipLaunchKernelGGL(k_fill<int32_t>, dim3(fb), dim3(256), 0, stream, (int32_t*)agg, n,
-                       (int32_t)0x7FFFFFFF);
-  const ScanChoice sc = choose_scan(p->num_disp, band, p->tau);
+    mpvl::fill_i32((int32_t*)agg, n, 0x7FFFFFFF, stream);
+  const mpv_schedule dflt{};
+  const ScanChoice sc = choose_scan(p->num_disp, band, p->tau, dflt);
+  const int out = p->agg_type == MPV_AGG_U16 ? OUT_U16 : OUT_I32;
   for (int i = 0; i < nd; ++i) {
     ScanArgs a{};
     a.W = W;
@@ -460,18 +641,9 @@ mpv_status mpv_aggregate(const mpv_params* p, const uint8_t* cost, int32_t W, in
     a.len = banded ? band->len : nullptr;
     a.agg = agg;
     a.first = i == 0;
-    const int blocks = plan_dirs(a, &dirs[i], 1, sc.LPL);
-    if (sc.banded_kernel) {
-      if (p->agg_type == MPV_AGG_U16)
-        launch_band<SRC_COST, OUT_U16>(a, sc.LPL, blocks, stream);
-      else
-        launch_band<SRC_COST, OUT_I32>(a, sc.LPL, blocks, stream);
-    } else {
-      if (p->agg_type == MPV_AGG_U16)
-        launch_full<SRC_COST, OUT_U16>(a, sc.LPL, sc.K, blocks, stream);
-      else
-        launch_full<SRC_COST, OUT_I32>(a, sc.LPL, sc.K, blocks, stream);
-    }
+    a.npd = 1;
+    plan_dirs(a, &dirs[i], 1, sc.LPL);
+    launch_scan(a, sc, SRC_COST, out, dflt, stream);
   }
   return launched();
 }
@@ -495,19 +667,17 @@ mpv_status mpv_disparity(const mpv_params* p, const void* agg, int32_t W, int32_
   ra.absolute = 0;
   ra.agg = agg;
   ra.lr = p->lr_max_diff;
+  ra.need_lr = 1;
   ra.disp = disp;
   ra.right = disp_right;
   ra.raw = disp_raw;
-  if (p->agg_type == MPV_AGG_U16)
-    launch_reduce<IN_U16>(ra, stream);
-  else
-    launch_reduce<IN_I32>(ra, stream);
+  mpvl::reduce_agg(ra, p->agg_type == MPV_AGG_U16 ? IN_U16 : IN_I32, stream);
   return launched();
 }
 
 size_t mpv_match_workspace_bytes(const mpv_params* p, int32_t W, int32_t H, const mpv_band* band) {
   if (check_params(p, true) || W < 1 || H < 1 || check_band(band, p->num_disp)) return 0;
-  return level_ws(p, W, H, band).total;
+  return level_ws(p, W, H, band, mpv_schedule{}).total;
 }
 
 mpv_status mpv_match(const mpv_params* p, const mpv_image* left, const mpv_image* right,
@@ -519,25 +689,28 @@ mpv_status mpv_match(const mpv_params* p, const mpv_image* left, const mpv_image
   if (left->width != right->width || left->height != right->height) return MPV_ERR_INVALID_ARG;
   if (left->width > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
   if ((st = check_band(band, p->num_disp))) return st;
-  const size_t need = level_ws(p, left->width, left->height, band).total;
+  const mpv_schedule dflt{};
+  const size_t need = level_ws(p, left->width, left->height, band, dflt).total;
   if (!workspace || workspace_bytes < need) return MPV_ERR_WORKSPACE;
   return run_level(p, left->data, left->pitch, right->data, right->pitch, left->width,
-                   left->height, band, disp, disp_right, disp_raw, (uint8_t*)workspace, 0, stream);
+                   left->height, band, disp, disp_right, disp_raw, (uint8_t*)workspace, 0, dflt,
+                   stream);
 }
 
 size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params* p, int32_t W, int32_t H) {
   PyrGeom g;
-  if (pyr_geom(p, W, H, g)) return 0;
+  if (!p || pyr_geom(p, p->base.num_disp, W, H, g)) return 0;
   return pyr_ws(p, g).total;
 }
 
 mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
                        const mpv_image* right, const mpv_pyramid_out* out, void* workspace,
                        size_t workspace_bytes, hipStream_t stream) {
-  if (!valid_image(left) || !valid_image(right) || !out || !out->disp) return MPV_ERR_INVALID_ARG;
+  if (!valid_image(left) || !valid_image(right) || !out || !out->disp || !p)
+    return MPV_ERR_INVALID_ARG;
   if (left->width != right->width || left->height != right->height) return MPV_ERR_INVALID_ARG;
   PyrGeom g;
-  mpv_status st = pyr_geom(p, left->width, left->height, g);
+  mpv_status st = pyr_geom(p, p->base.num_disp, left->width, left->height, g);
   if (st) return st;
   const PyrWs w = pyr_ws(p, g);
   if (!workspace || workspace_bytes < w.total) return MPV_ERR_WORKSPACE;
@@ -555,10 +728,7 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     uint8_t* dl = ws + w.img_off[l];
     uint8_t* dr = dl + (size_t)g.W[l] * g.H[l];
     HookScope hs(MPV_STAGE_DOWNSAMPLE, l, stream);
-    dim3 gd = pix_grid(g.W[l], g.H[l]);
-    gd.z = 2;
-    hipLaunchKernelGGL(k_downsample, gd, dim3(256), 0, stream, li[l + 1], lp[l + 1], dl, g.W[l],
-                       g.H[l], ri[l + 1], rp[l + 1], dr);
+    mpvl::downsample(li[l + 1], lp[l + 1], dl, ri[l + 1], rp[l + 1], dr, g.W[l], g.H[l], stream);
     li[l] = dl;
     ri[l] = dr;
     lp[l] = rp[l] = g.W[l];
@@ -566,23 +736,21 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
   int16_t* lo = (int16_t*)(ws + w.lo_off);
   for (int l = 0; l < L; ++l) {
     int16_t* raw = out->level_raw[l] ? out->level_raw[l] : (int16_t*)(ws + w.raw_off[l]);
-    mpv_params lpar = p->base;
-    lpar.num_disp = g.D[l];
+    const mpv_params lpar = level_params(p, g.D[l]);
     mpv_band b{nullptr, nullptr, g.cap[l]};
     if (l > 0) {
       const int16_t* prev = out->level_raw[l - 1] ? out->level_raw[l - 1]
                                                   : (const int16_t*)(ws + w.raw_off[l - 1]);
       HookScope hs(MPV_STAGE_PROPAGATE, l, stream);
-      hipLaunchKernelGGL(k_propagate, pix_grid(g.W[l], g.H[l]), dim3(256), 0, stream, prev,
-                         g.W[l - 1], g.H[l - 1], g.W[l], g.H[l], g.D[l], p->band_radius, g.cap[l],
-                         lo);
+      mpvl::propagate(prev, g.W[l - 1], g.H[l - 1], g.W[l], g.H[l], g.D[l], p->band_radius,
+                      g.cap[l], lo, stream);
       b.lo = lo;
     }
     const bool last = l == L - 1;
     if (last && out->disp_raw && !out->level_raw[l]) raw = out->disp_raw;
     st = run_level(&lpar, li[l], lp[l], ri[l], rp[l], g.W[l], g.H[l], l > 0 ? &b : nullptr,
                    last ? out->disp : nullptr, last ? out->disp_right : nullptr, raw,
-                   ws + w.level_off, l, stream);
+                   ws + w.level_off, l, p->sched, stream);
     if (st) return st;
     if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
       if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),
@@ -590,6 +758,139 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
         return MPV_ERR_DEVICE;
   }
   return launched();
+}
+
+// ---- batch -------------------------------------------------------------------------------
+mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* items, int32_t n,
+                            mpv_batch* out) {
+  if (!p || !items || n < 1 || !out) return MPV_ERR_INVALID_ARG;
+  mpv_batch_s* b = new (std::nothrow) mpv_batch_s();
+  if (!b) return MPV_ERR_INVALID_ARG;
+  b->p = *p;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    const mpv_batch_item& it = items[i];
+    if (!valid_image(&it.left) || !valid_image(&it.right) || !it.disp ||
+        it.left.width != it.right.width || it.left.height != it.right.height) {
+      delete b;
+      return MPV_ERR_INVALID_ARG;
+    }
+    mpv_batch_s::Pair pr{};
+    pr.item = it;
+    const mpv_status st = pyr_geom(p, it.num_disp, it.left.width, it.left.height, pr.g);
+    if (st) {
+      delete b;
+      return st;
+    }
+    pr.w = pyr_ws(p, pr.g);
+    pr.off = off;
+    off += align_up(pr.w.total);
+    b->pairs.push_back(pr);
+  }
+  TableBuilder tb;
+  plan_batch(*b, nullptr, tb);
+  b->table_bytes = align_up(tb.bytes.size());
+  b->total = b->table_bytes + off;
+  *out = b;
+  return MPV_OK;
+}
+
+size_t mpv_batch_workspace_bytes(mpv_batch b) { return b ? b->total : 0; }
+
+mpv_status mpv_batch_bind(mpv_batch b, void* workspace, size_t bytes, hipStream_t stream) {
+  if (!b || !workspace) return MPV_ERR_INVALID_ARG;
+  if (bytes < b->total) return MPV_ERR_WORKSPACE;
+  b->ws = (uint8_t*)workspace;
+  TableBuilder tb;
+  plan_batch(*b, b->ws, tb);
+  if (align_up(tb.bytes.size()) > b->table_bytes) return MPV_ERR_WORKSPACE;
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  if (hipMemcpyAsync(b->ws, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, stream) !=
+      hipSuccess)
+    return MPV_ERR_DEVICE;
+  return hipStreamSynchronize(stream) == hipSuccess ? MPV_OK : MPV_ERR_DEVICE;
+}
+
+mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
+  if (!b || !b->ws) return MPV_ERR_INVALID_ARG;
+  const int wpb = wpb_of(b->p.sched);
+  for (const auto& ln : b->launches) {
+    const void* desc = b->ws + ln.desc_off;
+    const int* first = (const int*)(b->ws + ln.first_off);
+    switch (ln.kind) {
+      case mpv_batch_s::DOWN: {
+        HookScope hs(MPV_STAGE_DOWNSAMPLE, ln.level, s);
+        mpvl::downsample_batch({(const PixArgs*)desc, first, ln.nseg}, ln.units, s);
+        break;
+      }
+      case mpv_batch_s::CENSUS: {
+        HookScope hs(MPV_STAGE_CENSUS, ln.level, s);
+        mpvl::census_batch({(const PixArgs*)desc, first, ln.nseg}, ln.units, s);
+        break;
+      }
+      case mpv_batch_s::PROP: {
+        HookScope hs(MPV_STAGE_PROPAGATE, ln.level, s);
+        mpvl::propagate_batch({(const PixArgs*)desc, first, ln.nseg}, ln.units, s);
+        break;
+      }
+      case mpv_batch_s::SCAN_FULL: {
+        HookScope hs(MPV_STAGE_SCAN, ln.level, s);
+        mpvl::scan_full_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.K,
+                              ln.tau, ln.masked, wpb, s);
+        break;
+      }
+      case mpv_batch_s::SCAN_BAND: {
+        HookScope hs(MPV_STAGE_SCAN, ln.level, s);
+        mpvl::scan_band_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.tau,
+                              false, wpb, s);
+        break;
+      }
+      case mpv_batch_s::REDUCE: {
+        HookScope hs(MPV_STAGE_REDUCE, ln.level, s);
+        mpvl::reduce_part_batch({(const RedArgs*)desc, first, ln.nseg}, ln.units, ln.stride, s);
+        break;
+      }
+    }
+  }
+  return launched();
+}
+
+mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t s) {
+  if (!b || !b->ws) return MPV_ERR_INVALID_ARG;
+  if (!b->exec) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return MPV_ERR_DEVICE;
+    mpv_status st = MPV_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      st = MPV_ERR_DEVICE;
+    } else {
+      st = mpv_batch_run(b, cap);
+      hipGraph_t g = nullptr;
+      if (hipStreamEndCapture(cap, &g) != hipSuccess || !g) st = MPV_ERR_DEVICE;
+      if (st == MPV_OK && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        b->exec = nullptr;
+        st = MPV_ERR_DEVICE;
+      }
+      b->graph = g;
+    }
+    (void)hipStreamDestroy(cap);
+    if (st) return st;
+  }
+  return hipGraphLaunch(b->exec, s) == hipSuccess ? MPV_OK : MPV_ERR_DEVICE;
+}
+
+void mpv_batch_destroy(mpv_batch b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
 }
 
 mpv_status mpv_set_timing_events(int32_t stage, int32_t level, hipEvent_t before, hipEvent_t after) {

@@ -1,0 +1,78 @@
+// Argument structs shared by the kernels (device) and the launch code (host).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpvk {
+
+enum { SRC_CENSUS = 0, SRC_COST = 1 };
+enum { OUT_PART = 0, OUT_U16 = 1, OUT_I32 = 2 };
+
+struct ScanArgs {
+  int W, H, D, cap;  // cap: slots per pixel of the cost volume / aggregate export
+  int lambda, tau;   // tau = min(tau, D-1) clamped to >= 1 (same energies, see host)
+  const uint32_t* cl;
+  const uint32_t* cr;
+  int cpitch, cmargin;
+  const uint8_t* cost;
+  const int16_t* lo;
+  const uint8_t* len;
+  uint8_t* part;
+  long long part_stride;  // bytes between direction volumes
+  int capP;               // partial slots per pixel
+  void* agg;              // canonical export [H][W][cap]
+  int first;              // canonical export: this direction writes instead of adding
+  // Directions of this descriptor: dir[0..ndir), their partial volumes are numbers
+  // dir_base .. dir_base+ndir-1 of the pair's npd volumes; stores of steps past a line's end
+  // go to a 256 B sink right after the pair's last volume.
+  int ndir;
+  int dir_base, npd;
+  int dir[8];
+  int gprefix[9];  // first wave of each direction (one wave = 64/LPL lines)
+};
+
+// Segment table of a batched launch: global wave u belongs to descriptor s with
+// first[s] <= u < first[s+1] (first[] ascending, first[0] = 0).
+template <typename T>
+struct Batch {
+  const T* desc;
+  const int* first;
+  int nseg;
+};
+
+enum { IN_PART = 0, IN_U16 = 1, IN_I32 = 2 };
+
+struct RedArgs {
+  int W, H, D;
+  int stride;  // slots per pixel of the input volume(s)
+  int bcap;    // band length where len == null (cap of the band, or D at full range)
+  const int16_t* lo;
+  const uint8_t* len;
+  int absolute;  // slot index = absolute disparity (partials of a banded full-range scan)
+  const uint8_t* part;
+  long long part_stride;
+  int npart;
+  const void* agg;
+  int lr;
+  int need_lr;  // batched launches: compute right disparity + LR for this descriptor
+  int16_t* disp;
+  int16_t* right;
+  int16_t* raw;
+};
+
+struct PixArgs {
+  int W, H;                // output size of this stage
+  const uint8_t* in[2];    // source images (views)
+  int in_pitch[2];
+  void* out[2];            // census: uint32 at y*opitch + omargin + x; downsample: uint8 [H][W]
+  int opitch, omargin;
+  int tiles_x, tiles;      // tiles per view
+  // propagate
+  const int16_t* coarse;
+  int Wc, Hc, Dl, R, cap;
+  int16_t* lo;
+};
+
+constexpr int RED_MAXW = 4096;
+
+}  // namespace mpvk

@@ -145,12 +145,27 @@ def match(left, right, params: MPVParams, band: Band | None = None, workspace=No
     return (disp, right_d, raw) if want_all else disp
 
 
-def pyramid_params(params: MPVParams, levels: int, radius: int) -> _L.PyramidParams:
-    return _L.PyramidParams(params.c(), levels, radius)
+@dataclass(frozen=True)
+class Schedule:
+    """Launch schedule (all give bit-identical results): waves per scan block (1/2/4),
+    lanes per line of full-range scans (0 default, 16/32/64), lanes per line of banded
+    scans (0 default, 16/32/64), batched scan order (0 pair by pair, 1 longest first)."""
+    waves_per_block: int = 0
+    full_lanes: int = 0
+    band_lanes: int = 0
+    order: int = 0
+
+    def c(self) -> _L.Schedule:
+        return _L.Schedule(self.waves_per_block, self.full_lanes, self.band_lanes, self.order)
 
 
-def pyramid_workspace_bytes(params: MPVParams, levels: int, radius: int, width: int, height: int) -> int:
-    pp = pyramid_params(params, levels, radius)
+def pyramid_params(params: MPVParams, levels: int, radius: int, sched: Schedule | None = None) -> _L.PyramidParams:
+    return _L.PyramidParams(params.c(), levels, radius, (sched or Schedule()).c())
+
+
+def pyramid_workspace_bytes(params: MPVParams, levels: int, radius: int, width: int, height: int,
+                            sched: Schedule | None = None) -> int:
+    pp = pyramid_params(params, levels, radius, sched)
     return int(_L.lib().mpv_pyramid_workspace_bytes(C.byref(pp), width, height))
 
 
@@ -161,10 +176,10 @@ class Pyramid:
     current stream and returns the finest LR-checked disparity (int16, -1 invalid)."""
 
     def __init__(self, params: MPVParams, width: int, height: int, levels: int = 3, radius: int = 4,
-                 device="cuda", keep_levels: bool = False):
+                 device="cuda", keep_levels: bool = False, sched: Schedule | None = None):
         self.params, self.width, self.height = params, width, height
         self.levels, self.radius = levels, radius
-        self._pp = pyramid_params(params, levels, radius)
+        self._pp = pyramid_params(params, levels, radius, sched)
         need = int(_L.lib().mpv_pyramid_workspace_bytes(C.byref(self._pp), width, height))
         if need == 0:
             raise _L.MPVError(_L.MPV_ERR_INVALID_ARG, "mpv_pyramid_workspace_bytes")
@@ -191,8 +206,62 @@ class Pyramid:
         return self.disp
 
 
-def pyramid(left, right, params: MPVParams, levels=3, radius=4, keep_levels=False):
+def pyramid(left, right, params: MPVParams, levels=3, radius=4, keep_levels=False, sched=None):
     h, w = left.shape
-    pyr = Pyramid(params, w, h, levels, radius, device=left.device, keep_levels=keep_levels)
+    pyr = Pyramid(params, w, h, levels, radius, device=left.device, keep_levels=keep_levels, sched=sched)
     pyr(left, right)
     return pyr
+
+
+class Batch:
+    """Many stereo pairs of different sizes and ranges matched together: every stage of
+    every pyramid level is one launch over all pairs (descriptor table in the workspace),
+    optionally replayed as one captured hipGraph. Each pair's output equals its solo
+    mpv_pyramid result. The pairs' input tensors are held by reference; refill them in
+    place between runs (``run`` reads whatever they hold)."""
+
+    def __init__(self, pairs, params: MPVParams, levels=3, radius=4, sched: Schedule | None = None,
+                 device="cuda", want_all=False):
+        self.params, self.levels, self.radius = params, levels, radius
+        self.pairs = list(pairs)  # [(left, right, num_disp)]
+        self.disp, self.right, self.raw = [], [], []
+        items = (_L.BatchItem * len(self.pairs))()
+        for i, (l, r, d) in enumerate(self.pairs):
+            li, ri = _image(l, f"left[{i}]"), _image(r, f"right[{i}]")
+            out = torch.empty(l.shape, dtype=torch.int16, device=l.device)
+            rt = torch.empty_like(out) if want_all else None
+            rw = torch.empty_like(out) if want_all else None
+            self.disp.append(out)
+            self.right.append(rt)
+            self.raw.append(rw)
+            items[i] = _L.BatchItem(li, ri, int(d), out.data_ptr(),
+                                    None if rt is None else rt.data_ptr(),
+                                    None if rw is None else rw.data_ptr())
+        pp = pyramid_params(params, levels, radius, sched)
+        h = C.c_void_p()
+        _L.check(_L.lib().mpv_batch_create(C.byref(pp), items, len(self.pairs), C.byref(h)),
+                 "mpv_batch_create")
+        self._h = h
+        need = int(_L.lib().mpv_batch_workspace_bytes(h))
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
+        _L.check(_L.lib().mpv_batch_bind(h, self.workspace.data_ptr(), need, _stream()),
+                 "mpv_batch_bind")
+
+    def run(self):
+        _L.check(_L.lib().mpv_batch_run(self._h, _stream()), "mpv_batch_run")
+        return self.disp
+
+    def run_graph(self):
+        _L.check(_L.lib().mpv_batch_run_graph(self._h, _stream()), "mpv_batch_run_graph")
+        return self.disp
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _L.lib().mpv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -168,3 +168,32 @@ def config_scene(name: str, seed: int | None = None) -> tuple[Scene, dict]:
     k = lo + int(np.random.Generator(np.random.PCG64(np.random.SeedSequence([s, 7]))).integers(0, hi - lo + 1))
     scene = make_scene(s, cfg["width"], cfg["height"], cfg["num_disp"] - 1, k, ground=cfg["ground"])
     return scene, cfg
+
+
+# Batched workload: 64 pairs, sizes and ranges drawn uniformly (seed 3), pair i from seed 3000+i.
+BATCH_SIZES = [(640, 360), (1280, 720), (1920, 1080)]
+BATCH_DISPS = [64, 128, 256]
+
+
+def batch_specs(n: int = 64, seed: int = 3):
+    """(scene seed, width, height, D, planes) of each pair of the batched workload."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    sizes = rng.integers(0, len(BATCH_SIZES), n)
+    disps = rng.integers(0, len(BATCH_DISPS), n)
+    planes = rng.integers(20, 41, n)
+    return [(seed * 1000 + i, *BATCH_SIZES[int(s)], BATCH_DISPS[int(d)], int(k))
+            for i, (s, d, k) in enumerate(zip(sizes, disps, planes))]
+
+
+def _spec_scene(spec):
+    s, w, h, d, k = spec
+    return make_scene(s, w, h, d - 1, k, ground=True)
+
+
+def batch_scenes(specs, workers: int = 0):
+    """Scenes of a list of specs, generated in parallel worker processes."""
+    if workers <= 1 or len(specs) <= 1:
+        return [_spec_scene(sp) for sp in specs]
+    import concurrent.futures as cf
+    with cf.ProcessPoolExecutor(min(workers, len(specs))) as ex:
+        return list(ex.map(_spec_scene, specs))

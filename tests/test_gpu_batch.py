@@ -1,0 +1,139 @@
+"""Batched multi-pair execution and launch schedules, through the C ABI.
+
+* every pair of a batch (mixed sizes and ranges) equals its solo mpv_pyramid result and the
+  oracle, bit for bit, for every schedule;
+* graph replays: the captured batch replayed several times, with eager work and
+  synchronisations in between, matches the eager run each time;
+* schedule invariance: every schedule an autotuner may pick gives identical bits;
+* the 64-pair workload (640x360 / 1280x720 / 1920x1080, D in {64, 128, 256}) at full size:
+  every pair equals its solo run, a sample equals the oracle.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2001_09678_amd import mpv as m, _lib
+    _lib.lib()
+    return m
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+SMALL = [(96, 64, 32), (131, 75, 48), (200, 117, 128), (64, 40, 64), (150, 90, 96), (131, 75, 40)]
+SCHEDULES = [dict(), dict(waves_per_block=4, order=1), dict(waves_per_block=2, order=0),
+             dict(full_lanes=32, band_lanes=32, order=1)]
+
+
+def _small_scenes():
+    from paper_2001_09678_amd.scene import make_scene
+    return [make_scene(70 + i, w, h, d - 1, 6, ground=True) for i, (w, h, d) in enumerate(SMALL)]
+
+
+@pytest.mark.parametrize("sched", range(len(SCHEDULES)))
+def test_batch_equals_solo_and_oracle(mpv, orc, sched):
+    _log("batch small, schedule", SCHEDULES[sched])
+    scenes = _small_scenes()
+    params = mpv.MPVParams(num_disp=64, num_paths=8)
+    s = mpv.Schedule(**SCHEDULES[sched])
+    pairs = [(_cuda(sc.left), _cuda(sc.right), d) for sc, (_, _, d) in zip(scenes, SMALL)]
+    b = mpv.Batch(pairs, params, levels=3, radius=4, sched=s, want_all=True)
+    b.run()
+    for i, (sc, (w, h, d)) in enumerate(zip(scenes, SMALL)):
+        got = _np(b.disp[i])
+        solo = mpv.pyramid(pairs[i][0], pairs[i][1], mpv.MPVParams(num_disp=d, num_paths=8), levels=3,
+                           radius=4)
+        np.testing.assert_array_equal(got, _np(solo.disp), err_msg=f"pair {i} vs solo")
+        ref = orc.pyramid(sc.left, sc.right, d, levels=3, radius=4, num_paths=8)[-1]
+        np.testing.assert_array_equal(got, ref.out, err_msg=f"pair {i} vs oracle")
+        np.testing.assert_array_equal(_np(b.raw[i]), ref.dl)
+        np.testing.assert_array_equal(_np(b.right[i]), ref.dr)
+
+
+def test_batch_graph_replays(mpv):
+    """Capture once, replay with new inputs written between replays (eager work), each
+    replay checked against an eager run on the same inputs."""
+    import torch
+    from paper_2001_09678_amd.scene import make_scene
+    _log("batch graph replays")
+    params = mpv.MPVParams(num_disp=64, num_paths=8)
+    lefts = [torch.empty((h, w), dtype=torch.uint8, device="cuda") for (w, h, _) in SMALL]
+    rights = [torch.empty_like(t) for t in lefts]
+    pairs = [(l, r, d) for l, r, (_, _, d) in zip(lefts, rights, SMALL)]
+    gb = mpv.Batch(pairs, params, levels=3, radius=4, sched=mpv.Schedule(order=1))
+    eb = mpv.Batch(pairs, params, levels=3, radius=4)
+    for rep in range(3):
+        for i, (w, h, d) in enumerate(SMALL):
+            sc = make_scene(500 + 10 * rep + i, w, h, d - 1, 5, ground=rep % 2 == 0)
+            lefts[i].copy_(_cuda(sc.left))
+            rights[i].copy_(_cuda(sc.right))
+        torch.cuda.synchronize()
+        gb.run_graph()
+        torch.cuda.synchronize()
+        eb.run()
+        torch.cuda.synchronize()
+        for i in range(len(SMALL)):
+            np.testing.assert_array_equal(_np(gb.disp[i]), _np(eb.disp[i]), err_msg=f"replay {rep} pair {i}")
+        assert any((_np(t) >= 0).any() for t in gb.disp)
+
+
+@pytest.mark.parametrize("levels,sched", [
+    (3, dict(waves_per_block=4)), (3, dict(waves_per_block=2, band_lanes=32)), (3, dict(band_lanes=64)),
+    (1, dict(full_lanes=32)), (1, dict(full_lanes=32, waves_per_block=4)),
+])
+def test_schedule_invariance_full_size(mpv, levels, sched):
+    """1280x720, D=128, 8 paths: every schedule gives the default schedule's bits."""
+    from paper_2001_09678_amd.scene import config_scene
+    _log("schedule invariance", levels, sched)
+    sc, cfg = config_scene("c2")
+    L, R = _cuda(sc.left), _cuda(sc.right)
+    params = mpv.MPVParams(num_disp=128, num_paths=8)
+    ref = mpv.pyramid(L, R, params, levels=levels, radius=4)
+    got = mpv.pyramid(L, R, params, levels=levels, radius=4, sched=mpv.Schedule(**sched))
+    np.testing.assert_array_equal(_np(got.disp), _np(ref.disp))
+    np.testing.assert_array_equal(_np(got.right), _np(ref.right))
+    np.testing.assert_array_equal(_np(got.raw), _np(ref.raw))
+
+
+def test_batch_workload_full_size(mpv, orc):
+    """The 64-pair workload at its full sizes in the launch configuration the benchmark
+    times (graph replay, longest lines first): each pair equals its solo run; three
+    pairs (one of each size) equal the oracle."""
+    from paper_2001_09678_amd.scene import batch_specs, batch_scenes
+    specs = batch_specs()
+    _log("batch workload: generating", len(specs), "scenes")
+    scenes = batch_scenes(specs, workers=16)
+    params = mpv.MPVParams(num_disp=128, num_paths=8)
+    pairs = [(_cuda(sc.left), _cuda(sc.right), sp[3]) for sc, sp in zip(scenes, specs)]
+    _log("batch workload: run")
+    b = mpv.Batch(pairs, params, levels=3, radius=4, sched=mpv.Schedule(waves_per_block=4, order=1))
+    b.run_graph()
+    seen = set()
+    for i, (sc, sp) in enumerate(zip(scenes, specs)):
+        got = _np(b.disp[i])
+        solo = mpv.pyramid(pairs[i][0], pairs[i][1], mpv.MPVParams(num_disp=sp[3], num_paths=8),
+                           levels=3, radius=4)
+        np.testing.assert_array_equal(got, _np(solo.disp), err_msg=f"pair {i} {sp}")
+        if sp[1] not in seen:
+            seen.add(sp[1])
+            _log("oracle for pair", i, sp)
+            ref = orc.pyramid(sc.left, sc.right, sp[3], levels=3, radius=4, num_paths=8)[-1]
+            np.testing.assert_array_equal(got, ref.out, err_msg=f"pair {i} vs oracle")
