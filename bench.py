@@ -91,6 +91,43 @@ def stage_breakdown(pyr, left, right, levels, reps=20):
     return out
 
 
+def batch_bench(params, levels, dev, steps):
+    """64 pairs of mixed size (640x360 / 1280x720 / 1920x1080) and range (D 64/128/256),
+    multi-scale, one captured graph per batch, schedule picked by the autotuner."""
+    import torch
+    from paper_2001_09678_amd import autotune, mpv
+    from paper_2001_09678_amd.scene import batch_scenes, batch_specs
+    specs = batch_specs()
+    scenes = batch_scenes(specs, workers=16)
+    pairs = [(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev), sp[3])
+             for sc, sp in zip(scenes, specs)]
+    sched, _ = autotune.tune_batch(pairs, params, levels, 4, use_cache=False)
+    b = mpv.Batch(pairs, params, levels, 4, sched=sched)
+    for _ in range(3):
+        b.run_graph()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        b.run_graph()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    nominal = sum(w * h * d for _, w, h, d, _ in specs)
+    evaluated = 0
+    for _, w, h, d, _ in specs:
+        for l in range(levels):
+            s = levels - 1 - l
+            dl = -(-d // (1 << s))
+            evaluated += (w >> s) * (h >> s) * (dl if l == 0 else min(9, dl))
+    return {"pairs": len(specs), "ms_per_batch": round(ms, 4), "pairs_per_s": round(len(specs) / ms * 1e3, 1),
+            "value": round(nominal / (ms * 1e-3) / 1e6, 1), "unit": "Mde/s",
+            "mde_s_evaluated": round(evaluated / (ms * 1e-3) / 1e6, 1),
+            "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
+            "schedule": sched.__dict__, "graph": True}
+
+
 def pct(vals, q):
     s = sorted(vals)
     k = min(len(s) - 1, max(0, int(round(q / 100.0 * (len(s) - 1)))))
@@ -126,6 +163,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -133,10 +172,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2001_09678_amd import _lib as L
-    from paper_2001_09678_amd import mpv
+    from paper_2001_09678_amd import autotune, mpv
     from paper_2001_09678_amd.scene import config_scene
 
     L.lib()  # fails loudly without the HIP library
@@ -147,8 +185,12 @@ def main():
     right = torch.from_numpy(scene.right).to(dev)
     params = mpv.MPVParams(num_disp=D, num_paths=P, lam=8, tau=4, lr_max_diff=1)
 
+    # ---- schedules picked by the autotuner (every candidate is checked bit-identical)
+    sched, _ = autotune.tune_pyramid(left, right, params, levels, 4, use_cache=False)
+    psched, _ = autotune.tune_pyramid(left, right, params, 1, 4, use_cache=False)
+
     # ---- multi-scale (the measured workload)
-    pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev)
+    pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=sched)
     ms, per_step, scan_ms, wall = time_pipeline(pyr, left, right, args.steps, args.warmup,
                                                 hook_stage=L.STAGE_SCAN, hook_level=levels - 1)
     nominal = W * H * D
@@ -166,7 +208,7 @@ def main():
     achieved = scan_bytes / (scan_avg * 1e-3) / 1e9
 
     # ---- plain single-scale MPV on the same pair (full range at full resolution)
-    plain = mpv.Pyramid(params, W, H, levels=1, radius=4, device=dev)
+    plain = mpv.Pyramid(params, W, H, levels=1, radius=4, device=dev, sched=psched)
     pms, pstep, pscan, _ = time_pipeline(plain, left, right, args.plain_steps, min(args.warmup, 5),
                                          hook_stage=L.STAGE_SCAN, hook_level=0)
     pscan_avg = sum(pscan) / len(pscan)
@@ -174,6 +216,7 @@ def main():
     agree = float((plain.disp == pyr.disp).float().mean().item())
 
     breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
+    batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
 
     result = {
         "metric": METRIC,
@@ -210,6 +253,8 @@ def main():
                      "kernel": "k_scan_band<16,census,partial> (finest level, 8 directions)",
                      "kernel_ms": round(scan_avg, 4), "algorithmic_bytes": scan_bytes},
         "stage_ms": breakdown,
+        "schedule": {"multiscale": sched.__dict__, "plain": psched.__dict__},
+        "batch": batch,
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cfg)
