@@ -88,6 +88,17 @@ def lib():
             "mpv_batch_run": ([P, P], i32),
             "mpv_batch_run_graph": ([P, P], i32),
             "mpv_batch_destroy": ([P], None),
+            "mpv_lb_coarse_workspace_bytes": ([C.POINTER(Params), i32, i32], S),
+            "mpv_lb_coarse": ([C.POINTER(Params), C.POINTER(Image), C.POINTER(Image), P, P, P, P, S, P], i32),
+            "mpv_lb_packed_elems": ([i32, i32], S),
+            "mpv_lb_packed_bwd_elems": ([i32, i32], S),
+            "mpv_lb_pack": ([P, i32, i32, P, P, P], i32),
+            "mpv_lb_conv": ([P, i32, i32, i32, i32, P, P, i32, i32, P, i32, P, i32, i32, P], i32),
+            "mpv_lb_dw_workspace_bytes": ([i32, i32, i32, i32, i32], S),
+            "mpv_lb_conv_dw": ([P, P, i32, i32, i32, i32, i32, i32, P, P, P, S, P], i32),
+            "mpv_lb_loss": ([P, P, P, i32, i32, i32, i32, i32, C.c_float, C.c_float, P, P, P], i32),
+            "mpv_lb_adam": ([P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, i32, P], i32),
+            "mpv_lb_bands": ([P, P, i32, i32, i32, i32, i32, C.c_float, P, P, P, P], i32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)

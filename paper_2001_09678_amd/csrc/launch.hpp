@@ -49,4 +49,9 @@ void census_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
 void downsample_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
 void propagate_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
 
+// Features of a coarse level for the band-proposal network (kern_lb.hip).
+void lb_features(const uint8_t* part, long long pstride, int capP, int P, int D, int W, int H,
+                 const int16_t* raw, const int16_t* disp, const uint8_t* img, int ipitch, float Z,
+                 uint16_t* feat, hipStream_t s);
+
 }  // namespace mpvl

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/mpv.h"
+#include "../../include/mpv_lb.h"
 #include "launch.hpp"
 
 using namespace mpvk;
@@ -891,6 +892,35 @@ void mpv_batch_destroy(mpv_batch b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   delete b;
+}
+
+// ---- learned band proposal: coarse level + features --------------------------------------
+size_t mpv_lb_coarse_workspace_bytes(const mpv_params* p, int32_t W0, int32_t H0) {
+  if (check_params(p, true) || W0 < 1 || H0 < 1 || W0 > MPV_MAX_WIDTH) return 0;
+  return level_ws(p, W0, H0, nullptr, mpv_schedule{}).total;
+}
+
+mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_image* right0,
+                         uint16_t* feat, int16_t* raw0, int16_t* disp0, void* workspace,
+                         size_t workspace_bytes, hipStream_t stream) {
+  mpv_status st = check_params(p, true);
+  if (st) return st;
+  if (!valid_image(left0) || !valid_image(right0) || !feat || !raw0 || !disp0)
+    return MPV_ERR_INVALID_ARG;
+  if (left0->width != right0->width || left0->height != right0->height) return MPV_ERR_INVALID_ARG;
+  const int W = left0->width, H = left0->height;
+  if (W > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
+  const mpv_schedule dflt{};
+  const LevelWs lw = level_ws(p, W, H, nullptr, dflt);
+  if (!workspace || workspace_bytes < lw.total) return MPV_ERR_WORKSPACE;
+  uint8_t* ws = (uint8_t*)workspace;
+  st = run_level(p, left0->data, left0->pitch, right0->data, right0->pitch, W, H, nullptr, disp0,
+                 nullptr, raw0, ws, 0, dflt, stream);
+  if (st) return st;
+  const float Z = (float)(p->num_paths * (24 + p->lambda * tau_eff(p->tau, p->num_disp)));
+  mpvl::lb_features(ws + lw.part_off, (long long)H * W * lw.sc.capP, lw.sc.capP, p->num_paths,
+                    p->num_disp, W, H, raw0, disp0, left0->data, left0->pitch, Z, feat, stream);
+  return launched();
 }
 
 mpv_status mpv_set_timing_events(int32_t stage, int32_t level, hipEvent_t before, hipEvent_t after) {

@@ -17,15 +17,19 @@ def L():
 
 
 def header_functions():
-    text = open(os.path.join(ROOT, "include", "mpv.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mpv_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(mpv_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(L):
     names = header_functions()
     assert "mpv_pyramid" in names and "mpv_cost" in names and "mpv_aggregate" in names
-    assert "mpv_disparity" in names
+    assert "mpv_disparity" in names and "mpv_lb_conv" in names and "mpv_batch_run_graph" in names
     raw = C.CDLL(L.LIB_PATH)
     for n in names:
         assert hasattr(raw, n), n
