@@ -128,6 +128,49 @@ def batch_bench(params, levels, dev, steps):
             "schedule": sched.__dict__, "graph": True}
 
 
+def learned_bench(params, dev, steps, pairs):
+    """Learned band proposal (coarse level -> network -> per-pixel bands -> banded finest
+    level) on held-out seeded pairs of the same shape: fps with and without the per-frame
+    fallback, and bad-pixel rates against plain MPV and error rates against the ground truth
+    for plain, the fixed +/-4 pyramid and the learned bands."""
+    import torch
+    from paper_2001_09678_amd import learned
+    from paper_2001_09678_amd.scene import batch_scenes
+    if not os.path.exists(learned.DEFAULT_WEIGHTS):
+        return {"skipped": "no trained weights"}
+    net, meta = learned.BandNet.load(learned.DEFAULT_WEIGHTS)
+    W, H = 1280, 720
+    specs = learned.scene_specs(42000, pairs, W, H, params.num_disp)
+    sc = batch_scenes(specs[:1])[0]
+    left = torch.from_numpy(sc.left).to(dev)
+    right = torch.from_numpy(sc.right).to(dev)
+    m = learned.LearnedMatcher(net, params, W, H)
+    out = {}
+    for name, fb in (("banded", False), ("with_fallback", True)):
+        for _ in range(5):
+            m(left, right, allow_fallback=fb)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for i in range(steps):
+            m(left, right, allow_fallback=fb)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        ms = ev[0].elapsed_time(ev[steps]) / steps
+        out[name] = {"ms_per_step": round(ms, 4), "fps": round(1000.0 / ms, 1),
+                     "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4)}
+    m(left, right, allow_fallback=False)
+    d0 = -(-params.num_disp // 4)
+    evaluated = (W // 4) * (H // 4) * d0 + int(m.len.sum().item())
+    out["banded"]["mde_s_evaluated"] = round(evaluated / (out["banded"]["ms_per_step"] * 1e-3) / 1e6, 1)
+    out["banded"]["mean_band_width"] = round(int(m.len.sum().item()) / (W * H), 3)
+    out["quality"] = learned.evaluate(net, specs, params)
+    out["weights"] = {k: meta[k] for k in ("pairs", "first_seed", "steps", "batch", "lr", "beta") if k in meta}
+    out["held_out_pairs"] = pairs
+    return out
+
+
 def pct(vals, q):
     s = sorted(vals)
     k = min(len(s) - 1, max(0, int(round(q / 100.0 * (len(s) - 1)))))
@@ -165,6 +208,8 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-pairs", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -217,6 +262,7 @@ def main():
 
     breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
     batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
+    learned_res = {} if args.no_learned else learned_bench(params, dev, args.plain_steps, args.learned_pairs)
 
     result = {
         "metric": METRIC,
@@ -255,6 +301,7 @@ def main():
         "stage_ms": breakdown,
         "schedule": {"multiscale": sched.__dict__, "plain": psched.__dict__},
         "batch": batch,
+        "learned": learned_res,
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cfg)

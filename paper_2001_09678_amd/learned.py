@@ -129,18 +129,19 @@ class BandNet:
         self.pack()
 
     # ---- checkpoints (numpy .npz, no pickled objects)
-    def state(self, extra: dict | None = None) -> dict:
+    def state(self, extra: dict | None = None, weights_only: bool = False) -> dict:
         torch.cuda.synchronize()
-        st = {"params": self.params.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
-              "step": np.array([self.step], np.int64)}
+        st = {"params": self.params.cpu().numpy(), "step": np.array([self.step], np.int64)}
+        if not weights_only:
+            st["m"], st["v"] = self.m.cpu().numpy(), self.v.cpu().numpy()
         if extra:
             st["extra"] = np.frombuffer(json.dumps(extra).encode(), dtype=np.uint8)
         return st
 
-    def save(self, path: str, extra: dict | None = None):
+    def save(self, path: str, extra: dict | None = None, weights_only: bool = False):
         os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
         buf = io.BytesIO()
-        np.savez(buf, **self.state(extra))
+        np.savez(buf, **self.state(extra, weights_only))
         tmp = path + ".tmp"
         with open(tmp, "wb") as f:
             f.write(buf.getvalue())
@@ -150,10 +151,10 @@ class BandNet:
     def load(cls, path: str, device="cuda"):
         with np.load(path, allow_pickle=False) as z:
             net = cls(device, params=z["params"])
+            net.step = int(z["step"][0])
             if "m" in z:
                 net.m.copy_(torch.from_numpy(z["m"]))
                 net.v.copy_(torch.from_numpy(z["v"]))
-                net.step = int(z["step"][0])
             extra = json.loads(bytes(z["extra"]).decode()) if "extra" in z else {}
         return net, extra
 
@@ -245,6 +246,7 @@ class LearnedMatcher:
         self.disp = torch.empty((height, width), dtype=torch.int16, device=device)
         self.fallbacks = 0
         self.frames = 0
+        self.last_fallback = False
 
     def propose(self, left, right):
         l0, r0 = coarse_images(left, right, self.cfg.levels)
@@ -254,15 +256,19 @@ class LearnedMatcher:
         return o
 
     def __call__(self, left, right, allow_fallback=True):
+        """Disparity of one frame. With the fallback on, the low-confidence count is read back
+        (one small device-to-host copy) and decides between the banded and the full-range
+        finest level before either runs."""
         self.propose(left, right)
-        out = mpv.match(left, right, self.params, self.band, workspace=self.ws)
         self.frames += 1
         if allow_fallback:
             self.nlow_host.copy_(self.nlow, non_blocking=False)
             if self.nlow_host.item() > self.cfg.fallback_frac * self.w0 * self.h0:
                 self.fallbacks += 1
-                out = mpv.match(left, right, self.params, None, workspace=self.ws)
-        return out
+                self.last_fallback = True
+                return mpv.match(left, right, self.params, None, workspace=self.ws)
+        self.last_fallback = False
+        return mpv.match(left, right, self.params, self.band, workspace=self.ws)
 
 
 # ---------------------------------------------------------------------------------------
@@ -275,11 +281,12 @@ def scene_specs(first_seed: int, count: int, width=1280, height=720, num_disp=12
 
 
 class Dataset:
-    """Features, coarse winners and plain-MPV labels of a list of scenes, resident on the GPU."""
+    """Features, coarse winners and plain-MPV labels of a list of scenes, resident on the GPU.
+    Scenes are generated on the host in chunks (worker processes) and dropped once labelled."""
 
-    def __init__(self, specs, params: mpv.MPVParams, levels=3, device="cuda", workers=16, scenes=None):
-        from .scene import batch_scenes
-        scenes = batch_scenes(specs, workers=workers) if scenes is None else scenes
+    def __init__(self, specs, params: mpv.MPVParams, levels=3, device="cuda", workers=16, chunk=64,
+                 log=None):
+        from .scene import scene_chunks
         _, W, H, D, _ = specs[0]
         s = levels - 1
         self.W, self.H, self.hc, self.wc = W, H, H >> s, W >> s
@@ -292,22 +299,34 @@ class Dataset:
         self.feat = torch.empty((n, self.hc, self.wc, 8), dtype=torch.int16, device=device)
         self.raw0 = torch.empty((n, self.hc, self.wc), dtype=torch.int16, device=device)
         self.labels = torch.empty((n, H, W), dtype=torch.int16, device=device)
-        self.left, self.right = [], []
-        counts = np.zeros(n, np.int64)
-        for i, sc in enumerate(scenes):
-            L = torch.from_numpy(sc.left).to(device)
-            R = torch.from_numpy(sc.right).to(device)
-            self.left.append(L)
-            self.right.append(R)
-            l0, r0 = coarse_images(L, R, levels)
-            coarse(l0, r0, self.feat[i], self.raw0[i], torch.empty_like(self.raw0[i]))
-            self.labels[i].copy_(plain(L, R))
+        disp0 = torch.empty((self.hc, self.wc), dtype=torch.int16, device=device)
+        i = 0
+        for scenes in scene_chunks(specs, workers=workers, chunk=chunk):
+            for sc in scenes:
+                L = torch.from_numpy(sc.left).to(device)
+                R = torch.from_numpy(sc.right).to(device)
+                l0, r0 = coarse_images(L, R, levels)
+                coarse(l0, r0, self.feat[i], self.raw0[i], disp0)
+                self.labels[i].copy_(plain(L, R))
+                i += 1
+            if log:
+                log(f"dataset: {i}/{n} pairs labelled")
         torch.cuda.synchronize()
-        lab = self.labels.cpu().numpy()
-        covered = lab[:, : 4 * self.hc, : 4 * self.wc] >= 0
-        counts[:] = covered.reshape(n, -1).sum(axis=1)
-        self.counts = counts
+        covered = self.labels[:, : 4 * self.hc, : 4 * self.wc] >= 0
+        self.counts = covered.reshape(n, -1).sum(dim=1).cpu().numpy().astype(np.int64)
         self.n = n
+
+
+def dataset_loss(net: BandNet, data: Dataset, beta: float = 0.05, batch: int = 8) -> float:
+    """Mean loss over every labelled pixel of the dataset (forward only, fixed order)."""
+    total = 0.0
+    count = int(data.counts.sum())
+    for i in range(0, data.n, batch):
+        j = min(i + batch, data.n)
+        o, _ = net.forward(data.feat[i:j])
+        _, parts = loss(o, data.raw0[i:j], data.labels[i:j], beta, 1.0 / max(count, 1))
+        total += float(parts.double().sum().item())
+    return total
 
 
 def train(net: BandNet, data: Dataset, steps: int, batch: int = 8, lr: float = 2e-3, beta: float = 0.05,
@@ -336,3 +355,128 @@ def train(net: BandNet, data: Dataset, steps: int, batch: int = 8, lr: float = 2
         if ckpt and ckpt_every and (step + 1) % ckpt_every == 0:
             net.save(ckpt, {"step": step + 1, "rng": rng.bit_generator.state, "seed": seed})
     return history, rng.bit_generator.state
+
+
+# ---------------------------------------------------------------------------------------
+# Evaluation: learned bands vs the fixed +-radius pyramid vs plain full-range MPV
+# ---------------------------------------------------------------------------------------
+def compare_to_plain(disp, plain):
+    """Plain-valid pixels where `disp` is invalid, and where it is valid but more than 1 away."""
+    valid = plain >= 0
+    inv = valid & (disp < 0)
+    dif = valid & (disp >= 0) & ((disp.int() - plain.int()).abs() > 1)
+    return int(inv.sum()), int(dif.sum()), int(valid.sum())
+
+
+def gt_errors(disp, gt, occluded):
+    """Non-occluded pixels whose disparity is invalid or more than 1 from the ground truth."""
+    m = ~occluded
+    err = m & ((disp < 0) | ((disp.int() - gt.int()).abs() > 1))
+    return int(err.sum()), int(m.sum())
+
+
+def evaluate(net: BandNet, specs, params: mpv.MPVParams, cfg: LearnedConfig | None = None, workers=16,
+             radius=4, log=None):
+    """Bad-pixel rates against plain MPV (split into invalid / off by more than 1) and error
+    rates against the ground truth, for plain, the fixed-band pyramid, and learned bands with
+    and without the per-frame fallback."""
+    from .scene import scene_chunks
+    cfg = cfg or LearnedConfig()
+    _, W, H, _, _ = specs[0]
+    plain = mpv.Pyramid(params, W, H, levels=1)
+    fixed = mpv.Pyramid(params, W, H, levels=cfg.levels, radius=radius)
+    lm = LearnedMatcher(net, params, W, H, cfg)
+    names = ["plain", f"fixed_pm{radius}", "learned_banded", "learned"]
+    acc = {k: dict(inv=0, dif=0, valid=0, max_pair=0.0, gt_err=0, gt_n=0) for k in names}
+    frames = 0
+    for scenes in scene_chunks(specs, workers=workers, chunk=32):
+        for sc in scenes:
+            L = torch.from_numpy(sc.left).cuda()
+            R = torch.from_numpy(sc.right).cuda()
+            gt = torch.from_numpy(sc.disp).cuda()
+            occ = torch.from_numpy(sc.occluded).cuda()
+            ref = plain(L, R).clone()
+            banded = lm(L, R, allow_fallback=False).clone()
+            fb = lm.nlow_host.copy_(lm.nlow).item() > cfg.fallback_frac * lm.w0 * lm.h0
+            lm.fallbacks += int(fb)
+            outs = {"plain": ref, names[1]: fixed(L, R), "learned_banded": banded,
+                    "learned": ref if fb else banded}
+            for k, d in outs.items():
+                i, df, n = compare_to_plain(d, ref)
+                e, g = gt_errors(d, gt, occ)
+                a = acc[k]
+                a["inv"] += i
+                a["dif"] += df
+                a["valid"] += n
+                a["max_pair"] = max(a["max_pair"], (i + df) / max(n, 1))
+                a["gt_err"] += e
+                a["gt_n"] += g
+            frames += 1
+        if log:
+            log(f"evaluate: {frames}/{len(specs)} pairs")
+    res = {}
+    for k, a in acc.items():
+        res[k] = {"bad_vs_plain": (a["inv"] + a["dif"]) / max(a["valid"], 1),
+                  "invalid_vs_plain": a["inv"] / max(a["valid"], 1),
+                  "differ_vs_plain": a["dif"] / max(a["valid"], 1),
+                  "max_pair_bad_vs_plain": a["max_pair"],
+                  "err_gt": a["gt_err"] / max(a["gt_n"], 1)}
+    res["fallback_frac"] = lm.fallbacks / max(frames, 1)
+    res["pairs"] = frames
+    return res
+
+
+def _main(argv=None):
+    import argparse
+    import time
+    ap = argparse.ArgumentParser(description="Train the band-proposal network on seeded synthetic pairs "
+                                             "labelled by plain full-range MPV, then evaluate held-out pairs.")
+    ap.add_argument("--pairs", type=int, default=2000)
+    ap.add_argument("--first-seed", type=int, default=40000)
+    ap.add_argument("--eval-pairs", type=int, default=200)
+    ap.add_argument("--eval-seed", type=int, default=42000)
+    ap.add_argument("--width", type=int, default=1280)
+    ap.add_argument("--height", type=int, default=720)
+    ap.add_argument("--num-disp", type=int, default=128)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--beta", type=float, default=0.05)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--ckpt", default=None)
+    ap.add_argument("--resume", action="store_true")
+    ap.add_argument("--workers", type=int, default=16)
+    a = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    params = mpv.MPVParams(num_disp=a.num_disp, num_paths=8)
+    t0 = time.time()
+    specs = scene_specs(a.first_seed, a.pairs, a.width, a.height, a.num_disp)
+    data = Dataset(specs, params, workers=a.workers, log=log)
+    log(f"dataset ready in {time.time() - t0:.1f} s")
+    start, rng_state = 0, None
+    if a.resume and a.ckpt and os.path.exists(a.ckpt):
+        net, extra = BandNet.load(a.ckpt)
+        start, rng_state = extra["step"], extra["rng"]
+    else:
+        net = BandNet("cuda", seed=a.seed)
+    t1 = time.time()
+    hist, _ = train(net, data, a.steps, batch=a.batch, lr=a.lr, beta=a.beta, seed=a.seed, start_step=start,
+                    rng_state=rng_state, ckpt=a.ckpt, ckpt_every=500 if a.ckpt else 0, log_every=100, log=log)
+    torch.cuda.synchronize()
+    log(f"trained {a.steps - start} steps in {time.time() - t1:.1f} s")
+    meta = {"pairs": a.pairs, "first_seed": a.first_seed, "steps": a.steps, "batch": a.batch, "lr": a.lr,
+            "beta": a.beta, "seed": a.seed, "shape": [a.width, a.height, a.num_disp],
+            "loss_history": hist}
+    if a.eval_pairs:
+        del data
+        res = evaluate(net, scene_specs(a.eval_seed, a.eval_pairs, a.width, a.height, a.num_disp), params,
+                       workers=a.workers, log=log)
+        meta["eval"] = res
+        log(json.dumps(res, indent=1))
+    net.save(a.out, meta, weights_only=True)
+    log(f"saved {a.out}")
+
+
+if __name__ == "__main__":
+    _main()

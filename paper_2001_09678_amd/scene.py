@@ -190,6 +190,21 @@ def _spec_scene(spec):
     return make_scene(s, w, h, d - 1, k, ground=True)
 
 
+def scene_chunks(specs, workers: int = 0, chunk: int = 64):
+    """Yields the scenes of `specs` in order, `chunk` at a time (bounded host memory)."""
+    if workers <= 1:
+        for i in range(0, len(specs), chunk):
+            yield [_spec_scene(sp) for sp in specs[i:i + chunk]]
+        return
+    import concurrent.futures as cf
+    with cf.ProcessPoolExecutor(min(workers, len(specs))) as ex:
+        pending = [ex.submit(_spec_scene, sp) for sp in specs[:chunk]]
+        for i in range(0, len(specs), chunk):
+            nxt = [ex.submit(_spec_scene, sp) for sp in specs[i + chunk:i + 2 * chunk]]
+            yield [f.result() for f in pending]
+            pending = nxt
+
+
 def batch_scenes(specs, workers: int = 0):
     """Scenes of a list of specs, generated in parallel worker processes."""
     if workers <= 1 or len(specs) <= 1:
