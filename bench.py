@@ -171,6 +171,45 @@ def learned_bench(params, dev, steps, pairs):
     return out
 
 
+def serve_bench(seconds, per_rig=8, saturate=32):
+    """Frame-stream service: 8 rigs at 30 fps (shapes and ranges drawn by seed 5), HBM-budget
+    admission, continuous batching on 2 streams; latency is arrival to download complete,
+    host frames in pinned memory. Then the same rigs with every frame offered at once
+    (saturated) for the service's throughput ceiling."""
+    import torch
+    from paper_2001_09678_amd import serve
+    specs = serve.rig_specs(8, 5)
+    frames = serve.rig_frames(specs, per_rig, pinned=True)
+    ex = serve.GpuExecutor(streams=2)
+    budget = 16 << 30
+
+    def make(rid, rig, seq, t):
+        l, r = frames[rig][seq % per_rig]
+        return serve.Request(rid, rig, seq, specs[rig], l, r, t)
+
+    def once(sched, max_inflight):
+        server = serve.Server(ex, budget, max_inflight=max_inflight, max_batch=8)
+        t0 = time.perf_counter()
+        res = serve.run(server, sched, make)
+        span = time.perf_counter() - t0
+        out = serve.latency_summary(res, span)
+        out.update({"peak_hbm_bytes": server.pool.peak, "launches": server.launches,
+                    "mean_batch": round(sum(server.batch_sizes) / max(1, len(server.batch_sizes)), 2),
+                    "wall_s": round(span, 3)})
+        server.close()
+        return out
+
+    once([(0.0, r, 0) for r in range(8)], 16)  # warm-up: first allocation of every rig's slot
+    torch.cuda.synchronize()
+    paced = once(serve.arrivals(8, 30.0, seconds, seed=5), 32)
+    paced["offered_fps"] = 240
+    sat = once([(0.0, r, f) for f in range(saturate) for r in range(8)], 32)
+    return {"rigs": [[sp.width, sp.height, sp.num_disp] for sp in specs], "hbm_budget_bytes": budget,
+            "streams": 2, "paced_30fps": paced, "saturated": sat,
+            "fallback_fraction": None,
+            "note": "fixed +/-4 band pyramid per frame; learned bands are not used by the service"}
+
+
 def pct(vals, q):
     s = sorted(vals)
     k = min(len(s) - 1, max(0, int(round(q / 100.0 * (len(s) - 1)))))
@@ -209,6 +248,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--learned-pairs", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -263,6 +304,7 @@ def main():
     breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
     batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
     learned_res = {} if args.no_learned else learned_bench(params, dev, args.plain_steps, args.learned_pairs)
+    serve_res = {} if args.no_serve else serve_bench(args.serve_seconds)
 
     result = {
         "metric": METRIC,
@@ -302,6 +344,7 @@ def main():
         "schedule": {"multiscale": sched.__dict__, "plain": psched.__dict__},
         "batch": batch,
         "learned": learned_res,
+        "serve": serve_res,
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cfg)

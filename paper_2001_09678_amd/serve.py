@@ -1,0 +1,382 @@
+"""Frame-stream service: several camera rigs, HBM-budget admission, continuous batching.
+
+The counterpart of the paper's real-time pipeline (Section 3.7: frames captured and matched
+while the previous ones are still in flight), for many rigs sharing one GPU:
+
+* rigs deliver frames at a fixed rate (random phase, small jitter);
+* a FIFO admission queue admits the head frame while a slot for its shape fits in the HBM
+  budget (inputs, pyramid workspace and outputs of one in-flight frame; idle slots of other
+  shapes are evicted first) and fewer than `max_inflight` frames are in flight;
+* admitted frames are launched at once, round-robin over k streams: upload, multi-scale MPV,
+  download, each frame completing on its own event. A frame joins whenever a slot frees;
+  no frame waits for a whole batch to finish (continuous batching);
+* a request fails alone: an invalid shape or range, a request larger than the whole budget,
+  an error raised while launching it, or a deadline passed in the queue.
+
+Latency is arrival to the host seeing its download complete. The scheduler is written
+against an executor interface (bytes_needed / alloc / free / launch / done / collect) and a
+clock, so admission, batching, fault handling and latency bookkeeping also run on the CPU
+with a simulated executor and a virtual clock.
+"""
+from __future__ import annotations
+
+import time
+from collections import OrderedDict, deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = ["FrameSpec", "Request", "Result", "SlotPool", "Server", "rig_specs", "rig_frames", "arrivals", "run",
+           "GpuExecutor", "latency_summary"]
+
+RESOLUTIONS = [(640, 360), (1280, 720), (1920, 1080)]
+RANGES = [64, 128, 256]
+
+
+@dataclass(frozen=True)
+class FrameSpec:
+    width: int
+    height: int
+    num_disp: int
+
+
+@dataclass
+class Request:
+    rid: int
+    rig: int
+    seq: int
+    spec: FrameSpec
+    left: object          # host image (uint8 [H][W]); pinned for the GPU executor
+    right: object
+    t_arrival: float
+    deadline: float | None = None
+    inject: str | None = None  # fault injection for tests: "launch" makes the launch of this request raise
+
+
+@dataclass
+class Result:
+    rid: int
+    rig: int
+    seq: int
+    ok: bool
+    disp: object = None
+    error: str | None = None
+    t_arrival: float = 0.0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+class SlotPool:
+    """Device memory of in-flight frames, bounded by `budget` bytes. A slot belongs to one
+    frame shape and is reused by later frames of that shape; idle slots of other shapes are
+    freed (least recently used first) when a new one would not fit."""
+
+    def __init__(self, budget: int, bytes_fn, alloc_fn, free_fn):
+        self.budget = int(budget)
+        self.bytes_fn, self.alloc_fn, self.free_fn = bytes_fn, alloc_fn, free_fn
+        self.idle: OrderedDict[int, tuple] = OrderedDict()  # id -> (spec, slot, bytes)
+        self.held = 0          # bytes of all slots, idle or busy
+        self.busy = 0          # bytes of busy slots
+        self.peak = 0
+        self._next = 0
+
+    def acquire(self, spec: FrameSpec):
+        need = self.bytes_fn(spec)
+        for k, (s, slot, b) in self.idle.items():
+            if s == spec:
+                del self.idle[k]
+                self.busy += b
+                return slot, b
+        # free idle slots (other shapes) until the new one fits
+        while self.held + need > self.budget and self.idle:
+            _, (s, slot, b) = self.idle.popitem(last=False)
+            self.free_fn(slot)
+            self.held -= b
+        if self.held + need > self.budget:
+            return None
+        slot = self.alloc_fn(spec)
+        self.held += need
+        self.busy += need
+        self.peak = max(self.peak, self.held)
+        return slot, need
+
+    def release(self, spec: FrameSpec, slot, nbytes: int):
+        self.busy -= nbytes
+        self._next += 1
+        self.idle[self._next] = (spec, slot, nbytes)
+
+    def close(self):
+        for _, (s, slot, b) in list(self.idle.items()):
+            self.free_fn(slot)
+            self.held -= b
+        self.idle.clear()
+
+
+class Server:
+    """Admission queue + continuous batching over an executor."""
+
+    def __init__(self, executor, budget: int, max_inflight: int = 16, max_batch: int = 8,
+                 clock=time.perf_counter):
+        self.ex = executor
+        self.clock = clock
+        self.pool = SlotPool(budget, executor.bytes_needed, executor.alloc, executor.free)
+        self.max_inflight, self.max_batch = max_inflight, max_batch
+        self.queue: deque[Request] = deque()
+        self.inflight: list = []   # (ticket, request, slot, bytes, t_admit)
+        self.results: list[Result] = []
+        self.launches = 0
+        self.batch_sizes: list[int] = []
+        self.max_busy = 0
+
+    def offer(self, req: Request):
+        self.queue.append(req)
+
+    def _fail(self, req: Request, why: str, now: float, t_admit: float = 0.0):
+        self.results.append(Result(req.rid, req.rig, req.seq, False, None, why, req.t_arrival, t_admit, now))
+
+    def pending(self) -> int:
+        return len(self.queue) + len(self.inflight)
+
+    def step(self):
+        """Collect finished frames, then admit and launch what fits. Returns the number of
+        frames completed in this step."""
+        now = self.clock()
+        done = 0
+        still = []
+        for item in self.inflight:
+            ticket, req, slot, nb, t_admit = item
+            if self.ex.done(ticket):
+                out = self.ex.collect(ticket)
+                t = self.clock()
+                if isinstance(out, Exception):
+                    self._fail(req, f"{type(out).__name__}: {out}", t, t_admit)
+                else:
+                    self.results.append(Result(req.rid, req.rig, req.seq, True, out, None, req.t_arrival, t_admit, t))
+                self.pool.release(req.spec, slot, nb)
+                done += 1
+            else:
+                still.append(item)
+        self.inflight = still
+        # admission: FIFO, the head waits until it fits
+        batch = []
+        now = self.clock()
+        while self.queue and len(self.inflight) + len(batch) < self.max_inflight and len(batch) < self.max_batch:
+            req = self.queue[0]
+            if req.deadline is not None and now > req.deadline:
+                self.queue.popleft()
+                self._fail(req, "expired in queue", now)
+                continue
+            need = self.ex.bytes_needed(req.spec)
+            if need <= 0:
+                self.queue.popleft()
+                self._fail(req, "invalid frame shape or disparity range", now)
+                continue
+            if need > self.pool.budget:
+                self.queue.popleft()
+                self._fail(req, "frame does not fit in the HBM budget", now)
+                continue
+            got = self.pool.acquire(req.spec)
+            if got is None:
+                break
+            self.queue.popleft()
+            batch.append((req, got[0], got[1]))
+        self.max_busy = max(self.max_busy, self.pool.busy)
+        if batch:
+            tickets = self.ex.launch([(r, s) for r, s, _ in batch])
+            t_admit = self.clock()
+            self.launches += 1
+            self.batch_sizes.append(len(batch))
+            for (req, slot, nb), tk in zip(batch, tickets):
+                self.inflight.append((tk, req, slot, nb, t_admit))
+        return done
+
+    def close(self):
+        self.pool.close()
+
+
+# ---------------------------------------------------------------------------------------
+# Rigs and the driving loop
+# ---------------------------------------------------------------------------------------
+def rig_specs(n_rigs: int = 8, seed: int = 5):
+    """Per-rig (resolution, disparity range), drawn by `seed`."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    res = rng.integers(0, len(RESOLUTIONS), n_rigs)
+    rngs = rng.integers(0, len(RANGES), n_rigs)
+    return [FrameSpec(*RESOLUTIONS[a], RANGES[b]) for a, b in zip(res, rngs)]
+
+
+def rig_frames(specs, per_rig: int, seed: int = 5, workers: int = 16, pinned: bool = False):
+    """Pre-generated frames of each rig (seeds seed*10^6 + rig*10^5 + f), cycled by the rigs."""
+    from .scene import batch_scenes
+    flat = [(seed * 10**6 + r * 10**5 + f, sp.width, sp.height, sp.num_disp, 30)
+            for r, sp in enumerate(specs) for f in range(per_rig)]
+    scenes = batch_scenes(flat, workers=workers)
+    out = []
+    for r in range(len(specs)):
+        frames = []
+        for sc in scenes[r * per_rig:(r + 1) * per_rig]:
+            l, rr = sc.left, sc.right
+            if pinned:
+                import torch
+                l = torch.from_numpy(l).pin_memory()
+                rr = torch.from_numpy(rr).pin_memory()
+            frames.append((l, rr))
+        out.append(frames)
+    return out
+
+
+def arrivals(n_rigs: int, fps: float, duration: float, seed: int = 5, jitter: float = 1e-3):
+    """Sorted (t, rig, seq): rig r delivers frame f at phase_r + f/fps + U(-jitter, jitter)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1])))
+    out = []
+    period = 1.0 / fps
+    for r in range(n_rigs):
+        phase = rng.uniform(0, period)
+        n = int(np.floor((duration - phase) / period)) + 1 if duration > phase else 0
+        t = phase + np.arange(n) * period + rng.uniform(-jitter, jitter, n)
+        out += [(max(0.0, float(x)), r, f) for f, x in enumerate(t)]
+    out.sort()
+    return out
+
+
+def run(server: Server, schedule, make_request, clock=time.perf_counter, wait=None, deadline_s=None):
+    """Offers each scheduled frame at its time (relative to the start) and steps the server
+    until every frame has a result. `wait(t)` idles until absolute clock time t (default:
+    short sleeps); a virtual clock passes its own."""
+    t0 = clock()
+    i = 0
+    n = len(schedule)
+    rid = 0
+    while i < n or server.pending():
+        now = clock() - t0
+        while i < n and schedule[i][0] <= now:
+            t, rig, seq = schedule[i]
+            req = make_request(rid, rig, seq, t0 + t)
+            if deadline_s is not None:
+                req.deadline = t0 + t + deadline_s
+            server.offer(req)
+            rid += 1
+            i += 1
+        server.step()
+        nxt = t0 + schedule[i][0] if i < n else None
+        if wait is not None:
+            wait(nxt)
+        elif server.inflight or nxt is None:
+            time.sleep(0.0002)
+        else:
+            time.sleep(max(0.0, min(0.0005, nxt - clock())))
+    return server.results
+
+
+def latency_summary(results, t_span: float | None = None):
+    ok = [r for r in results if r.ok]
+    lat = np.array([r.latency * 1e3 for r in ok]) if ok else np.zeros(1)
+    out = {"frames": len(results), "ok": len(ok), "failed": len(results) - len(ok),
+           "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+           "max_ms": round(float(lat.max()), 4)}
+    if t_span:
+        out["frames_per_s"] = round(len(ok) / t_span, 1)
+    return out
+
+
+# ---------------------------------------------------------------------------------------
+# GPU executor: one multi-scale matcher (HIP library) per slot
+# ---------------------------------------------------------------------------------------
+@dataclass
+class _Slot:
+    spec: FrameSpec
+    left: object
+    right: object
+    matcher: object
+    host_out: object
+    event: object = None
+    extra: dict = field(default_factory=dict)
+
+
+class GpuExecutor:
+    """Uploads, matches (multi-scale MPV, fixed +/-radius bands) and downloads each frame on
+    one of `streams` HIP streams; a frame is done when its own event has completed."""
+
+    def __init__(self, levels: int = 3, radius: int = 4, num_paths: int = 8, streams: int = 2,
+                 device="cuda", sched=None):
+        import torch
+        from . import _lib
+        _lib.lib()  # the HIP library is required; there is no other path
+        self.torch = torch
+        self.levels, self.radius, self.num_paths = levels, radius, num_paths
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self.k = 0
+        self.sched = sched
+        self._bytes: dict = {}
+
+    def params(self, spec: FrameSpec):
+        from . import mpv
+        return mpv.MPVParams(num_disp=spec.num_disp, num_paths=self.num_paths)
+
+    def levels_for(self, spec: FrameSpec) -> int:
+        return self.levels
+
+    def bytes_needed(self, spec: FrameSpec) -> int:
+        if spec in self._bytes:
+            return self._bytes[spec]
+        from . import mpv
+        from ._lib import MPVError
+        try:
+            ws = mpv.pyramid_workspace_bytes(self.params(spec), self.levels_for(spec), self.radius,
+                                             spec.width, spec.height, self.sched)
+        except (MPVError, ValueError):
+            ws = 0
+        if ws <= 0:
+            self._bytes[spec] = 0
+            return 0
+        W, H = spec.width, spec.height
+        total = int(ws) + 2 * W * H + 3 * 2 * W * H  # workspace, both views, disp/raw/right maps
+        self._bytes[spec] = total
+        return total
+
+    def alloc(self, spec: FrameSpec):
+        from . import mpv
+        torch = self.torch
+        W, H = spec.width, spec.height
+        m = mpv.Pyramid(self.params(spec), W, H, levels=self.levels_for(spec), radius=self.radius,
+                        device=self.device, sched=self.sched)
+        return _Slot(spec, torch.empty((H, W), dtype=torch.uint8, device=self.device),
+                     torch.empty((H, W), dtype=torch.uint8, device=self.device), m,
+                     torch.empty((H, W), dtype=torch.int16, pin_memory=True), torch.cuda.Event())
+
+    def free(self, slot: _Slot):
+        slot.matcher = None
+        slot.left = slot.right = None
+
+    def launch(self, items):
+        torch = self.torch
+        s = self.streams[self.k % len(self.streams)]
+        self.k += 1
+        tickets = []
+        with torch.cuda.stream(s):
+            for req, slot in items:
+                try:
+                    if req.inject == "launch":
+                        raise RuntimeError("injected launch fault")
+                    slot.left.copy_(req.left, non_blocking=True)
+                    slot.right.copy_(req.right, non_blocking=True)
+                    out = slot.matcher(slot.left, slot.right)
+                    slot.host_out.copy_(out, non_blocking=True)
+                    slot.event.record(s)
+                    tickets.append(slot)
+                except Exception as e:  # the failing request only
+                    tickets.append(e)
+        return tickets
+
+    def done(self, ticket) -> bool:
+        return isinstance(ticket, Exception) or ticket.event.query()
+
+    def collect(self, ticket):
+        if isinstance(ticket, Exception):
+            return ticket
+        return ticket.host_out.numpy().copy()
