@@ -176,6 +176,9 @@ __device__ __forceinline__ int wave_unit() {
   return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
 }
 
+// True when `c` holds in every lane of the wave (all lanes active).
+__device__ __forceinline__ bool wave_all(bool c) { return __builtin_amdgcn_ballot_w64(!c) == 0; }
+
 __device__ __forceinline__ int num_lines(int r, int W, int H) {
   return c_dy[r] == 0 ? H : (c_dx[r] == 0 ? W : W + H - 1);
 }
@@ -228,7 +231,7 @@ __device__ __forceinline__ void block_line(const ScanArgs& a, int b, int& r, int
   r = a.dir[ri];
   ln.dx = c_dx[r];
   ln.dy = c_dy[r];
-  const int g = lane_id() / LPL;
+  const int g = LPL == 64 ? 0 : lane_id() / LPL;  // 64-lane groups: wave-uniform line data
   const int line = (b - a.gprefix[ri]) * (64 / LPL) + g;
   if (line < num_lines(r, a.W, a.H)) {
     line_info(r, line, a.W, a.H, ln.x0, ln.y0, ln.n);
@@ -550,7 +553,7 @@ __device__ __forceinline__ void export_canonical(void* agg, size_t idx, uint32_t
 template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
 __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, int unit) {
   const int lane = lane_id();
-  const int l = lane % LPL;
+  const int l = LPL == 64 ? lane : lane % LPL;
   const int kk = l % CHUNK;
   int r, ri, nmax;
   Line ln;
@@ -562,19 +565,28 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, int unit) {
   for (int k = 0; k < K; ++k) P[k] = 0;
   uint32_t acc = 0;  // canonical offset: sum of the minima subtracted so far
   uint8_t* part = a.part + (long long)(a.dir_base + ri) * a.part_stride;
-  const uint32_t sink = (uint32_t)((a.npd - a.dir_base - ri) * a.part_stride);
+  uint8_t* const sinkp = a.part + (long long)a.npd * a.part_stride;  // 256 B behind the volumes
+  const rsrc_t rpart = make_rsrc(part);
 
-  uint32_t ring[PREFETCH][2 * K];  // right census of the lane's 2K candidates
-  uint32_t bw[PREFETCH];           // broadcast step words
-  int bl[PREFETCH];                // broadcast band lengths
-  auto fetch = [&](int t, uint32_t (&dst)[2 * K]) {
+  // The lane's NC candidates d0l .. d0l+NC-1 sit at census offsets c-d0l-NC+1 .. c-d0l:
+  // element i of a fetch is the right census of d = d0l + NC-1-i. For 64-lane groups c is
+  // wave-uniform, so the base is scalar and the lane offset a constant.
+  constexpr int NC = 2 * K, SPAN = 2 * LPL * K;
+  const int d0l = 2 * l * K;
+  const uint32_t loff = (uint32_t)(SPAN - d0l - NC) << 2;
+  uint32_t ring[PREFETCH][NC];  // right census of the lane's NC candidates
+  uint32_t bw[PREFETCH];        // broadcast step words
+  int bl[PREFETCH];             // broadcast band lengths
+  const rsrc_t rcr = make_rsrc(a.cr);
+  auto fetch_c = [&](uint32_t c, uint32_t (&dst)[NC]) {
     if constexpr (SRC == SRC_CENSUS) {
-      const uint32_t c = la.cen(t);
+      // c >= census margin > SPAN, so every offset below is non-negative
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const uint32_t d0 = 2 * (l * K + k);
-        dst[2 * k] = ld_u32(a.cr, c - d0);
-        dst[2 * k + 1] = ld_u32(a.cr, c - d0 - 1);
+      for (int i = 0; i < NC; ++i) {
+        if constexpr (LPL == 64)
+          dst[i] = buf_ld32(rcr, loff + 4 * i, (c - (uint32_t)(SPAN - 1)) << 2);
+        else
+          dst[i] = buf_ld32(rcr, ((c - (uint32_t)(d0l + NC - 1)) << 2) + 4 * i, 0u);
       }
     }
   };
@@ -583,120 +595,165 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, int unit) {
     constexpr int q = decltype(qc)::value;
     bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
     if constexpr (BANDED) bl[q] = group_bcast<LPL, q>((int)cur.y);
-    fetch(q, ring[q]);
+    fetch_c(la.cen(q), ring[q]);
   });
-
-  for (int t0 = 0; t0 < nmax; t0 += CHUNK) {
-    const uint2 nxt = load_chunk<BANDED, SRC>(a, la, t0 + CHUNK, kk);
-    static_for<CHUNK>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      constexpr int slot = k % PREFETCH;
-      const int t = t0 + k;
-      const int tt = la.tt(t);
-      const int x = la.x0 + tt * la.dx;
-      const uint32_t p = la.pix(t);
-      const uint32_t w = bw[slot];
-      const int b0 = BANDED ? (int)(w >> 24) : 0;
-      const int bn = BANDED ? bl[slot] : a.D;
-      uint32_t cr[2 * K];
+  // loop-invariant masks: halves for d >= D are absent nodes (unbanded path)
+  uint32_t dmask[K];
 #pragma unroll
-      for (int q = 0; q < 2 * K; ++q) cr[q] = ring[slot][q];
-      {  // step t + PREFETCH: broadcast its word and issue its census loads
-        constexpr int kn = (k + PREFETCH) % CHUNK;
-        const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
-        bw[slot] = (uint32_t)group_bcast<LPL, kn>((int)src.x);
-        if constexpr (BANDED) bl[slot] = group_bcast<LPL, kn>((int)src.y);
-        fetch(t + PREFETCH, ring[slot]);
+  for (int q = 0; q < K; ++q) {
+    const int d0 = d0l + 2 * q;
+    dmask[q] = (d0 < a.D ? 0u : INF16) | ((d0 + 1 < a.D ? 0u : INF16) << 16);
+  }
+  const uint32_t pstep = (uint32_t)(la.dp * a.capP);
+
+  // One step. FAST: the whole chunk and its prefetches lie inside every line of the wave and
+  // every candidate has x - d >= 0, so offsets run incrementally with no clamps or border tests.
+  auto step = [&](auto kc, auto fc, const uint2& nxt, int t0, uint32_t pst, uint32_t cpf) {
+    constexpr int k = decltype(kc)::value;
+    constexpr bool FAST = decltype(fc)::value;
+    constexpr int slot = k % PREFETCH;
+    const int t = t0 + k;
+    const uint32_t w = bw[slot];
+    const int b0 = BANDED ? (int)(w >> 24) : 0;
+    const int bn = BANDED ? bl[slot] : a.D;
+    uint32_t cr[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) cr[q] = ring[slot][q];
+    {  // step t + PREFETCH: broadcast its word and issue its census loads
+      constexpr int kn = (k + PREFETCH) % CHUNK;
+      const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
+      bw[slot] = (uint32_t)group_bcast<LPL, kn>((int)src.x);
+      if constexpr (BANDED) bl[slot] = group_bcast<LPL, kn>((int)src.y);
+      fetch_c(FAST ? cpf : la.cen(t + PREFETCH), ring[slot]);
+    }
+    // ---- matching cost of this pixel, two disparities per pair
+    uint32_t C[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int d0 = d0l + 2 * q;
+      uint32_t c0, c1;
+      if constexpr (SRC == SRC_CENSUS) {
+        const uint32_t cl = w & 0xFFFFFFu;
+        c0 = (uint32_t)__popc(cl ^ cr[NC - 1 - 2 * q]);
+        c1 = (uint32_t)__popc(cl ^ cr[NC - 2 - 2 * q]);
+        if constexpr (!FAST) {
+          const int x = la.x0 + la.tt(t) * la.dx;
+          c0 = (x - d0 >= 0) ? c0 : 24u;
+          c1 = (x - d0 - 1 >= 0) ? c1 : 24u;
+        }
+      } else {
+        const uint8_t* cp = a.cost + (size_t)la.pix(t) * a.cap;
+        const int j0 = min(max(d0 - b0, 0), a.cap - 1), j1 = min(max(d0 + 1 - b0, 0), a.cap - 1);
+        c0 = cp[j0];
+        c1 = cp[j1];
       }
-      // ---- matching cost of this pixel, two disparities per pair
-      uint32_t C[K];
+      if constexpr (BANDED) {
+        const bool in0 = d0 < a.D && d0 >= b0 && d0 < b0 + bn;
+        const bool in1 = d0 + 1 < a.D && d0 + 1 >= b0 && d0 + 1 < b0 + bn;
+        C[q] = (in0 ? c0 : INF16) | ((in1 ? c1 : INF16) << 16);
+      } else {
+        C[q] = pk_max(c0 | (c1 << 16), dmask[q]);
+      }
+    }
+    // ---- transition: min over predecessors of P(d') + lambda*min(|d-d'|, tau),
+    //      then normalise by the minimum over the line's disparities
+    uint32_t L[K];
+    uint32_t m;
+    if constexpr (TAU > 0) {
+      // complement encoding (u = INF16 - value per half, absent <= 0): max instead of min
+      uint32_t E[K];
+      pair_envelope_c<LPL, K, TAU>(P, E, a.lambda);
+      const uint32_t cap = t == 0 ? INF2 : splat16(INF16 - lt);
+      int mu = -32768;
 #pragma unroll
       for (int q = 0; q < K; ++q) {
-        const int d0 = 2 * (l * K + q);
-        uint32_t c0, c1;
-        if constexpr (SRC == SRC_CENSUS) {
-          const uint32_t cl = w & 0xFFFFFFu;
-          c0 = (x - d0 >= 0) ? (uint32_t)__popc(cl ^ cr[2 * q]) : 24u;
-          c1 = (x - d0 - 1 >= 0) ? (uint32_t)__popc(cl ^ cr[2 * q + 1]) : 24u;
-        } else {
-          const uint8_t* cp = a.cost + (size_t)p * a.cap;
-          const int j0 = min(max(d0 - b0, 0), a.cap - 1), j1 = min(max(d0 + 1 - b0, 0), a.cap - 1);
-          c0 = cp[j0];
-          c1 = cp[j1];
-        }
-        const bool in0 = d0 < a.D && (!BANDED || (d0 >= b0 && d0 < b0 + bn));
-        const bool in1 = d0 + 1 < a.D && (!BANDED || (d0 + 1 >= b0 && d0 + 1 < b0 + bn));
-        C[q] = (in0 ? c0 : INF16) | ((in1 ? c1 : INF16) << 16);
+        L[q] = pk_sub_i(pk_max_i(E[q], cap), C[q]);
+        mu = max(mu, max(lo16s(L[q]), hi16s(L[q])));
       }
-      // ---- transition: min over predecessors of P(d') + lambda*min(|d-d'|, tau),
-      //      then normalise by the minimum over the line's disparities
-      uint32_t L[K];
-      uint32_t m;
-      if constexpr (TAU > 0) {
-        // complement encoding (u = INF16 - value per half, absent <= 0): max instead of min
-        uint32_t E[K];
-        pair_envelope_c<LPL, K, TAU>(P, E, a.lambda);
-        const uint32_t cap = t == 0 ? INF2 : splat16(INF16 - lt);
-        int mu = -32768;
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-          L[q] = pk_sub_i(pk_max_i(E[q], cap), C[q]);
-          mu = max(mu, max(lo16s(L[q]), hi16s(L[q])));
-        }
+      if constexpr (LPL == 64)
+        mu = wave_max_s(mu);  // scalar: the splats below are scalar too
+      else
         mu = group_max<LPL>(mu);
-        m = INF16 - (uint32_t)mu;
-        const uint32_t off = splat16(m);
+      m = INF16 - (uint32_t)mu;
+      const uint32_t off = splat16(m);
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-          P[q] = pk_add_i(L[q], off);              // next state, complement encoded
-          L[q] = pk_sub_i(INF2, L[q]);             // energies relative to the previous minimum
-        }
-      } else {
-        uint32_t E[K];
-        pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda);
-        const uint32_t mcap = t == 0 ? 0u : splat16(lt);  // the first pixel has no predecessor
-#pragma unroll
-        for (int q = 0; q < K; ++q) L[q] = pk_add(C[q], pk_min(E[q], mcap));
-        m = min(lo16(L[0]), hi16(L[0]));
-#pragma unroll
-        for (int q = 1; q < K; ++q) m = min(m, min(lo16(L[q]), hi16(L[q])));
-        m = group_min<LPL>(m);
-#pragma unroll
-        for (int q = 0; q < K; ++q) P[q] = pk_sub(L[q], splat16(m));
+      for (int q = 0; q < K; ++q) {
+        P[q] = pk_add_i(L[q], off);              // next state, complement encoded
+        L[q] = pk_sub_i(INF2, L[q]);             // energies relative to the previous minimum
       }
-      // ---- outputs
-      if constexpr (OUT == OUT_PART) {
+    } else {
+      uint32_t E[K];
+      pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda);
+      const uint32_t mcap = t == 0 ? 0u : splat16(lt);  // the first pixel has no predecessor
+#pragma unroll
+      for (int q = 0; q < K; ++q) L[q] = pk_add(C[q], pk_min(E[q], mcap));
+      m = min(lo16(L[0]), hi16(L[0]));
+#pragma unroll
+      for (int q = 1; q < K; ++q) m = min(m, min(lo16(L[q]), hi16(L[q])));
+      m = group_min<LPL>(m);
+#pragma unroll
+      for (int q = 0; q < K; ++q) P[q] = pk_sub(L[q], splat16(m));
+    }
+    // ---- outputs
+    if constexpr (OUT == OUT_PART) {
+      // past the line's end the store goes to a sink behind the last direction's volume
+      uint32_t v = 0;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const uint32_t nq = TAU > 0 ? pk_sub(L[q], splat16(m)) : P[q];  // L - min, >= 0
+        const uint32_t c = pk_min(nq, 0x00FF00FFu);
+        v |= __builtin_amdgcn_perm(0u, c, 0x0c0c0200u) << (16 * q);
+      }
+      if constexpr (FAST) {
+        // pst is wave-uniform for 64-lane groups: scalar offset, constant lane offset
+        const uint32_t vo = LPL == 64 ? 2 * l * K : pst + 2 * l * K, so = LPL == 64 ? pst : 0u;
+        if constexpr (K == 1)
+          __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, rpart, (int)vo, (int)so, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b32(v, rpart, (int)vo, (int)so, 0);
+      } else {
         // past the line's end the store goes to a sink behind the last direction's volume
-        uint8_t* dst = part + (t < la.n ? p * (uint32_t)a.capP + 2 * l * K : sink + 4 * lane);
-        uint32_t v = 0;
+        uint8_t* dst = t < la.n ? part + la.pix(t) * (uint32_t)a.capP + 2 * l * K : sinkp + 4 * lane;
+        if constexpr (K == 1)
+          *(uint16_t*)dst = (uint16_t)v;
+        else
+          *(uint32_t*)dst = v;
+      }
+    } else {
+      if (t < la.n) {
+        const uint32_t p = la.pix(t);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-          const uint32_t nq = TAU > 0 ? pk_sub(L[q], splat16(m)) : P[q];  // L - min, >= 0
-          const uint32_t c = pk_min(nq, 0x00FF00FFu);
-          v |= ((c & 0xFFu) | ((c >> 8) & 0xFF00u)) << (16 * q);
-        }
-        if constexpr (K == 1) {
-          *(uint16_t*)dst = (uint16_t)v;
-        } else {
-          *(uint32_t*)dst = v;
-        }
-      } else {
-        if (t < la.n) {
 #pragma unroll
-          for (int q = 0; q < K; ++q) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int d = 2 * (l * K + q) + h;
-              const int j = d - b0;
-              if (d < a.D && j >= 0 && j < bn)
-                export_canonical<OUT>(a.agg, (size_t)p * a.cap + j, (h ? hi16(L[q]) : lo16(L[q])) + acc,
-                                      a.first);
-            }
+          for (int h = 0; h < 2; ++h) {
+            const int d = d0l + 2 * q + h;
+            const int j = d - b0;
+            if (d < a.D && j >= 0 && j < bn)
+              export_canonical<OUT>(a.agg, (size_t)p * a.cap + j, (h ? hi16(L[q]) : lo16(L[q])) + acc,
+                                    a.first);
           }
         }
       }
-      acc += m;
-    });
+    }
+    acc += m;
+  };
+
+  for (int t0 = 0; t0 < nmax; t0 += CHUNK) {
+    const uint2 nxt = load_chunk<BANDED, SRC>(a, la, t0 + CHUNK, kk);
+    const int xa = la.x0 + t0 * la.dx, xb = xa + (CHUNK - 1) * la.dx;
+    const bool fast = wave_all(t0 + CHUNK + PREFETCH <= la.n &&
+                               (SRC != SRC_CENSUS || min(xa, xb) >= a.D - 1));
+    if (fast) {
+      uint32_t pst = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;
+      uint32_t cpf = (uint32_t)(la.c0 + (t0 + PREFETCH) * la.dc);
+      static_for<CHUNK>([&](auto kc) {
+        step(kc, std::true_type{}, nxt, t0, pst, cpf);
+        pst += pstep;
+        cpf += (uint32_t)la.dc;
+      });
+    } else {
+      static_for<CHUNK>([&](auto kc) { step(kc, std::false_type{}, nxt, t0, 0u, 0u); });
+    }
     cur = nxt;
   }
 }
@@ -709,7 +766,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, int unit) {
 template <int LPL, int SRC, int OUT, int TAU, bool VAR>
 __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, int unit) {
   const int lane = lane_id();
-  const int j = lane % LPL;
+  const int j = LPL == 64 ? lane : lane % LPL;
   const int kk = j % CHUNK;
   const int gbase = lane - j;
   int r, ri, nmax;
@@ -723,15 +780,24 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, int unit) {
   int lo_prev = 0;
   uint32_t acc = 0;
   uint8_t* part = a.part + (long long)(a.dir_base + ri) * a.part_stride;
-  const uint32_t sink = (uint32_t)((a.npd - a.dir_base - ri) * a.part_stride);
+  uint8_t* const sinkp = a.part + (long long)a.npd * a.part_stride;  // 256 B behind the volumes
+  const rsrc_t rpart = make_rsrc(part);
+  const rsrc_t rcr = make_rsrc(a.cr);
 
   uint32_t ring[PREFETCH];  // right census of this lane's candidate
   uint32_t bw[PREFETCH];    // broadcast step words (left census | band start << 24)
   int bl[PREFETCH];         // broadcast band lengths
-  auto fetch = [&](int t, uint32_t w) -> uint32_t {
+  // Right census of candidate d = b0 + j at census offset c: the census margin (at least
+  // D + 64 words left of x = 0) keeps c - b0 - j in bounds for every lane (b0 <= D-1).
+  // For 64-lane groups c and b0 are wave-uniform: scalar base, constant lane offset.
+  const uint32_t loff = (uint32_t)(LPL - 1 - j) << 2;
+  auto fetch_c = [&](uint32_t c, uint32_t w) -> uint32_t {
     if constexpr (SRC == SRC_CENSUS) {
-      const int b0 = (int)(w >> 24);
-      return ld_u32(a.cr, la.cen(t) - (uint32_t)min(b0 + j, a.D));  // stays within the margin
+      const uint32_t b0 = w >> 24;
+      if constexpr (LPL == 64)
+        return buf_ld32(rcr, loff, (c - b0 - (uint32_t)(LPL - 1)) << 2);
+      else
+        return buf_ld32(rcr, (c - b0 - (uint32_t)j) << 2, 0u);
     } else {
       return 0u;
     }
@@ -741,69 +807,97 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, int unit) {
     constexpr int q = decltype(qc)::value;
     bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
     if constexpr (VAR) bl[q] = group_bcast<LPL, q>((int)cur.y);
-    ring[q] = fetch(q, bw[q]);
+    ring[q] = fetch_c(la.cen(q), bw[q]);
   });
+  const uint32_t pstep = (uint32_t)(la.dp * a.capP);
+
+  // One step; FAST as in the full-range scan (no clamps, no border test, no sink).
+  auto step = [&](auto kc, auto fc, const uint2& nxt, int t0, uint32_t pst, uint32_t cpf) {
+    constexpr int k = decltype(kc)::value;
+    constexpr bool FAST = decltype(fc)::value;
+    constexpr int slot = k % PREFETCH;
+    const int t = t0 + k;
+    const uint32_t w = bw[slot];
+    const int b0 = (int)(w >> 24);
+    const int bn = VAR ? bl[slot] : a.cap;
+    const uint32_t crv = ring[slot];
+    {  // step t + PREFETCH: broadcast its word and issue its census load
+      constexpr int kn = (k + PREFETCH) % CHUNK;
+      const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
+      const uint32_t wn = (uint32_t)group_bcast<LPL, kn>((int)src.x);
+      if constexpr (VAR) bl[slot] = group_bcast<LPL, kn>((int)src.y);
+      bw[slot] = wn;
+      ring[slot] = fetch_c(FAST ? cpf : la.cen(t + PREFETCH), wn);
+    }
+    uint32_t C;
+    if constexpr (SRC == SRC_CENSUS) {
+      uint32_t pc = (uint32_t)__popc((w & 0xFFFFFFu) ^ crv);
+      if constexpr (!FAST) {
+        const int x = la.x0 + la.tt(t) * la.dx;
+        pc = (x - b0 - j >= 0) ? pc : 24u;
+      }
+      C = pc + ((j < bn) ? 0u : INF32);
+    } else {
+      C = (j < bn) ? (uint32_t)a.cost[(size_t)la.pix(t) * a.cap + min(j, a.cap - 1)] : INF32;
+    }
+    uint32_t L, m;
+    const int src = j + (b0 - lo_prev) + e;
+    if constexpr (TAU > 0) {
+      // complement encoding: Pu = INF32 - P (absent 0), larger is better
+      const int E = band_envelope_c<LPL, TAU>(Pu, a.lambda);  // lane i <-> position i - e
+      const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
+      const int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
+      const int Mu = t == 0 ? (int)INF32 : max(Ev, (int)(INF32 - lt));
+      const int Lu = (j < bn) ? Mu - (int)C : 0;
+      int mu;
+      if constexpr (LPL == 64)
+        mu = wave_max_s(Lu);
+      else
+        mu = group_max<LPL>(Lu);
+      L = (j < bn) ? INF32 - (uint32_t)Lu : INF32;
+      m = INF32 - (uint32_t)mu;
+      Pu = (j < bn) ? Lu + ((int)INF32 - mu) : 0;
+      P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;
+    } else {
+      const uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda);  // lane i <-> position i - e
+      const uint32_t got =
+          (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, (int)E);
+      const uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
+      L = C + (t == 0 ? 0u : min(Ev, lt));
+      m = group_min<LPL>(L);
+      P = (j < bn) ? L - m : INF32;
+    }
+    if constexpr (OUT == OUT_PART) {
+      const uint8_t v8 = (uint8_t)min(P, 255u);
+      if constexpr (FAST) {
+        const uint32_t vo = LPL == 64 ? (uint32_t)j : pst + j, so = LPL == 64 ? pst : 0u;
+        __builtin_amdgcn_raw_buffer_store_b8(v8, rpart, (int)vo, (int)so, 0);
+      } else {
+        *(t < la.n ? part + la.pix(t) * (uint32_t)a.capP + j : sinkp + lane) = v8;
+      }
+    } else {
+      if (t < la.n && j < bn) export_canonical<OUT>(a.agg, (size_t)la.pix(t) * a.cap + j, L + acc, a.first);
+    }
+    acc += m;
+    lo_prev = b0;
+  };
 
   for (int t0 = 0; t0 < nmax; t0 += CHUNK) {
     const uint2 nxt = load_chunk<true, SRC>(a, la, t0 + CHUNK, kk);
-    static_for<CHUNK>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      constexpr int slot = k % PREFETCH;
-      const int t = t0 + k;
-      const int tt = la.tt(t);
-      const int x = la.x0 + tt * la.dx;
-      const uint32_t p = la.pix(t);
-      const uint32_t w = bw[slot];
-      const int b0 = (int)(w >> 24);
-      const int bn = VAR ? bl[slot] : a.cap;
-      const uint32_t crv = ring[slot];
-      {  // step t + PREFETCH: broadcast its word and issue its census load
-        constexpr int kn = (k + PREFETCH) % CHUNK;
-        const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
-        const uint32_t wn = (uint32_t)group_bcast<LPL, kn>((int)src.x);
-        if constexpr (VAR) bl[slot] = group_bcast<LPL, kn>((int)src.y);
-        bw[slot] = wn;
-        ring[slot] = fetch(t + PREFETCH, wn);
-      }
-      uint32_t C;
-      if constexpr (SRC == SRC_CENSUS) {
-        // written as a sum so that the popcount is always evaluated (no branch)
-        const uint32_t pc = (uint32_t)__popc((w & 0xFFFFFFu) ^ crv);
-        C = ((x - b0 - j >= 0) ? pc : 24u) + ((j < bn) ? 0u : INF32);
-      } else {
-        C = (j < bn) ? (uint32_t)a.cost[(size_t)p * a.cap + min(j, a.cap - 1)] : INF32;
-      }
-      uint32_t L, m;
-      const int src = j + (b0 - lo_prev) + e;
-      if constexpr (TAU > 0) {
-        // complement encoding: Pu = INF32 - P (absent 0), larger is better
-        const int E = band_envelope_c<LPL, TAU>(Pu, a.lambda);  // lane i <-> position i - e
-        const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
-        const int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
-        const int Mu = t == 0 ? (int)INF32 : max(Ev, (int)(INF32 - lt));
-        const int Lu = (j < bn) ? Mu - (int)C : 0;
-        const int mu = group_max<LPL>(Lu);
-        L = (j < bn) ? INF32 - (uint32_t)Lu : INF32;
-        m = INF32 - (uint32_t)mu;
-        Pu = (j < bn) ? Lu + ((int)INF32 - mu) : 0;
-        P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;
-      } else {
-        const uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda);  // lane i <-> position i - e
-        const uint32_t got =
-            (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, (int)E);
-        const uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
-        L = C + (t == 0 ? 0u : min(Ev, lt));
-        m = group_min<LPL>(L);
-        P = (j < bn) ? L - m : INF32;
-      }
-      if constexpr (OUT == OUT_PART) {
-        part[t < la.n ? p * (uint32_t)a.capP + j : sink + lane] = (uint8_t)min(P, 255u);
-      } else {
-        if (t < la.n && j < bn) export_canonical<OUT>(a.agg, (size_t)p * a.cap + j, L + acc, a.first);
-      }
-      acc += m;
-      lo_prev = b0;
-    });
+    const int xa = la.x0 + t0 * la.dx, xb = xa + (CHUNK - 1) * la.dx;
+    const bool fast = wave_all(t0 + CHUNK + PREFETCH <= la.n &&
+                               (SRC != SRC_CENSUS || min(xa, xb) >= a.D - 1));
+    if (fast) {
+      uint32_t pst = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;
+      uint32_t cpf = (uint32_t)(la.c0 + (t0 + PREFETCH) * la.dc);
+      static_for<CHUNK>([&](auto kc) {
+        step(kc, std::true_type{}, nxt, t0, pst, cpf);
+        pst += pstep;
+        cpf += (uint32_t)la.dc;
+      });
+    } else {
+      static_for<CHUNK>([&](auto kc) { step(kc, std::false_type{}, nxt, t0, 0u, 0u); });
+    }
     cur = nxt;
   }
 }

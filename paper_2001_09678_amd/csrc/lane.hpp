@@ -25,6 +25,10 @@ __device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b) {
   return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
                                                                 __builtin_bit_cast(u16x2, b)));
 }
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
   return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
 }
@@ -62,6 +66,7 @@ constexpr int ROW_SHL1 = 0x101;
 constexpr int ROW_SHR1 = 0x111;
 constexpr int ROW_ROR1 = 0x121, ROW_ROR2 = 0x122, ROW_ROR4 = 0x124, ROW_ROR8 = 0x128;
 constexpr int WAVE_SHL1 = 0x130;
+constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
 constexpr int WAVE_SHR1 = 0x138;
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
@@ -255,6 +260,30 @@ __device__ __forceinline__ int group_max(int v) {
     v = max((int)s[0], (int)s[1]);
   }
   return v;
+}
+
+// Maximum over the whole wave, returned wave-uniform (scalar): a rotate butterfly inside
+// each 16-lane row, then the four row maxima read into scalar registers.
+__device__ __forceinline__ int wave_max_s(int v) {
+  v = max(v, dpp0<ROW_ROR8>(v));
+  v = max(v, dpp0<ROW_ROR4>(v));
+  v = max(v, dpp0<ROW_ROR2>(v));
+  v = max(v, dpp0<ROW_ROR1>(v));
+  // rows 1 and 3 take the maximum of the row before; rows 2 and 3 that of lane 31
+  // (disabled rows read INT_MIN, the identity of max, so the DPP fuses into the max)
+  v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, ROW_BCAST15, 0xA, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, ROW_BCAST31, 0xC, 0xF, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Buffer resource over `p` (raw addressing, no stride; gfx9 data-format word): loads and
+// stores then take a scalar offset plus a 32-bit lane offset, with no 64-bit address math.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ uint32_t buf_ld32(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
 }
 
 // Minimum over aligned groups of N lanes (N = 1, 2, 4, 8, 16), in every lane of the group.

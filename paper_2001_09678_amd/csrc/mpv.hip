@@ -166,18 +166,22 @@ struct LevelWs {
   size_t census_off, part_off, total;
   int cpitch, cmargin;
   ScanChoice sc;
+  bool fits;  // scans address one census image and one direction's partials with 32-bit offsets
 };
 
 LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const mpv_schedule& s) {
   LevelWs w{};
   w.sc = choose_scan(p->num_disp, band, p->tau, s);
-  w.cmargin = (int)align_up((size_t)std::max(max_dpad(p->num_disp), p->num_disp) + 1, 16);
+  // left census margin: covers x - d for every lane of a full-range (padded range) or
+  // banded (band start <= D-1, up to 64 lanes) scan
+  w.cmargin = (int)align_up((size_t)std::max(max_dpad(p->num_disp), p->num_disp + 64) + 1, 16);
   w.cpitch = w.cmargin + W;
   w.census_off = 0;
   const size_t cen = align_up((size_t)H * w.cpitch * sizeof(uint32_t));
   w.part_off = w.census_off + 2 * cen;
   // partial volumes, then a 256 B sink for stores past a line's end
   w.total = w.part_off + align_up((size_t)p->num_paths * H * W * w.sc.capP) + ALIGN;
+  w.fits = (size_t)H * W * w.sc.capP <= 0x7FFFFFFFu && cen <= 0x7FFFFFFFu;
   return w;
 }
 
@@ -277,6 +281,11 @@ mpv_status pyr_geom(const mpv_pyramid_params* p, int D, int W, int H, PyrGeom& g
     g.D[l] = (D + (1 << sh) - 1) >> sh;
     if (g.W[l] < 1 || g.H[l] < 1) return MPV_ERR_INVALID_ARG;
     g.cap[l] = l == 0 ? g.D[l] : std::min(2 * p->band_radius + 1, g.D[l]);
+    mpv_params lp = base;
+    lp.num_disp = g.D[l];
+    int16_t dummy;
+    const mpv_band b{l > 0 ? &dummy : nullptr, nullptr, g.cap[l]};
+    if (!level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched).fits) return MPV_ERR_INVALID_ARG;
   }
   return MPV_OK;
 }
@@ -677,8 +686,10 @@ mpv_status mpv_disparity(const mpv_params* p, const void* agg, int32_t W, int32_
 }
 
 size_t mpv_match_workspace_bytes(const mpv_params* p, int32_t W, int32_t H, const mpv_band* band) {
-  if (check_params(p, true) || W < 1 || H < 1 || check_band(band, p->num_disp)) return 0;
-  return level_ws(p, W, H, band, mpv_schedule{}).total;
+  if (check_params(p, true) || W < 1 || H < 1 || W > MPV_MAX_WIDTH || check_band(band, p->num_disp))
+    return 0;
+  const LevelWs lw = level_ws(p, W, H, band, mpv_schedule{});
+  return lw.fits ? lw.total : 0;
 }
 
 mpv_status mpv_match(const mpv_params* p, const mpv_image* left, const mpv_image* right,
@@ -691,8 +702,9 @@ mpv_status mpv_match(const mpv_params* p, const mpv_image* left, const mpv_image
   if (left->width > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
   if ((st = check_band(band, p->num_disp))) return st;
   const mpv_schedule dflt{};
-  const size_t need = level_ws(p, left->width, left->height, band, dflt).total;
-  if (!workspace || workspace_bytes < need) return MPV_ERR_WORKSPACE;
+  const LevelWs lw = level_ws(p, left->width, left->height, band, dflt);
+  if (!lw.fits) return MPV_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < lw.total) return MPV_ERR_WORKSPACE;
   return run_level(p, left->data, left->pitch, right->data, right->pitch, left->width,
                    left->height, band, disp, disp_right, disp_raw, (uint8_t*)workspace, 0, dflt,
                    stream);
@@ -897,7 +909,8 @@ void mpv_batch_destroy(mpv_batch b) {
 // ---- learned band proposal: coarse level + features --------------------------------------
 size_t mpv_lb_coarse_workspace_bytes(const mpv_params* p, int32_t W0, int32_t H0) {
   if (check_params(p, true) || W0 < 1 || H0 < 1 || W0 > MPV_MAX_WIDTH) return 0;
-  return level_ws(p, W0, H0, nullptr, mpv_schedule{}).total;
+  const LevelWs lw = level_ws(p, W0, H0, nullptr, mpv_schedule{});
+  return lw.fits ? lw.total : 0;
 }
 
 mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_image* right0,
@@ -912,6 +925,7 @@ mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_
   if (W > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
   const mpv_schedule dflt{};
   const LevelWs lw = level_ws(p, W, H, nullptr, dflt);
+  if (!lw.fits) return MPV_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < lw.total) return MPV_ERR_WORKSPACE;
   uint8_t* ws = (uint8_t*)workspace;
   st = run_level(p, left0->data, left0->pitch, right0->data, right0->pitch, W, H, nullptr, disp0,
