@@ -27,6 +27,31 @@ sys.path.insert(0, ROOT)
 METRIC = "MPV Mde/s & fps at 1280x720 D=128 on 1 GPU; learned-band vs plain; p99 ms"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel (finest-level banded scan) per launch, from
+# `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of this script (see profiles/),
+# each calibrated by the same counter on a 1 GiB int32 negation kernel (1 GiB read, 1 GiB
+# written). Valid only for the kernel sources they were taken with (SHA-1 over the files
+# below); reported as null once those sources change.
+SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
+                "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band.hip"]
+SCAN_TRAFFIC = {"sources_sha1": "a5cc07b221b9046f3d017908e89692c763202741",
+                "fetch_bytes": 150798578, "write_bytes": 121675673}
+
+
+def scan_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in SCAN_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def parse_sched(text):
+    from paper_2001_09678_amd import mpv
+    w, f, b, o = (int(v) for v in text.split(","))
+    return mpv.Schedule(waves_per_block=w, full_lanes=f, band_lanes=b, order=o)
+
 
 def _events(n):
     import torch
@@ -249,6 +274,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--sched", default=None, help="multi-scale schedule 'waves,full_lanes,band_lanes,order' "
+                                                  "(skips the autotuner)")
+    ap.add_argument("--plain-sched", default=None, help="plain full-range schedule (skips the autotuner)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the measurements, run an int32 negation over this many MiB (counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--learned-pairs", type=int, default=16)
     args = ap.parse_args()
@@ -272,8 +302,10 @@ def main():
     params = mpv.MPVParams(num_disp=D, num_paths=P, lam=8, tau=4, lr_max_diff=1)
 
     # ---- schedules picked by the autotuner (every candidate is checked bit-identical)
-    sched, _ = autotune.tune_pyramid(left, right, params, levels, 4, use_cache=False)
-    psched, _ = autotune.tune_pyramid(left, right, params, 1, 4, use_cache=False)
+    sched = parse_sched(args.sched) if args.sched else autotune.tune_pyramid(left, right, params, levels, 4,
+                                                                              use_cache=False)[0]
+    psched = parse_sched(args.plain_sched) if args.plain_sched else autotune.tune_pyramid(
+        left, right, params, 1, 4, use_cache=False)[0]
 
     # ---- multi-scale (the measured workload)
     pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=sched)
@@ -300,6 +332,10 @@ def main():
     pscan_avg = sum(pscan) / len(pscan)
     pscan_bytes = P * W * H * 128 + 2 * 4 * W * H
     agree = float((plain.disp == pyr.disp).float().mean().item())
+
+    traffic = None
+    if SCAN_TRAFFIC["sources_sha1"] and SCAN_TRAFFIC["sources_sha1"] == scan_sources_sha1():
+        traffic = int(SCAN_TRAFFIC["fetch_bytes"] + SCAN_TRAFFIC["write_bytes"])
 
     breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
     batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
@@ -337,7 +373,7 @@ def main():
                                     "frac": round(pscan_bytes / (pscan_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                   "agreement_with_multiscale": round(agree, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_scan_band<16,census,partial> (finest level, 8 directions)",
                      "kernel_ms": round(scan_avg, 4), "algorithmic_bytes": scan_bytes},
         "stage_ms": breakdown,
@@ -346,6 +382,17 @@ def main():
         "learned": learned_res,
         "serve": serve_res,
     }
+    if traffic is not None:
+        result["roofline"]["traffic_fetch"] = SCAN_TRAFFIC["fetch_bytes"]
+        result["roofline"]["traffic_write"] = SCAN_TRAFFIC["write_bytes"]
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib << 18  # int32 elements
+        src = torch.ones(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cfg)
     print(json.dumps(result), flush=True)
