@@ -550,14 +550,16 @@ __device__ __forceinline__ void export_canonical(void* agg, size_t idx, uint32_t
 // (unnormalised) export, TAU compile-time tau (0: runtime). BANDED: a lane's disparity
 // outside the pixel's band is an absent node; partials are then indexed by absolute
 // disparity.
+// `a`: the descriptor's values; `tab`: the same descriptor where its direction tables are
+// read (batched launches pass a private copy as `a` and the table entry as `tab`).
 template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
-__device__ __forceinline__ void scan_full_wave(const ScanArgs& a, int unit) {
+__device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs& tab, int unit) {
   const int lane = lane_id();
   const int l = LPL == 64 ? lane : lane % LPL;
   const int kk = l % CHUNK;
   int r, ri, nmax;
   Line ln;
-  block_line<LPL>(a, unit, r, ri, ln, nmax);
+  block_line<LPL>(tab, unit, r, ri, ln, nmax);
   const LineAddr la = line_addr(a, ln);
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
   uint32_t P[K];
@@ -764,14 +766,14 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, int unit) {
 // slots on each side, then lane j of the new pixel picks position j + lo(p) - lo(p-r).
 // VAR: per-pixel band lengths (otherwise every pixel has len = cap).
 template <int LPL, int SRC, int OUT, int TAU, bool VAR>
-__device__ __forceinline__ void scan_band_wave(const ScanArgs& a, int unit) {
+__device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs& tab, int unit) {
   const int lane = lane_id();
   const int j = LPL == 64 ? lane : lane % LPL;
   const int kk = j % CHUNK;
   const int gbase = lane - j;
   int r, ri, nmax;
   Line ln;
-  block_line<LPL>(a, unit, r, ri, ln, nmax);
+  block_line<LPL>(tab, unit, r, ri, ln, nmax);
   const LineAddr la = line_addr(a, ln);
   const int e = a.tau - 1;
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
@@ -907,7 +909,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, int unit) {
 template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
 __global__ __launch_bounds__(256) void k_scan_full(ScanArgs a) {
   const int u = wave_unit();
-  if (u < a.gprefix[a.ndir]) scan_full_wave<LPL, K, SRC, OUT, TAU, BANDED>(a, u);
+  if (u < a.gprefix[a.ndir]) scan_full_wave<LPL, K, SRC, OUT, TAU, BANDED>(a, a, u);
 }
 
 template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
@@ -915,13 +917,15 @@ __global__ __launch_bounds__(256) void k_scan_full_batch(Batch<ScanArgs> b) {
   const int u = wave_unit();
   if (u >= b.first[b.nseg]) return;
   const int s = batch_find(b.first, b.nseg, u);
-  scan_full_wave<LPL, K, SRC, OUT, TAU, BANDED>(b.desc[s], u - b.first[s]);
+  // a private copy: read once (scalar loads), not re-read after every partial store
+  const ScanArgs a = b.desc[s];
+  scan_full_wave<LPL, K, SRC, OUT, TAU, BANDED>(a, b.desc[s], u - b.first[s]);
 }
 
 template <int LPL, int SRC, int OUT, int TAU, bool VAR>
 __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
   const int u = wave_unit();
-  if (u < a.gprefix[a.ndir]) scan_band_wave<LPL, SRC, OUT, TAU, VAR>(a, u);
+  if (u < a.gprefix[a.ndir]) scan_band_wave<LPL, SRC, OUT, TAU, VAR>(a, a, u);
 }
 
 template <int LPL, int SRC, int OUT, int TAU, bool VAR>
@@ -929,7 +933,8 @@ __global__ __launch_bounds__(256) void k_scan_band_batch(Batch<ScanArgs> b) {
   const int u = wave_unit();
   if (u >= b.first[b.nseg]) return;
   const int s = batch_find(b.first, b.nseg, u);
-  scan_band_wave<LPL, SRC, OUT, TAU, VAR>(b.desc[s], u - b.first[s]);
+  const ScanArgs a = b.desc[s];  // private copy, as above
+  scan_band_wave<LPL, SRC, OUT, TAU, VAR>(a, b.desc[s], u - b.first[s]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1172,7 +1177,8 @@ template <int LPP>
 __global__ __launch_bounds__(256) void k_reduce_part_batch(Batch<RedArgs> b) {
   const int u = blockIdx.x;
   const int s = batch_find(b.first, b.nseg, u);
-  reduce_part_row<LPP>(b.desc[s], u - b.first[s], b.desc[s].need_lr);
+  const RedArgs a = b.desc[s];  // private copy: not re-read after every store
+  reduce_part_row<LPP>(a, u - b.first[s], a.need_lr);
 }
 
 // ---------------------------------------------------------------------------------------
