@@ -17,9 +17,9 @@ void reduce_part(const RedArgs& a, int need_lr, hipStream_t s) {
   switch (a.stride / 16) {
     case 1: hipLaunchKernelGGL(k_reduce_part<1>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
     case 2: hipLaunchKernelGGL(k_reduce_part<2>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-    case 4: hipLaunchKernelGGL(k_reduce_part<4>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-    case 8: hipLaunchKernelGGL(k_reduce_part<8>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
-    default: hipLaunchKernelGGL(k_reduce_part<16>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
+    case 4: hipLaunchKernelGGL(k_reduce_part<4>, dim3(a.H), dim3(1024), 0, s, a, need_lr); break;
+    case 8: hipLaunchKernelGGL(k_reduce_part<8>, dim3(a.H), dim3(1024), 0, s, a, need_lr); break;
+    default: hipLaunchKernelGGL(k_reduce_part<16>, dim3(a.H), dim3(1024), 0, s, a, need_lr); break;
   }
 }
 
@@ -27,9 +27,9 @@ void reduce_part_batch(const Batch<RedArgs>& b, int rows, int stride, hipStream_
   switch (stride / 16) {
     case 1: hipLaunchKernelGGL(k_reduce_part_batch<1>, dim3(rows), dim3(256), 0, s, b); break;
     case 2: hipLaunchKernelGGL(k_reduce_part_batch<2>, dim3(rows), dim3(256), 0, s, b); break;
-    case 4: hipLaunchKernelGGL(k_reduce_part_batch<4>, dim3(rows), dim3(256), 0, s, b); break;
-    case 8: hipLaunchKernelGGL(k_reduce_part_batch<8>, dim3(rows), dim3(256), 0, s, b); break;
-    default: hipLaunchKernelGGL(k_reduce_part_batch<16>, dim3(rows), dim3(256), 0, s, b); break;
+    case 4: hipLaunchKernelGGL(k_reduce_part_batch<4>, dim3(rows), dim3(1024), 0, s, b); break;
+    case 8: hipLaunchKernelGGL(k_reduce_part_batch<8>, dim3(rows), dim3(1024), 0, s, b); break;
+    default: hipLaunchKernelGGL(k_reduce_part_batch<16>, dim3(rows), dim3(1024), 0, s, b); break;
   }
 }
 

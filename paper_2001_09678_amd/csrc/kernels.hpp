@@ -1084,9 +1084,9 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
   __shared__ uint32_t s_rkey[RED_MAXW];
   __shared__ int16_t s_dl[RED_MAXW];
   constexpr uint32_t NOK = 0xFFFFFFFFu;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x, nw = nt >> 6;
   if (need_lr) {
-    for (int x = tid; x < a.W; x += 256) s_rkey[x] = NOK;
+    for (int x = tid; x < a.W; x += nt) s_rkey[x] = NOK;
     __syncthreads();
   }
   const int lane = lane_id();
@@ -1094,18 +1094,24 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
   const int jl = lane % LPP;
   const int j0 = jl * 16;
   constexpr int PPW = 64 / LPP;  // pixels per wave step
-  const int xsteps = (a.W + 4 * PPW - 1) / (4 * PPW);
+  const int xsteps = (a.W + nw * PPW - 1) / (nw * PPW);
   for (int it = 0; it < xsteps; ++it) {
-    const int x = (it * 4 + wave) * PPW + lane / LPP;
+    const int x = (it * nw + wave) * PPW + lane / LPP;
     const bool xin = x < a.W;
     const size_t p = (size_t)y * a.W + (xin ? x : a.W - 1);
+    // every direction's 16 slots are loaded before any is used (npart <= 8, uniform)
+    const uint8_t* q0 = a.part + p * a.stride + j0;
+    uint4 wv[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      wv[r] = r < a.npart ? *(const uint4*)(q0 + r * a.part_stride) : make_uint4(0u, 0u, 0u, 0u);
     int b0, bn;
     band_at(a.lo, a.len, p, a.D, a.bcap, b0, bn);
     // s[2q]: slots 4q (lo), 4q+2 (hi); s[2q+1]: slots 4q+1 (lo), 4q+3 (hi)
     uint32_t sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const uint8_t* q0 = a.part + p * a.stride + j0;
-    for (int r = 0; r < a.npart; ++r) {
-      const uint4 w = *(const uint4*)(q0 + r * a.part_stride);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint4 w = wv[r];
       const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -1150,7 +1156,7 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
   }
   if (!need_lr) return;
   __syncthreads();
-  for (int x = tid; x < a.W; x += 256) {
+  for (int x = tid; x < a.W; x += nt) {
     const size_t p = (size_t)y * a.W + x;
     const uint32_t k = s_rkey[x];
     if (a.right) a.right[p] = k == NOK ? (int16_t)-1 : (int16_t)(511 - (int)(k & 511u));
@@ -1167,14 +1173,15 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
   }
 }
 
+// Blocks of 256 threads, or 1024 for pixels of 4 or more lanes (more loads in flight per row).
 template <int LPP>
-__global__ __launch_bounds__(256) void k_reduce_part(RedArgs a, int need_lr) {
+__global__ __launch_bounds__(1024) void k_reduce_part(RedArgs a, int need_lr) {
   reduce_part_row<LPP>(a, blockIdx.x, need_lr);
 }
 
 // Batched: one block per image row of every pair; need_lr is per descriptor (a.lr_need).
 template <int LPP>
-__global__ __launch_bounds__(256) void k_reduce_part_batch(Batch<RedArgs> b) {
+__global__ __launch_bounds__(1024) void k_reduce_part_batch(Batch<RedArgs> b) {
   const int u = blockIdx.x;
   const int s = batch_find(b.first, b.nseg, u);
   const RedArgs a = b.desc[s];  // private copy: not re-read after every store
