@@ -26,6 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MPV Mde/s & fps at 1280x720 D=128 on 1 GPU; learned-band vs plain; p99 ms"
 HBM_PEAK_GBS = 8000.0
+# integer VALU issue: 256 CUs x 4 SIMD16 units (64 lanes per CU per cycle) x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic integer operations per evaluated node and direction (cost, truncated-L1
+# envelope, transition minimum, normalisation, amortised line minimum)
+OPS_PER_NODE_PATH = 14
 
 # HBM traffic of the dominant kernel (finest-level banded scan) per launch, from
 # `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of this script (see profiles/),
@@ -34,8 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # below); reported as null once those sources change.
 SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band.hip"]
-SCAN_TRAFFIC = {"sources_sha1": "a5cc07b221b9046f3d017908e89692c763202741",
-                "fetch_bytes": 150798578, "write_bytes": 121675673}
+SCAN_TRAFFIC = {"sources_sha1": "c31b41c8ce7c4adec71fb2326733de82e78fa44b",
+                "fetch_bytes": 150744308, "write_bytes": 121673420}
 
 
 def scan_sources_sha1():
@@ -114,6 +119,33 @@ def stage_breakdown(pyr, left, right, levels, reps=20):
             torch.cuda.synchronize()
             out[f"L{l}.{name}"] = round(sum(b[i].elapsed_time(a[i]) for i in range(reps)) / reps, 4)
     return out
+
+
+def stream_bench(params, levels, dev, sched, steps, frames=16):
+    """Frames of the measured shape in flight together: `frames` 1280x720 pairs (seeds
+    2..2+frames-1) per captured graph, so the levels of different frames overlap."""
+    import torch
+    from paper_2001_09678_amd import mpv
+    from paper_2001_09678_amd.scene import batch_scenes
+    specs = [(2 + i, 1280, 720, 128, 30) for i in range(frames)]
+    scenes = batch_scenes(specs, workers=16)
+    pairs = [(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev), 128) for sc in scenes]
+    b = mpv.Batch(pairs, params, levels, 4, sched=sched)
+    for _ in range(3):
+        b.run_graph()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        b.run_graph()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return {"frames_per_launch": frames, "ms_per_launch": round(ms, 4),
+            "fps": round(frames / ms * 1e3, 1), "value": round(frames * 1280 * 720 * 128 / (ms * 1e-3) / 1e6, 1),
+            "unit": "Mde/s", "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
+            "note": "throughput with frames in flight; the headline value is one frame per step"}
 
 
 def batch_bench(params, levels, dev, steps):
@@ -241,7 +273,7 @@ def pct(vals, q):
     return s[k]
 
 
-def cpu_baseline(scene, cfg, budget_s=20.0, max_frames=5):
+def cpu_baseline(scene, cfg, budget_s=15.0, max_frames=60):
     """The oracle as it stands (fast transition mode), on this host's cores, over whole
     frames of the same workload until the time budget is spent."""
     import oracle
@@ -331,6 +363,10 @@ def main():
                                          hook_stage=L.STAGE_SCAN, hook_level=0)
     pscan_avg = sum(pscan) / len(pscan)
     pscan_bytes = P * W * H * 128 + 2 * 4 * W * H
+    pscan_ops = OPS_PER_NODE_PATH * P * W * H * D
+    _, _, pred, _ = time_pipeline(plain, left, right, args.plain_steps, 2, hook_stage=L.STAGE_REDUCE, hook_level=0)
+    pred_avg = sum(pred) / len(pred)
+    pred_bytes = P * W * H * 128 + 3 * 2 * W * H  # every partial read once; three int16 maps written
     agree = float((plain.disp == pyr.disp).float().mean().item())
 
     traffic = None
@@ -339,6 +375,7 @@ def main():
 
     breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
     batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
+    stream = {} if args.no_batch else stream_bench(params, levels, dev, sched, args.batch_steps * 2)
     learned_res = {} if args.no_learned else learned_bench(params, dev, args.plain_steps, args.learned_pairs)
     serve_res = {} if args.no_serve else serve_bench(args.serve_seconds)
 
@@ -371,6 +408,13 @@ def main():
                   "scan_roofline": {"bound": "hbm", "achieved": round(pscan_bytes / (pscan_avg * 1e-3) / 1e9, 1),
                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(pscan_bytes / (pscan_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                  "scan_alu_roofline": {"bound": "alu", "achieved": round(pscan_ops / (pscan_avg * 1e-3) / 1e12, 2),
+                                        "peak": round(ALU_PEAK_TOPS, 1), "unit": "Tops/s",
+                                        "frac": round(pscan_ops / (pscan_avg * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4)},
+                  "reduce_ms": round(pred_avg, 4),
+                  "reduce_roofline": {"bound": "hbm", "achieved": round(pred_bytes / (pred_avg * 1e-3) / 1e9, 1),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(pred_bytes / (pred_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                   "agreement_with_multiscale": round(agree, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -379,6 +423,7 @@ def main():
         "stage_ms": breakdown,
         "schedule": {"multiscale": sched.__dict__, "plain": psched.__dict__},
         "batch": batch,
+        "stream": stream,
         "learned": learned_res,
         "serve": serve_res,
     }
