@@ -53,6 +53,7 @@ typedef enum {
 #define MPV_MAX_DISP 256
 #define MPV_MAX_LEVELS 4
 #define MPV_MAX_WIDTH 4096
+#define MPV_MAX_HEIGHT 65536
 
 /* Scan directions, in the order of the paper's multi-path table (Section 3.2, Table alg):
  * bit r of a path mask selects direction r. num_paths = P selects the first P. */
@@ -172,14 +173,16 @@ size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params *p, int32_t width, i
  * Each level runs cost -> all P paths -> sum -> WTA -> LR exactly as the unfused calls
  * do, so the outputs equal mpv_cost + mpv_aggregate + mpv_disparity per level.
  * Requires 24 + lambda*min(tau, D-1) <= 255, num_paths in {1,2,4,8} and every level at
- * least 1x1 pixel and at most MPV_MAX_WIDTH wide. */
+ * least 1x1 pixel, at most MPV_MAX_WIDTH wide and MPV_MAX_HEIGHT high; one direction's
+ * partial volume (width * height * slots) below 2^31 bytes (MPV_ERR_INVALID_ARG otherwise). */
 mpv_status mpv_pyramid(const mpv_pyramid_params *p, const mpv_image *left, const mpv_image *right,
                        const mpv_pyramid_out *out, void *workspace, size_t workspace_bytes,
                        hipStream_t stream);
 
 /* One fused level with a caller-given band (the learned-band path: a network proposes
  * lo/len per pixel and the finest level searches only there). Same arithmetic and
- * outputs as one level of mpv_pyramid. band may be NULL (full range). */
+ * outputs as one level of mpv_pyramid, with the same limits. band may be NULL (full range).
+ * mpv_match_workspace_bytes returns 0 for arguments mpv_match would reject. */
 size_t mpv_match_workspace_bytes(const mpv_params *p, int32_t width, int32_t height,
                                  const mpv_band *band);
 mpv_status mpv_match(const mpv_params *p, const mpv_image *left, const mpv_image *right,

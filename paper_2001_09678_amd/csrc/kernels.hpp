@@ -778,7 +778,13 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   const int e = a.tau - 1;
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
   uint32_t P = INF32;  // normalised energies of the previous pixel (runtime-tau path)
-  int Pu = 0;          // the same in complement encoding (compile-time-tau path)
+  // compile-time-tau path: unnormalised energies in complement encoding, Pu = INF32 - L
+  // (absent 0). L never needs normalising here: the fused path has 24 + lambda*tau <= 255
+  // and lines of at most MPV_MAX_HEIGHT (or MPV_MAX_WIDTH) pixels, so L < 2^24, far from
+  // INF32. The line maximum then feeds only the next step's truncation candidate and the
+  // stored bytes, off the step's dependent chain.
+  int Pu = 0;
+  int capu = 0;  // max over the previous pixel's band of Pu, minus lambda*tau
   int lo_prev = 0;
   uint32_t acc = 0;
   uint8_t* part = a.part + (long long)(a.dir_base + ri) * a.part_stride;
@@ -849,17 +855,18 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       const int E = band_envelope_c<LPL, TAU>(Pu, a.lambda);  // lane i <-> position i - e
       const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
       const int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
-      const int Mu = t == 0 ? (int)INF32 : max(Ev, (int)(INF32 - lt));
+      const int Mu = t == 0 ? (int)INF32 : max(Ev, capu);
       const int Lu = (j < bn) ? Mu - (int)C : 0;
+      Pu = Lu;  // next state
       int mu;
       if constexpr (LPL == 64)
         mu = wave_max_s(Lu);
       else
         mu = group_max<LPL>(Lu);
-      L = (j < bn) ? INF32 - (uint32_t)Lu : INF32;
-      m = INF32 - (uint32_t)mu;
-      Pu = (j < bn) ? Lu + ((int)INF32 - mu) : 0;
-      P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;
+      capu = mu - (int)lt;
+      L = (j < bn) ? INF32 - (uint32_t)Lu : INF32;  // canonical energy itself
+      m = 0;                                          // (no offset to carry)
+      P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;    // energy minus the line minimum
     } else {
       const uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda);  // lane i <-> position i - e
       const uint32_t got =

@@ -166,7 +166,9 @@ struct LevelWs {
   size_t census_off, part_off, total;
   int cpitch, cmargin;
   ScanChoice sc;
-  bool fits;  // scans address one census image and one direction's partials with 32-bit offsets
+  // scans address one census image and one direction's partials with 32-bit offsets, and
+  // keep unnormalised energies of lines up to MPV_MAX_HEIGHT long in 32 bits
+  bool fits;
 };
 
 LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const mpv_schedule& s) {
@@ -181,7 +183,7 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const 
   w.part_off = w.census_off + 2 * cen;
   // partial volumes, then a 256 B sink for stores past a line's end
   w.total = w.part_off + align_up((size_t)p->num_paths * H * W * w.sc.capP) + ALIGN;
-  w.fits = (size_t)H * W * w.sc.capP <= 0x7FFFFFFFu && cen <= 0x7FFFFFFFu;
+  w.fits = (size_t)H * W * w.sc.capP <= 0x7FFFFFFFu && cen <= 0x7FFFFFFFu && H <= MPV_MAX_HEIGHT;
   return w;
 }
 

@@ -93,6 +93,13 @@ def test_fused_limits(L):
     # too many levels for the image
     deep = L.PyramidParams(_params(L, num_disp=128, num_paths=8), 4, 4)
     assert lib.mpv_pyramid_workspace_bytes(C.byref(deep), 6, 6) == 0
+    # height limit (unnormalised 32-bit line energies) and the 2^31-byte partial volume
+    one = L.PyramidParams(_params(L, num_disp=64, num_paths=8), 1, 4)
+    assert lib.mpv_pyramid_workspace_bytes(C.byref(one), 16, 65536) > 0
+    assert lib.mpv_pyramid_workspace_bytes(C.byref(one), 16, 65537) == 0
+    p256 = _params(L, num_disp=256, num_paths=8)
+    assert lib.mpv_match_workspace_bytes(C.byref(p256), 4096, 2047, None) > 0
+    assert lib.mpv_match_workspace_bytes(C.byref(p256), 4096, 2049, None) == 0
     # workspace too small is reported before any launch
     fake = C.c_void_p(0x1000)
     img = L.Image(fake, 1280, 720, 1280)
