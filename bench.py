@@ -102,13 +102,12 @@ def stage_breakdown(pyr, left, right, levels, reps=20):
     from paper_2001_09678_amd import _lib as L
     lib = L.lib()
     out = {}
+    # (the band propagation runs inside the coarser level's reduce)
     names = {L.STAGE_DOWNSAMPLE: "downsample", L.STAGE_CENSUS: "census", L.STAGE_SCAN: "scan",
-             L.STAGE_REDUCE: "reduce", L.STAGE_PROPAGATE: "propagate"}
+             L.STAGE_REDUCE: "reduce"}
     for st, name in names.items():
         for l in range(levels):
             if st == L.STAGE_DOWNSAMPLE and l == levels - 1:
-                continue
-            if st == L.STAGE_PROPAGATE and l == 0:
                 continue
             b, a = _events(reps), _events(reps)
             torch.cuda.synchronize()

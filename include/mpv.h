@@ -223,8 +223,10 @@ void mpv_batch_destroy(mpv_batch b);
 #define MPV_STAGE_DOWNSAMPLE 0
 #define MPV_STAGE_CENSUS 1
 #define MPV_STAGE_SCAN 2      /* all P directions of one level, one launch */
-#define MPV_STAGE_REDUCE 3    /* sum + WTA + right disparity + LR of one level */
-#define MPV_STAGE_PROPAGATE 4
+#define MPV_STAGE_REDUCE 3    /* sum + WTA + right disparity + LR of one level, and the band
+                                 of the next finer level (Section 3.4 propagation) */
+#define MPV_STAGE_PROPAGATE 4 /* no launches of its own: the band propagation runs inside the
+                                 coarser level's reduce */
 #define MPV_NUM_STAGES 5
 
 /* While set, every later launch of `stage` at pyramid level `level` (0 = coarsest; the

@@ -73,12 +73,6 @@ void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int
                      W, H, lo, len, cap, D, out);
 }
 
-void propagate(const int16_t* coarse, int Wc, int Hc, int W, int H, int Dl, int R, int cap,
-               int16_t* lo, hipStream_t s) {
-  hipLaunchKernelGGL(k_propagate, pix_grid(W, H, 1), dim3(256), 0, s, coarse, Wc, Hc, W, H, Dl, R,
-                     cap, lo);
-}
-
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s) {
   const int b = (int)std::min<size_t>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_fill<uint16_t>, dim3(b), dim3(256), 0, s, p, n, v);
@@ -95,10 +89,6 @@ void census_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s) {
 
 void downsample_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_downsample_batch, dim3(blocks), dim3(256), 0, s, b);
-}
-
-void propagate_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_propagate_batch, dim3(blocks), dim3(256), 0, s, b);
 }
 
 }  // namespace mpvl

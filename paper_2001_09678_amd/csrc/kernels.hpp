@@ -1149,6 +1149,13 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
       if (jl == 0) {
         if (a.raw) a.raw[p] = (int16_t)dl;
         if (need_lr) s_dl[x] = (int16_t)dl;
+        if (a.nlo) {  // the 2x2 finer pixels of this one, and the odd last column / row
+          const int16_t v = (int16_t)min(max(2 * dl - a.nR, 0), a.nD - a.ncap);
+          const int fx1 = x == a.W - 1 ? a.nW : min(2 * x + 2, a.nW);
+          const int fy1 = y == a.H - 1 ? a.nH : min(2 * y + 2, a.nH);
+          for (int fy = 2 * y; fy < fy1; ++fy)
+            for (int fx = 2 * x; fx < fx1; ++fx) a.nlo[(size_t)fy * a.nW + fx] = v;
+        }
       }
       if (need_lr) {
 #pragma unroll
@@ -1195,21 +1202,7 @@ __global__ __launch_bounds__(1024) void k_reduce_part_batch(Batch<RedArgs> b) {
   reduce_part_row<LPP>(a, u - b.first[s], a.need_lr);
 }
 
-// ---------------------------------------------------------------------------------------
-// Coarse-to-fine band (Section 3.4): lo = clamp(2 * parent raw WTA - R, 0, Dl - cap)
-// ---------------------------------------------------------------------------------------
-#ifdef MPV_MISC_KERNELS
-__global__ __launch_bounds__(256) void k_propagate(const int16_t* __restrict__ coarse, int Wc,
-                                                   int Hc, int W, int H, int Dl, int R, int cap,
-                                                   int16_t* __restrict__ lo) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= W || y >= H) return;
-  const int cx = min(x >> 1, Wc - 1), cy = min(y >> 1, Hc - 1);
-  const int c = 2 * (int)coarse[(size_t)cy * Wc + cx];
-  lo[(size_t)y * W + x] = (int16_t)min(max(c - R, 0), Dl - cap);
-}
-#endif
+
 
 
 // ---------------------------------------------------------------------------------------
@@ -1253,16 +1246,7 @@ __global__ __launch_bounds__(256) void k_downsample_batch(Batch<PixArgs> b) {
 #endif
 
 
-#ifdef MPV_MISC_KERNELS
-__global__ __launch_bounds__(256) void k_propagate_batch(Batch<PixArgs> b) {
-  const PixArgs* a;
-  int v, x, y;
-  if (!batch_pixel(b, a, v, x, y)) return;
-  const int cx = min(x >> 1, a->Wc - 1), cy = min(y >> 1, a->Hc - 1);
-  const int c = 2 * (int)a->coarse[(size_t)cy * a->Wc + cx];
-  a->lo[(size_t)y * a->W + x] = (int16_t)min(max(c - a->R, 0), a->Dl - a->cap);
-}
-#endif
+
 
 
 template <typename T>

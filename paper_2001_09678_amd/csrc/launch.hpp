@@ -39,15 +39,12 @@ void downsample(const uint8_t* in, int pitch, uint8_t* out, const uint8_t* in2, 
                 uint8_t* out2, int w, int h, hipStream_t s);
 void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int H,
           const int16_t* lo, const uint8_t* len, int cap, int D, uint8_t* cost, hipStream_t s);
-void propagate(const int16_t* coarse, int Wc, int Hc, int W, int H, int Dl, int R, int cap,
-               int16_t* lo, hipStream_t s);
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s);
 void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 
 // Batched per-pixel stages: `blocks` = sum over descriptors of their tiles (x2 for two views).
 void census_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
 void downsample_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
-void propagate_batch(const Batch<PixArgs>& b, int blocks, hipStream_t s);
 
 // Features of a coarse level for the band-proposal network (kern_lb.hip).
 void lb_features(const uint8_t* part, long long pstride, int capP, int P, int D, int W, int H,

@@ -212,8 +212,14 @@ ScanArgs level_scan_args(const mpv_params* p, int W, int H, const mpv_band* band
   return a;
 }
 
+// Band of the next finer level, written by this level's reduce.
+struct NextBand {
+  int16_t* lo;
+  int W, H, D, R, cap;
+};
+
 RedArgs level_red_args(const mpv_params* p, const ScanArgs& a, const LevelWs& lw, int16_t* disp,
-                       int16_t* right, int16_t* raw) {
+                       int16_t* right, int16_t* raw, const NextBand* nb = nullptr) {
   RedArgs ra{};
   ra.W = a.W;
   ra.H = a.H;
@@ -231,6 +237,14 @@ RedArgs level_red_args(const mpv_params* p, const ScanArgs& a, const LevelWs& lw
   ra.disp = disp;
   ra.right = right;
   ra.raw = raw;
+  if (nb) {
+    ra.nlo = nb->lo;
+    ra.nW = nb->W;
+    ra.nH = nb->H;
+    ra.nD = nb->D;
+    ra.nR = nb->R;
+    ra.ncap = nb->cap;
+  }
   return ra;
 }
 
@@ -238,7 +252,7 @@ RedArgs level_red_args(const mpv_params* p, const ScanArgs& a, const LevelWs& lw
 mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const uint8_t* R,
                      int rpitch, int W, int H, const mpv_band* band, int16_t* disp,
                      int16_t* right, int16_t* raw, uint8_t* ws, int level,
-                     const mpv_schedule& sched, hipStream_t s) {
+                     const mpv_schedule& sched, hipStream_t s, const NextBand* nb = nullptr) {
   const LevelWs lw = level_ws(p, W, H, band, sched);
   ScanArgs a = level_scan_args(p, W, H, band, lw, ws);
   {
@@ -253,7 +267,7 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
     HookScope hs(MPV_STAGE_SCAN, level, s);
     launch_scan(a, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
   }
-  const RedArgs ra = level_red_args(p, a, lw, disp, right, raw);
+  const RedArgs ra = level_red_args(p, a, lw, disp, right, raw, nb);
   {
     HookScope hs(MPV_STAGE_REDUCE, level, s);
     mpvl::reduce_part(ra, ra.need_lr, s);
@@ -295,7 +309,7 @@ mpv_status pyr_geom(const mpv_pyramid_params* p, int D, int W, int H, PyrGeom& g
 struct PyrWs {
   size_t img_off[MPV_MAX_LEVELS];  // left at off, right at off + W*H
   size_t raw_off[MPV_MAX_LEVELS];
-  size_t lo_off;
+  size_t lo_off[2];  // band starts: level l reads buffer l & 1, its reduce writes the other
   size_t level_off;  // census + partials, reused per level
   size_t total;
 };
@@ -317,8 +331,10 @@ PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g) {
     w.raw_off[l] = off;
     off += align_up((size_t)g.W[l] * g.H[l] * sizeof(int16_t));
   }
-  w.lo_off = off;
-  off += align_up((size_t)g.W[g.L - 1] * g.H[g.L - 1] * sizeof(int16_t));
+  for (int k = 0; k < 2; ++k) {
+    w.lo_off[k] = off;
+    off += align_up((size_t)g.W[g.L - 1] * g.H[g.L - 1] * sizeof(int16_t));
+  }
   w.level_off = off;
   size_t lvl = 0;
   for (int l = 0; l < g.L; ++l) {
@@ -349,7 +365,7 @@ struct mpv_batch_s {
   size_t table_bytes = 0;  // descriptor tables at the start of the workspace
   size_t total = 0;
   uint8_t* ws = nullptr;
-  enum Kind { DOWN, CENSUS, PROP, SCAN_FULL, SCAN_BAND, REDUCE };
+  enum Kind { DOWN, CENSUS, SCAN_FULL, SCAN_BAND, REDUCE };
   struct Launch {
     Kind kind;
     int level;
@@ -442,8 +458,8 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       uint8_t* r = region(pr);
       const mpv_params lp = level_params(&b.p, pr.g.D[l]);
       static int16_t dummy_lo;
-      mpv_band band{l > 0 ? (r ? (const int16_t*)(r + pr.w.lo_off) : &dummy_lo) : nullptr, nullptr,
-                    pr.g.cap[l]};
+      mpv_band band{l > 0 ? (r ? (const int16_t*)(r + pr.w.lo_off[l & 1]) : &dummy_lo) : nullptr,
+                    nullptr, pr.g.cap[l]};
       lws[i] = level_ws(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, sc);
       sargs[i] = level_scan_args(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, lws[i],
                                  r ? r + pr.w.level_off : nullptr);
@@ -459,24 +475,6 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       cd.push_back(a);
     }
     add_pix(mpv_batch_s::CENSUS, l, cd, 2);
-    if (l > 0) {
-      std::vector<PixArgs> pd;
-      for (auto& pr : b.pairs) {
-        uint8_t* r = region(pr);
-        PixArgs a{};
-        a.W = pr.g.W[l];
-        a.H = pr.g.H[l];
-        a.coarse = r ? (const int16_t*)(r + pr.w.raw_off[l - 1]) : nullptr;
-        a.Wc = pr.g.W[l - 1];
-        a.Hc = pr.g.H[l - 1];
-        a.Dl = pr.g.D[l];
-        a.R = b.p.band_radius;
-        a.cap = pr.g.cap[l];
-        a.lo = r ? (int16_t*)(r + pr.w.lo_off) : nullptr;
-        pd.push_back(a);
-      }
-      add_pix(mpv_batch_s::PROP, l, pd, 1);
-    }
     // scans: pairs grouped by kernel variant, one descriptor per (pair, direction)
     struct Key {
       bool band;
@@ -548,8 +546,17 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
         uint8_t* r = region(pr);
         const mpv_params lp = level_params(&b.p, pr.g.D[l]);
         int16_t* raw = r ? (int16_t*)(r + pr.w.raw_off[l]) : nullptr;
+        NextBand nb{r ? (int16_t*)(r + pr.w.lo_off[(l + 1) & 1]) : nullptr, 0, 0, 0, 0, 0};
+        if (!last) {
+          nb.W = pr.g.W[l + 1];
+          nb.H = pr.g.H[l + 1];
+          nb.D = pr.g.D[l + 1];
+          nb.R = b.p.band_radius;
+          nb.cap = pr.g.cap[l + 1];
+        }
         RedArgs ra = level_red_args(&lp, sargs[i], lws[i], last ? pr.item.disp : nullptr,
-                                    last ? pr.item.disp_right : nullptr, raw);
+                                    last ? pr.item.disp_right : nullptr, raw,
+                                    last || !r ? nullptr : &nb);
         if (last && pr.item.disp_raw) ra.raw = pr.item.disp_raw;
         d.push_back(ra);
         first.push_back(rows);
@@ -748,24 +755,24 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     ri[l] = dr;
     lp[l] = rp[l] = g.W[l];
   }
-  int16_t* lo = (int16_t*)(ws + w.lo_off);
   for (int l = 0; l < L; ++l) {
     int16_t* raw = out->level_raw[l] ? out->level_raw[l] : (int16_t*)(ws + w.raw_off[l]);
     const mpv_params lpar = level_params(p, g.D[l]);
-    mpv_band b{nullptr, nullptr, g.cap[l]};
-    if (l > 0) {
-      const int16_t* prev = out->level_raw[l - 1] ? out->level_raw[l - 1]
-                                                  : (const int16_t*)(ws + w.raw_off[l - 1]);
-      HookScope hs(MPV_STAGE_PROPAGATE, l, stream);
-      mpvl::propagate(prev, g.W[l - 1], g.H[l - 1], g.W[l], g.H[l], g.D[l], p->band_radius,
-                      g.cap[l], lo, stream);
-      b.lo = lo;
-    }
+    // this level's band was written by the coarser level's reduce (Section 3.4 propagation)
+    mpv_band b{l > 0 ? (const int16_t*)(ws + w.lo_off[l & 1]) : nullptr, nullptr, g.cap[l]};
     const bool last = l == L - 1;
+    NextBand nb{(int16_t*)(ws + w.lo_off[(l + 1) & 1]), 0, 0, 0, 0, 0};
+    if (!last) {
+      nb.W = g.W[l + 1];
+      nb.H = g.H[l + 1];
+      nb.D = g.D[l + 1];
+      nb.R = p->band_radius;
+      nb.cap = g.cap[l + 1];
+    }
     if (last && out->disp_raw && !out->level_raw[l]) raw = out->disp_raw;
     st = run_level(&lpar, li[l], lp[l], ri[l], rp[l], g.W[l], g.H[l], l > 0 ? &b : nullptr,
                    last ? out->disp : nullptr, last ? out->disp_right : nullptr, raw,
-                   ws + w.level_off, l, p->sched, stream);
+                   ws + w.level_off, l, p->sched, stream, last ? nullptr : &nb);
     if (st) return st;
     if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
       if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),
@@ -848,11 +855,6 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
       case mpv_batch_s::CENSUS: {
         HookScope hs(MPV_STAGE_CENSUS, ln.level, s);
         mpvl::census_batch({(const PixArgs*)desc, first, ln.nseg}, ln.units, s);
-        break;
-      }
-      case mpv_batch_s::PROP: {
-        HookScope hs(MPV_STAGE_PROPAGATE, ln.level, s);
-        mpvl::propagate_batch({(const PixArgs*)desc, first, ln.nseg}, ln.units, s);
         break;
       }
       case mpv_batch_s::SCAN_FULL: {

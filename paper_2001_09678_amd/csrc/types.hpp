@@ -58,6 +58,11 @@ struct RedArgs {
   int16_t* disp;
   int16_t* right;
   int16_t* raw;
+  // Band of the next finer level (Section 3.4), written beside the raw winner: fine pixel
+  // (fx, fy) takes this level's pixel (min(fx/2, W-1), min(fy/2, H-1)) and gets
+  // lo = clamp(2 * raw - nR, 0, nD - ncap). Null: no finer level.
+  int16_t* nlo;
+  int nW, nH, nD, nR, ncap;
 };
 
 struct PixArgs {
@@ -67,10 +72,6 @@ struct PixArgs {
   void* out[2];            // census: uint32 at y*opitch + omargin + x; downsample: uint8 [H][W]
   int opitch, omargin;
   int tiles_x, tiles;      // tiles per view
-  // propagate
-  const int16_t* coarse;
-  int Wc, Hc, Dl, R, cap;
-  int16_t* lo;
 };
 
 constexpr int RED_MAXW = 4096;
