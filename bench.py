@@ -102,12 +102,12 @@ def stage_breakdown(pyr, left, right, levels, reps=20):
     from paper_2001_09678_amd import _lib as L
     lib = L.lib()
     out = {}
-    # (the band propagation runs inside the coarser level's reduce)
-    names = {L.STAGE_DOWNSAMPLE: "downsample", L.STAGE_CENSUS: "census", L.STAGE_SCAN: "scan",
-             L.STAGE_REDUCE: "reduce"}
+    # one census launch serves every level; the band propagation runs inside the coarser
+    # level's reduce; no coarse images are built
+    names = {L.STAGE_CENSUS: "census", L.STAGE_SCAN: "scan", L.STAGE_REDUCE: "reduce"}
     for st, name in names.items():
         for l in range(levels):
-            if st == L.STAGE_DOWNSAMPLE and l == levels - 1:
+            if st == L.STAGE_CENSUS and l > 0:
                 continue
             b, a = _events(reps), _events(reps)
             torch.cuda.synchronize()
@@ -116,7 +116,8 @@ def stage_breakdown(pyr, left, right, levels, reps=20):
                 pyr(left, right)
             lib.mpv_set_timing_events(st, l, None, None)
             torch.cuda.synchronize()
-            out[f"L{l}.{name}"] = round(sum(b[i].elapsed_time(a[i]) for i in range(reps)) / reps, 4)
+            key = "census(all levels)" if st == L.STAGE_CENSUS else f"L{l}.{name}"
+            out[key] = round(sum(b[i].elapsed_time(a[i]) for i in range(reps)) / reps, 4)
     return out
 
 

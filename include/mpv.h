@@ -220,8 +220,9 @@ mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t stream);
 void mpv_batch_destroy(mpv_batch b);
 
 /* Measurement hook (per-kernel timing without a profiler). Stages of one level: */
-#define MPV_STAGE_DOWNSAMPLE 0
-#define MPV_STAGE_CENSUS 1
+#define MPV_STAGE_DOWNSAMPLE 0 /* batches only: mpv_pyramid builds no coarse images */
+#define MPV_STAGE_CENSUS 1     /* mpv_pyramid: one launch for every level, bracketed whatever
+                                  level is hooked */
 #define MPV_STAGE_SCAN 2      /* all P directions of one level, one launch */
 #define MPV_STAGE_REDUCE 3    /* sum + WTA + right disparity + LR of one level, and the band
                                  of the next finer level (Section 3.4 propagation) */

@@ -73,6 +73,10 @@ void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int
                      W, H, lo, len, cap, D, out);
 }
 
+void census_pyr(const CenPyr& cp, hipStream_t s) {
+  hipLaunchKernelGGL(k_census_pyr, dim3(cp.first[cp.L], 2), dim3(256), 0, s, cp);
+}
+
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s) {
   const int b = (int)std::min<size_t>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_fill<uint16_t>, dim3(b), dim3(256), 0, s, p, n, v);

@@ -119,6 +119,63 @@ __device__ __forceinline__ uint32_t census_at(const uint8_t* img, int W, int H, 
 }
 
 #ifdef MPV_MISC_KERNELS
+// Pixel (x, y) of the level S halvings below the input: the 2x2 rounded mean applied S
+// times (Section 3.4 pyramid), each step over the four pixels of the step below.
+template <int S>
+__device__ __forceinline__ int pyr_pixel(const uint8_t* img, int pitch, int x, int y) {
+  if constexpr (S == 0) {
+    return img[(size_t)y * pitch + x];
+  } else {
+    const int a = pyr_pixel<S - 1>(img, pitch, 2 * x, 2 * y);
+    const int b = pyr_pixel<S - 1>(img, pitch, 2 * x + 1, 2 * y);
+    const int c = pyr_pixel<S - 1>(img, pitch, 2 * x, 2 * y + 1);
+    const int d = pyr_pixel<S - 1>(img, pitch, 2 * x + 1, 2 * y + 1);
+    return (a + b + c + d + 2) >> 2;
+  }
+}
+
+// One block: a 64x4 tile of one level's census for one view (blockIdx.y). The tile's
+// pixels and a 2-pixel border (coordinates clamped to the level, as the census clamps its
+// neighbours) are built in LDS from the input, then each thread takes one census.
+__global__ __launch_bounds__(256) void k_census_pyr(CenPyr cp) {
+  __shared__ uint8_t t[8][68];
+  int l = 0;
+  while (l + 1 < cp.L && (int)blockIdx.x >= cp.first[l + 1]) ++l;
+  const int b = blockIdx.x - cp.first[l];
+  const int v = blockIdx.y;
+  const int W = cp.W[l], H = cp.H[l];
+  const int x0 = (b % cp.tiles_x[l]) * 64, y0 = (b / cp.tiles_x[l]) * 4;
+  const int s = cp.L - 1 - l;
+  const uint8_t* img = cp.img[v];
+  const int pitch = cp.pitch[v];
+  for (int i = threadIdx.x; i < 8 * 68; i += 256) {
+    const int ty = i / 68, tx = i % 68;
+    const int x = min(max(x0 + tx - 2, 0), W - 1), y = min(max(y0 + ty - 2, 0), H - 1);
+    int p;
+    if (s == 0) p = pyr_pixel<0>(img, pitch, x, y);
+    else if (s == 1) p = pyr_pixel<1>(img, pitch, x, y);
+    else if (s == 2) p = pyr_pixel<2>(img, pitch, x, y);
+    else p = pyr_pixel<3>(img, pitch, x, y);
+    t[ty][tx] = (uint8_t)p;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= W || y >= H) return;
+  const int c = t[ty + 2][tx + 2];
+  uint32_t val = 0;
+  int bit = 0;
+#pragma unroll
+  for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (dx == 0 && dy == 0) continue;
+      val |= (uint32_t)(t[ty + 2 + dy][tx + 2 + dx] < c) << bit;
+      ++bit;
+    }
+  cp.out[l][v][(size_t)y * cp.opitch[l] + cp.omargin[l] + x] = val;
+}
+
 __global__ __launch_bounds__(256) void k_cost(const uint8_t* __restrict__ L, int lpitch,
                                               const uint8_t* __restrict__ R, int rpitch, int W,
                                               int H, const int16_t* __restrict__ lo,
@@ -305,7 +362,6 @@ __device__ __forceinline__ LineAddr line_addr(const ScanArgs& a, const Line& ln)
 
 template <bool BANDED, int SRC>
 __device__ __forceinline__ uint2 load_chunk(const ScanArgs& a, const LineAddr& la, int t0, int k) {
-  const int tt = la.tt(t0 + k);
   int b0 = 0, bn = a.D;
   if constexpr (BANDED) band_at(a.lo, a.len, (size_t)la.pix(t0 + k), a.D, a.cap, b0, bn);
   const uint32_t cl = SRC == SRC_CENSUS ? ld_u32(a.cl, la.cen(t0 + k)) : 0u;

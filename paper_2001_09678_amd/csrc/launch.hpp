@@ -7,6 +7,7 @@
 
 namespace mpvl {
 using mpvk::Batch;
+using mpvk::CenPyr;
 using mpvk::PixArgs;
 using mpvk::RedArgs;
 using mpvk::ScanArgs;
@@ -39,6 +40,7 @@ void downsample(const uint8_t* in, int pitch, uint8_t* out, const uint8_t* in2, 
                 uint8_t* out2, int w, int h, hipStream_t s);
 void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int H,
           const int16_t* lo, const uint8_t* len, int cap, int D, uint8_t* cost, hipStream_t s);
+void census_pyr(const CenPyr& cp, hipStream_t s);
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s);
 void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 

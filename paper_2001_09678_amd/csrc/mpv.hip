@@ -70,9 +70,11 @@ TimingHook g_hook[MPV_NUM_STAGES];
 struct HookScope {  // records the stage's events around the launches made in its lifetime
   const TimingHook* h;
   hipStream_t s;
+  // level ALL_LEVELS: one launch that serves every level, bracketed whatever level is hooked
+  static constexpr int ALL_LEVELS = -2;
   HookScope(int stage, int level, hipStream_t st) : h(nullptr), s(st) {
     const TimingHook& t = g_hook[stage];
-    if (t.before && (t.level == -1 || t.level == level)) {
+    if (t.before && (t.level == -1 || t.level == level || level == ALL_LEVELS)) {
       h = &t;
       (void)hipEventRecord(t.before, s);
     }
@@ -171,7 +173,10 @@ struct LevelWs {
   bool fits;
 };
 
-LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const mpv_schedule& s) {
+// own_census: the level workspace holds the census of both views (false when the caller
+// computed them elsewhere in the same layout).
+LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const mpv_schedule& s,
+                 bool own_census = true) {
   LevelWs w{};
   w.sc = choose_scan(p->num_disp, band, p->tau, s);
   // left census margin: covers x - d for every lane of a full-range (padded range) or
@@ -180,7 +185,7 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const 
   w.cpitch = w.cmargin + W;
   w.census_off = 0;
   const size_t cen = align_up((size_t)H * w.cpitch * sizeof(uint32_t));
-  w.part_off = w.census_off + 2 * cen;
+  w.part_off = w.census_off + (own_census ? 2 * cen : 0);
   // partial volumes, then a 256 B sink for stores past a line's end
   w.total = w.part_off + align_up((size_t)p->num_paths * H * W * w.sc.capP) + ALIGN;
   w.fits = (size_t)H * W * w.sc.capP <= 0x7FFFFFFFu && cen <= 0x7FFFFFFFu && H <= MPV_MAX_HEIGHT;
@@ -252,10 +257,14 @@ RedArgs level_red_args(const mpv_params* p, const ScanArgs& a, const LevelWs& lw
 mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const uint8_t* R,
                      int rpitch, int W, int H, const mpv_band* band, int16_t* disp,
                      int16_t* right, int16_t* raw, uint8_t* ws, int level,
-                     const mpv_schedule& sched, hipStream_t s, const NextBand* nb = nullptr) {
-  const LevelWs lw = level_ws(p, W, H, band, sched);
+                     const mpv_schedule& sched, hipStream_t s, const NextBand* nb = nullptr,
+                     uint32_t* const* cen = nullptr) {
+  const LevelWs lw = level_ws(p, W, H, band, sched, cen == nullptr);
   ScanArgs a = level_scan_args(p, W, H, band, lw, ws);
-  {
+  if (cen) {  // census computed beforehand, in the same layout (cpitch, cmargin)
+    a.cl = cen[0];
+    a.cr = cen[1];
+  } else {
     HookScope hs(MPV_STAGE_CENSUS, level, s);
     mpvl::census(L, lpitch, R, rpitch, W, H, (uint32_t*)a.cl, (uint32_t*)a.cr, lw.cpitch,
                  lw.cmargin, s);
@@ -310,6 +319,8 @@ struct PyrWs {
   size_t img_off[MPV_MAX_LEVELS];  // left at off, right at off + W*H
   size_t raw_off[MPV_MAX_LEVELS];
   size_t lo_off[2];  // band starts: level l reads buffer l & 1, its reduce writes the other
+  size_t cen_off[MPV_MAX_LEVELS];  // mpv_pyramid: census of both views of every level
+  int cpitch[MPV_MAX_LEVELS], cmargin[MPV_MAX_LEVELS];
   size_t level_off;  // census + partials, reused per level
   size_t total;
 };
@@ -320,10 +331,12 @@ mpv_params level_params(const mpv_pyramid_params* p, int Dl) {
   return lp;
 }
 
-PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g) {
+// fused_census (mpv_pyramid): the census of every level is computed up front from the input
+// (no coarse images are kept); otherwise (batches) coarse images and per-level census.
+PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g, bool fused_census = false) {
   PyrWs w{};
   size_t off = 0;
-  for (int l = 0; l + 1 < g.L; ++l) {
+  for (int l = 0; l + 1 < g.L && !fused_census; ++l) {
     w.img_off[l] = off;
     off += align_up((size_t)2 * g.W[l] * g.H[l]);
   }
@@ -335,15 +348,22 @@ PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g) {
     w.lo_off[k] = off;
     off += align_up((size_t)g.W[g.L - 1] * g.H[g.L - 1] * sizeof(int16_t));
   }
-  w.level_off = off;
   size_t lvl = 0;
   for (int l = 0; l < g.L; ++l) {
     const mpv_params lp = level_params(p, g.D[l]);
     mpv_band b{nullptr, nullptr, g.cap[l]};
     int16_t dummy;
     if (l > 0) b.lo = &dummy;  // only presence matters for sizing
-    lvl = std::max(lvl, level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched).total);
+    const LevelWs lw = level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched, !fused_census);
+    lvl = std::max(lvl, lw.total);
+    if (fused_census) {
+      w.cen_off[l] = off;
+      w.cpitch[l] = lw.cpitch;
+      w.cmargin[l] = lw.cmargin;
+      off += 2 * align_up((size_t)g.H[l] * lw.cpitch * sizeof(uint32_t));
+    }
   }
+  w.level_off = off;
   w.total = off + lvl;
   return w;
 }
@@ -722,7 +742,7 @@ mpv_status mpv_match(const mpv_params* p, const mpv_image* left, const mpv_image
 size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params* p, int32_t W, int32_t H) {
   PyrGeom g;
   if (!p || pyr_geom(p, p->base.num_disp, W, H, g)) return 0;
-  return pyr_ws(p, g).total;
+  return pyr_ws(p, g, true).total;
 }
 
 mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
@@ -734,26 +754,37 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
   PyrGeom g;
   mpv_status st = pyr_geom(p, p->base.num_disp, left->width, left->height, g);
   if (st) return st;
-  const PyrWs w = pyr_ws(p, g);
+  const PyrWs w = pyr_ws(p, g, true);
   if (!workspace || workspace_bytes < w.total) return MPV_ERR_WORKSPACE;
   uint8_t* ws = (uint8_t*)workspace;
   const int L = g.L;
-  // image pyramid, finest to coarsest
-  const uint8_t* li[MPV_MAX_LEVELS];
-  const uint8_t* ri[MPV_MAX_LEVELS];
-  int lp[MPV_MAX_LEVELS], rp[MPV_MAX_LEVELS];
-  li[L - 1] = left->data;
-  ri[L - 1] = right->data;
-  lp[L - 1] = left->pitch;
-  rp[L - 1] = right->pitch;
-  for (int l = L - 2; l >= 0; --l) {
-    uint8_t* dl = ws + w.img_off[l];
-    uint8_t* dr = dl + (size_t)g.W[l] * g.H[l];
-    HookScope hs(MPV_STAGE_DOWNSAMPLE, l, stream);
-    mpvl::downsample(li[l + 1], lp[l + 1], dl, ri[l + 1], rp[l + 1], dr, g.W[l], g.H[l], stream);
-    li[l] = dl;
-    ri[l] = dr;
-    lp[l] = rp[l] = g.W[l];
+  // census of every level of both views, built from the input in one launch
+  CenPyr cp{};
+  cp.img[0] = left->data;
+  cp.img[1] = right->data;
+  cp.pitch[0] = left->pitch;
+  cp.pitch[1] = right->pitch;
+  cp.L = L;
+  uint32_t* cen[MPV_MAX_LEVELS][2];
+  int blocks = 0;
+  for (int l = 0; l < L; ++l) {
+    cp.W[l] = g.W[l];
+    cp.H[l] = g.H[l];
+    const size_t view = align_up((size_t)g.H[l] * w.cpitch[l] * sizeof(uint32_t));
+    cen[l][0] = (uint32_t*)(ws + w.cen_off[l]);
+    cen[l][1] = (uint32_t*)(ws + w.cen_off[l] + view);
+    cp.out[l][0] = cen[l][0];
+    cp.out[l][1] = cen[l][1];
+    cp.opitch[l] = w.cpitch[l];
+    cp.omargin[l] = w.cmargin[l];
+    cp.tiles_x[l] = (g.W[l] + 63) / 64;
+    cp.first[l] = blocks;
+    blocks += cp.tiles_x[l] * ((g.H[l] + 3) / 4);
+  }
+  cp.first[L] = blocks;
+  {
+    HookScope hs(MPV_STAGE_CENSUS, HookScope::ALL_LEVELS, stream);
+    mpvl::census_pyr(cp, stream);
   }
   for (int l = 0; l < L; ++l) {
     int16_t* raw = out->level_raw[l] ? out->level_raw[l] : (int16_t*)(ws + w.raw_off[l]);
@@ -770,9 +801,9 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
       nb.cap = g.cap[l + 1];
     }
     if (last && out->disp_raw && !out->level_raw[l]) raw = out->disp_raw;
-    st = run_level(&lpar, li[l], lp[l], ri[l], rp[l], g.W[l], g.H[l], l > 0 ? &b : nullptr,
+    st = run_level(&lpar, nullptr, 0, nullptr, 0, g.W[l], g.H[l], l > 0 ? &b : nullptr,
                    last ? out->disp : nullptr, last ? out->disp_right : nullptr, raw,
-                   ws + w.level_off, l, p->sched, stream, last ? nullptr : &nb);
+                   ws + w.level_off, l, p->sched, stream, last ? nullptr : &nb, cen[l]);
     if (st) return st;
     if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
       if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),

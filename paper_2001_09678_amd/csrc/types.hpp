@@ -74,6 +74,18 @@ struct PixArgs {
   int tiles_x, tiles;      // tiles per view
 };
 
+// Census of every pyramid level of both views in one launch (level L-1 = the input).
+struct CenPyr {
+  const uint8_t* img[2];  // input images (finest level)
+  int pitch[2];
+  int L;
+  int W[4], H[4];
+  uint32_t* out[4][2];  // census of level l, view v: uint32 at y*opitch + omargin + x
+  int opitch[4], omargin[4];
+  int tiles_x[4];
+  int first[5];  // first block of each level (64x4 outputs per block)
+};
+
 constexpr int RED_MAXW = 4096;
 
 }  // namespace mpvk
