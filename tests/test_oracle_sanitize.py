@@ -1,0 +1,24 @@
+"""The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only): a C driver
+(tests/sanitize_oracle.c) runs every oracle function on small random inputs, including odd
+sizes, random bands and every number of paths, and checks fast == definition transitions."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_oracle_clean_under_asan_ubsan(tmp_path):
+    exe = str(tmp_path / "sanitize_oracle")
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-o", exe, os.path.join(HERE, "sanitize_oracle.c"),
+           os.path.join(ROOT, "oracle", "mpv_oracle.c")]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    res = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert res.stdout.strip().endswith("ok")
