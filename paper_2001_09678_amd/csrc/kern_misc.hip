@@ -1,5 +1,5 @@
-// Per-pixel kernels (census, downsample, cost export, band propagation, fill) and the
-// reduce kernels.
+// Per-pixel kernels (census, the all-level census of a pyramid, downsample, cost export,
+// fill) and the reduce kernels (which also write the next level's band).
 #define MPV_MISC_KERNELS
 #include "kernels.hpp"
 #include "launch.hpp"

@@ -14,8 +14,11 @@
 // the decomposition of Section 3.3: the envelope of lambda*|d-d'| is built by sweeps
 // along the disparity axis (here as doubling steps s = 1, 2, 4, ... so that a window of
 // tau-1 neighbours takes log2(tau) cross-lane steps), and the truncation at tau is one
-// more candidate, the previous minimum plus lambda*tau. Energies are kept normalised
-// (previous minimum subtracted), so that minimum is 0 and the candidate is lambda*tau.
+// more candidate, the previous minimum plus lambda*tau. Full-range scans keep their packed
+// 16-bit energies normalised (previous minimum subtracted, so the candidate is lambda*tau);
+// banded scans keep unnormalised 32-bit energies and take the candidate from the previous
+// pixel's minimum, computed beside the next step instead of on its dependent chain. The
+// stored partials are always the energy minus the pixel's minimum over its disparities.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

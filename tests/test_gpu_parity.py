@@ -205,7 +205,7 @@ def test_fused_match_banded(mpv, orc, cap, varlen, tau):
 
 @pytest.mark.parametrize("w,h,D,levels,R,P", [
     (160, 96, 64, 3, 4, 8), (97, 61, 48, 2, 4, 4), (130, 70, 128, 3, 2, 8), (64, 40, 32, 3, 64, 8),
-    (200, 120, 256, 3, 4, 4), (50, 30, 40, 4, 4, 2),
+    (200, 120, 256, 3, 4, 4), (50, 30, 40, 4, 4, 2), (23, 11, 16, 3, 4, 8), (8, 8, 8, 4, 1, 1),
 ])
 def test_fused_pyramid(mpv, orc, w, h, D, levels, R, P):
     _log("pyramid", w, h, D, levels, R, P)
