@@ -142,7 +142,26 @@ def stream_bench(params, levels, dev, sched, steps, frames=16):
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[steps]) / steps
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
-    return {"frames_per_launch": frames, "ms_per_launch": round(ms, 4),
+    # the finest level's scans of all frames (batched launches), timed by the stage hook
+    from paper_2001_09678_amd import _lib as L
+    lib = L.lib()
+    kb, ka = _events(steps), _events(steps)
+    torch.cuda.synchronize()
+    for i in range(steps):
+        lib.mpv_set_timing_events(L.STAGE_SCAN, levels - 1, kb[i].cuda_event, ka[i].cuda_event)
+        b.run()
+    lib.mpv_set_timing_events(L.STAGE_SCAN, levels - 1, None, None)
+    torch.cuda.synchronize()
+    scan_ms = sum(kb[i].elapsed_time(ka[i]) for i in range(steps)) / steps
+    P = params.num_paths
+    scan_bytes = frames * (P * 1280 * 720 * 9 + 2 * 4 * 1280 * 720)
+    scan_ops = frames * OPS_PER_NODE_PATH * P * 1280 * 720 * 9
+    roof = {"kernel": "k_scan_band_batch (finest level of every frame)", "kernel_ms": round(scan_ms, 4),
+            "hbm": {"achieved": round(scan_bytes / (scan_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(scan_bytes / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "alu": {"achieved": round(scan_ops / (scan_ms * 1e-3) / 1e12, 2), "peak": round(ALU_PEAK_TOPS, 1),
+                    "unit": "Tops/s", "frac": round(scan_ops / (scan_ms * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4)}}
+    return {"frames_per_launch": frames, "ms_per_launch": round(ms, 4), "finest_scan_roofline": roof,
             "fps": round(frames / ms * 1e3, 1), "value": round(frames * 1280 * 720 * 128 / (ms * 1e-3) / 1e6, 1),
             "unit": "Mde/s", "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
             "note": "throughput with frames in flight; the headline value is one frame per step"}
