@@ -24,9 +24,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-command-line-argument"]
 
 
+# Per-file code-generation choices, each measured on the GPU against the default: the
+# full-range scans schedule best with the backend's iterative ILP strategy (about 2.5 %
+# faster plain single-scale frames); the banded scans are fastest with the default.
+FILE_FLAGS = {
+    "kern_full.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "kern_full_batch.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+}
+
+
 def _compile(src: str) -> tuple[str, str]:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    res = subprocess.run([HIPCC, *FLAGS, "-c", "-o", obj, src], capture_output=True, text=True)
+    extra = FILE_FLAGS.get(os.path.basename(src), [])
+    res = subprocess.run([HIPCC, *FLAGS, *extra, "-c", "-o", obj, src], capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{res.stdout}{res.stderr}")
     return obj, res.stderr
