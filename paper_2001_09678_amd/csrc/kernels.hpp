@@ -739,8 +739,11 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
       const uint32_t off = splat16(m);
 #pragma unroll
       for (int q = 0; q < K; ++q) {
-        P[q] = pk_add_i(L[q], off);              // next state, complement encoded
-        L[q] = pk_sub_i(INF2, L[q]);             // energies relative to the previous minimum
+        P[q] = pk_add_i(L[q], off);  // next state, complement encoded
+        if constexpr (OUT == OUT_PART)
+          L[q] = pk_sub_i(splat16((uint32_t)mu), L[q]);  // energy minus the line minimum
+        else
+          L[q] = pk_sub_i(INF2, L[q]);  // energies relative to the previous minimum
       }
     } else {
       uint32_t E[K];
@@ -761,7 +764,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
       uint32_t v = 0;
 #pragma unroll
       for (int q = 0; q < K; ++q) {
-        const uint32_t nq = TAU > 0 ? pk_sub(L[q], splat16(m)) : P[q];  // L - min, >= 0
+        const uint32_t nq = TAU > 0 ? L[q] : P[q];  // L - min, >= 0
         const uint32_t c = pk_min(nq, 0x00FF00FFu);
         v |= __builtin_amdgcn_perm(0u, c, 0x0c0c0200u) << (16 * q);
       }
