@@ -8,7 +8,8 @@ The arithmetic lives in ``mpv_oracle.c`` (plain C, int64, OpenMP over independen
 lines); this file builds it with gcc, binds it with ctypes and composes the steps of the
 multi-scale pipeline (Section 3.4) in the paper's order: pyramid, per-level cost,
 per-path Viterbi energies (Section 3.2, eq. e(p,u); Section 3.3 fast technique), their
-sum, winner-take-all, left-right check, then the band for the next level.
+sum or the paper's layered merge (Section 3.2, Table alg), winner-take-all, left-right
+check, then the band for the next level.
 """
 from __future__ import annotations
 
@@ -59,6 +60,8 @@ def _load():
         lib.orc_aggregate.argtypes = [P, i32, i32, i32, P, P, i32, i32, C.c_uint32, i32, i32, i32,
                                       P, P, P]
         lib.orc_aggregate.restype = i32
+        lib.orc_layered.argtypes = [P, i32, i32, i32, P, P, i32, i32, i32, i32, i32, i32, P, P]
+        lib.orc_layered.restype = i32
         lib.orc_wta_lr.argtypes = [P, i32, i32, i32, P, P, i32, i32, P, P, P]
         lib.orc_propagate.argtypes = [P, i32, i32, i32, i32, i32, i32, P]
         lib.orc_propagate.restype = i32
@@ -125,6 +128,23 @@ def aggregate(cost_vol, num_disp, num_paths, lam, tau, lo=None, length=None, pat
     return (S, pp) if per_path else S
 
 
+def layered(cost_vol, num_disp, num_layers, lam, tau, lo=None, length=None, occ=False, mode=FAST,
+            per_layer=False):
+    """The paper's hierarchical merge (Section 3.2, Table alg): layer k merges directions
+    2k and 2k+1 over the previous layer's merged energy (the cost for k = 0); min for the
+    horizontal layer, floor mean for the others. Returns M [H][W][cap] (int64, absent
+    slots INF), and every layer's merged energies when per_layer."""
+    cost_vol = _c(cost_vol, np.uint8)
+    h, w, cap = cost_vol.shape
+    lo, length = _c(lo, np.int16), _c(length, np.uint8)
+    M = np.empty((h, w, cap), np.int64)
+    pl = np.zeros((num_layers, h, w, cap), np.int64) if per_layer else None
+    rc = _load().orc_layered(_p(cost_vol), w, h, num_disp, _p(lo), _p(length), cap, num_layers, lam,
+                             tau, 1 if occ else 0, mode, _p(M), _p(pl))
+    assert rc == 0
+    return (M, pl) if per_layer else M
+
+
 def wta_lr(S, num_disp, lr_max_diff, lo=None, length=None):
     S = _c(S, np.int64)
     h, w, cap = S.shape
@@ -165,11 +185,15 @@ class LevelResult:
 
 
 def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4,
-            lr_max_diff=1, mode=FAST, keep_sums=False, bands=None):
+            lr_max_diff=1, mode=FAST, keep_sums=False, bands=None, merge="sum", occ=False):
     """Multi-scale MPV (Section 3.4). Level 0 is the coarsest and searches its full range;
     every finer level searches the band propagated from the level above. ``levels=1`` is
     plain single-scale MPV. ``bands`` optionally replaces the finest level's band by a
-    given (lo, len, cap) triple (the learned-band path)."""
+    given (lo, len, cap) triple (the learned-band path). ``merge`` = "sum" sums the
+    ``num_paths`` directed paths; "layered" runs num_paths / 2 layers of the paper's
+    hierarchical merge (``occ``: its occlusion strategy) and takes decisions on the last
+    layer's merged energies."""
+    assert merge in ("sum", "layered")
     imgs = [_c(left, np.uint8)], [_c(right, np.uint8)]
     for _ in range(levels - 1):
         imgs[0].insert(0, downsample(imgs[0][0]))
@@ -190,7 +214,10 @@ def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4
             lo, length, cap = bands
         cl, cr = census(L_img), census(R_img)
         cv = cost(cl, cr, Dl, lo, length, cap)
-        S = aggregate(cv, Dl, num_paths, lam, tau, lo, length, mode=mode)
+        if merge == "sum":
+            S = aggregate(cv, Dl, num_paths, lam, tau, lo, length, mode=mode)
+        else:
+            S = layered(cv, Dl, num_paths // 2, lam, tau, lo, length, occ=occ, mode=mode)
         dl, dr, out = wta_lr(S, Dl, lr_max_diff, lo, length)
         results.append(LevelResult(w, h, Dl, cap, lo, dl, dr, out, S if keep_sums else None))
     return results

@@ -25,6 +25,13 @@
  *                    untruncated L1 envelope; truncation adds one extra candidate
  *                    (the previous pixel's minimum plus lambda*tau). Exactly equal to
  *                    the definition.
+ *
+ * Two ways of merging the directed paths:
+ *   orc_aggregate  - the sum S(p,d) = sum_r L_r(p,d) over the selected paths.
+ *   orc_layered    - the paper's hierarchical merge (Section 3.2, Table alg): four layers
+ *                    of opposite direction pairs, each pair merged per node (min for the
+ *                    horizontal layer, the mean for the others) and passed to the next
+ *                    layer as its data term, so the recurrence also runs over int64 data.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -119,15 +126,19 @@ void orc_cost(const uint32_t *cl, const uint32_t *cr, int W, int H,
         }
 }
 
-static int64_t trans(int d, int dp, int lambda, int tau)
+/* Transition weight from disparity dp at p-r to d at p. up multiplies the weight of an
+ * increase of disparity (dp < d); it is 1 except in the left-to-right pass of the layered
+ * merge with the occlusion strategy (orc_layered). */
+static int64_t trans(int d, int dp, int lambda, int tau, int up)
 {
     int a = d > dp ? d - dp : dp - d;
-    return (int64_t)lambda * (a < tau ? a : tau);
+    return (int64_t)(d > dp ? up : 1) * lambda * (a < tau ? a : tau);
 }
 
-/* One pixel of the directed recurrence. prevL/prev band describe p-r; out is L(p, .). */
-static void step_definition(const uint8_t *c, int b0, int bn, const int64_t *prevL, int q0, int qn,
-                            int lambda, int tau, int64_t *out, int cap)
+/* One pixel of the directed recurrence. c is the pixel's data term over its band slots;
+ * prevL/prev band describe p-r; out is L(p, .). */
+static void step_definition(const int64_t *c, int b0, int bn, const int64_t *prevL, int q0, int qn,
+                            int lambda, int tau, int up, int64_t *out, int cap)
 {
     for (int j = 0; j < cap; ++j)
         out[j] = ORC_INF;
@@ -135,80 +146,89 @@ static void step_definition(const uint8_t *c, int b0, int bn, const int64_t *pre
         int d = b0 + j;
         int64_t best = ORC_INF;
         for (int k = 0; k < qn; ++k) {
-            int64_t v = prevL[k] + trans(d, q0 + k, lambda, tau);
+            int64_t v = prevL[k] + trans(d, q0 + k, lambda, tau, up);
             if (v < best)
                 best = v;
         }
-        out[j] = (int64_t)c[j] + best;
+        out[j] = c[j] + best;
     }
 }
 
 /* Section 3.3: instead of comparing every predecessor node, sweep the disparity axis
- * once upward and once downward. E_up(u) = min(E(p-1,u), E_up(u-1) + lambda) carries the
- * best predecessor below u, E_dn(u) = min(E(p-1,u), E_dn(u+1) + lambda) the best one above.
- * With truncation at tau, every predecessor further than tau costs the same lambda*tau,
- * so the previous minimum plus lambda*tau is the last candidate. scratch holds 3*D. */
-static void step_fast(const uint8_t *c, int b0, int bn, const int64_t *prevL, int q0, int qn,
-                      int lambda, int tau, int D, int64_t *out, int cap, int64_t *scratch)
+ * once upward and once downward. E_up(u) = min(E(p-1,u), E_up(u-1) + up*lambda) carries
+ * the best predecessor below u, E_dn(u) = min(E(p-1,u), E_dn(u+1) + lambda) the best one
+ * above. With truncation at tau every predecessor at least tau below u costs up*lambda*tau
+ * and every one at least tau above costs lambda*tau, so the minima of the predecessors at
+ * or below u (plus up*lambda*tau) and at or above u (plus lambda*tau) are the last two
+ * candidates; for up = 1 both reduce to the previous minimum plus lambda*tau.
+ * scratch holds 5*D. */
+static void step_fast(const int64_t *c, int b0, int bn, const int64_t *prevL, int q0, int qn,
+                      int lambda, int tau, int up, int D, int64_t *out, int cap, int64_t *scratch)
 {
-    int64_t *A = scratch, *up = scratch + D, *dn = scratch + 2 * D;
-    int64_t m = ORC_INF;
+    int64_t *A = scratch, *upE = scratch + D, *dnE = scratch + 2 * D;
+    int64_t *pre = scratch + 3 * D, *suf = scratch + 4 * D;
     for (int u = 0; u < D; ++u)
         A[u] = ORC_INF;
-    for (int k = 0; k < qn; ++k) {
+    for (int k = 0; k < qn; ++k)
         A[q0 + k] = prevL[k];
-        if (prevL[k] < m)
-            m = prevL[k];
-    }
-    up[0] = A[0];
+    upE[0] = A[0];
+    pre[0] = A[0];
     for (int u = 1; u < D; ++u) {
-        int64_t t = up[u - 1] + lambda;
-        up[u] = A[u] < t ? A[u] : t;
+        int64_t t = upE[u - 1] + (int64_t)up * lambda;
+        upE[u] = A[u] < t ? A[u] : t;
+        pre[u] = A[u] < pre[u - 1] ? A[u] : pre[u - 1];
     }
-    dn[D - 1] = A[D - 1];
+    dnE[D - 1] = A[D - 1];
+    suf[D - 1] = A[D - 1];
     for (int u = D - 2; u >= 0; --u) {
-        int64_t t = dn[u + 1] + lambda;
-        dn[u] = A[u] < t ? A[u] : t;
+        int64_t t = dnE[u + 1] + lambda;
+        dnE[u] = A[u] < t ? A[u] : t;
+        suf[u] = A[u] < suf[u + 1] ? A[u] : suf[u + 1];
     }
-    int64_t trunc = m + (int64_t)lambda * tau;
     for (int j = 0; j < cap; ++j)
         out[j] = ORC_INF;
     for (int j = 0; j < bn; ++j) {
         int u = b0 + j;
-        int64_t h = up[u] < dn[u] ? up[u] : dn[u];
-        if (trunc < h)
-            h = trunc;
-        out[j] = (int64_t)c[j] + h;
+        int64_t h = upE[u] < dnE[u] ? upE[u] : dnE[u];
+        int64_t t1 = pre[u] + (int64_t)up * lambda * tau, t2 = suf[u] + (int64_t)lambda * tau;
+        if (t1 < h)
+            h = t1;
+        if (t2 < h)
+            h = t2;
+        out[j] = c[j] + h;
     }
 }
 
 /* L(p, .) for one pixel i whose predecessor along the path is q (q < 0: none). */
-static void path_pixel(const uint8_t *cost, int D, const int16_t *lo, const uint8_t *len, int cap,
-                       long i, long q, int lambda, int tau, int mode, int64_t *L, int64_t *scratch)
+static void path_pixel(const int64_t *data, int D, const int16_t *lo, const uint8_t *len, int cap,
+                       long i, long q, int lambda, int tau, int up, int mode, int64_t *L,
+                       int64_t *scratch)
 {
     int b0, bn;
     band_of(lo, len, cap, i, &b0, &bn);
     if (q < 0) {
         for (int j = 0; j < cap; ++j)
-            L[i * cap + j] = j < bn ? (int64_t)cost[i * cap + j] : ORC_INF;
+            L[i * cap + j] = j < bn ? data[i * cap + j] : ORC_INF;
         return;
     }
     int q0, qn;
     band_of(lo, len, cap, q, &q0, &qn);
     if (mode == ORC_DEFINITION)
-        step_definition(cost + i * cap, b0, bn, L + q * cap, q0, qn, lambda, tau, L + i * cap, cap);
+        step_definition(data + i * cap, b0, bn, L + q * cap, q0, qn, lambda, tau, up, L + i * cap,
+                        cap);
     else
-        step_fast(cost + i * cap, b0, bn, L + q * cap, q0, qn, lambda, tau, D, L + i * cap, cap,
+        step_fast(data + i * cap, b0, bn, L + q * cap, q0, qn, lambda, tau, up, D, L + i * cap, cap,
                   scratch);
 }
 
-/* Energies of one directed path r over the whole image, L[H][W][cap].
+/* Energies of one directed path r over the whole image, L[H][W][cap], for an int64 data
+ * term data[H][W][cap] (slot j of pixel p = disparity lo(p)+j).
  * Pixels are visited in an order where p-r always comes first. A horizontal path is a
  * set of independent rows (done in parallel); for the other directions every pixel of
  * a row depends only on the previous row in scan order, so a row is done in parallel
  * after the one before it. Returns 0, or -1 on bad arguments. */
-int orc_path(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
-             int cap, int r, int lambda, int tau, int mode, int64_t *L)
+static int path_run(const int64_t *data, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                    int cap, int r, int lambda, int tau, int up, int mode, int64_t *L)
 {
     if (r < 0 || r > 7 || W <= 0 || H <= 0 || cap <= 0 || D <= 0)
         return -1;
@@ -216,14 +236,14 @@ int orc_path(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const 
     if (dy == 0) {
 #pragma omp parallel
         {
-            int64_t *scratch = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)D);
+            int64_t *scratch = (int64_t *)malloc(sizeof(int64_t) * 5 * (size_t)D);
 #pragma omp for schedule(static)
             for (int y = 0; y < H; ++y)
                 for (int s = 0; s < W; ++s) {
                     int x = dx > 0 ? s : W - 1 - s;
                     int px = x - dx;
                     long q = (px < 0 || px >= W) ? -1 : (long)y * W + px;
-                    path_pixel(cost, D, lo, len, cap, (long)y * W + x, q, lambda, tau, mode, L,
+                    path_pixel(data, D, lo, len, cap, (long)y * W + x, q, lambda, tau, up, mode, L,
                                scratch);
                 }
             free(scratch);
@@ -235,18 +255,33 @@ int orc_path(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const 
         int py = y - dy;
 #pragma omp parallel
         {
-            int64_t *scratch = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)D);
+            int64_t *scratch = (int64_t *)malloc(sizeof(int64_t) * 5 * (size_t)D);
 #pragma omp for schedule(static)
             for (int x = 0; x < W; ++x) {
                 int px = x - dx;
                 long q = (py < 0 || py >= H || px < 0 || px >= W) ? -1 : (long)py * W + px;
-                path_pixel(cost, D, lo, len, cap, (long)y * W + x, q, lambda, tau, mode, L,
+                path_pixel(data, D, lo, len, cap, (long)y * W + x, q, lambda, tau, up, mode, L,
                            scratch);
             }
             free(scratch);
         }
     }
     return 0;
+}
+
+/* Energies of one directed path r over the matching cost volume cost[H][W][cap]. */
+int orc_path(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+             int cap, int r, int lambda, int tau, int mode, int64_t *L)
+{
+    long n = (long)W * H * cap;
+    if (W <= 0 || H <= 0 || cap <= 0)
+        return -1;
+    int64_t *data = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (long i = 0; i < n; ++i)
+        data[i] = cost[i];
+    int rc = path_run(data, W, H, D, lo, len, cap, r, lambda, tau, 1, mode, L);
+    free(data);
+    return rc;
 }
 
 /* Sum of the directed-path energies: S(p,d) = sum over the selected paths of L_r(p,d).
@@ -278,6 +313,69 @@ int orc_aggregate(const uint8_t *cost, int W, int H, int D, const int16_t *lo, c
             memcpy(per_path + (long)r * n, Lscratch, sizeof(int64_t) * (size_t)n);
     }
     return 0;
+}
+
+/* Layered merge of bi-directional paths (Section 3.2, the hierarchical merging of the
+ * paths and Table alg). Layer k = 0 .. num_layers-1 runs the two opposite directions 2k
+ * and 2k+1 of the table's order (left/right, up/down, the two diagonals) over a data
+ * term: the matching cost for the first layer, the previous layer's merged energy for the
+ * others (the current layer's node energies seed the next layer). Each direction's
+ * energies are taken relative to the pixel's minimum over its band,
+ *   Fh(p,d) = F(p,d) - min_d' F(p,d'),  Bh(p,d) = B(p,d) - min_d' B(p,d'),
+ * and merged per node: the horizontal layer keeps min(Fh, Bh) (sharpens edges), the
+ * others floor((Fh + Bh) / 2) (the mean, removes noise). occ != 0 applies the example
+ * strategy for occluded areas: the left-to-right pass (direction 0) pays twice the
+ * transition weight when the disparity increases. M[H][W][cap] receives the last layer's
+ * merged energies (absent slots ORC_INF); per_layer, when non-NULL, receives layer k's at
+ * per_layer + k*H*W*cap. Returns 0, or -1 on bad arguments. */
+int orc_layered(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                int cap, int num_layers, int lambda, int tau, int occ, int mode, int64_t *M,
+                int64_t *per_layer)
+{
+    long npx = (long)W * H, n = npx * cap;
+    if (num_layers < 1 || num_layers > 4 || W <= 0 || H <= 0 || cap <= 0)
+        return -1;
+    int64_t *data = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *B = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (long i = 0; i < n; ++i)
+        data[i] = cost[i];
+    int rc = 0;
+    for (int k = 0; k < num_layers && rc == 0; ++k) {
+        rc = path_run(data, W, H, D, lo, len, cap, 2 * k, lambda, tau, (occ && k == 0) ? 2 : 1,
+                      mode, F);
+        if (rc == 0)
+            rc = path_run(data, W, H, D, lo, len, cap, 2 * k + 1, lambda, tau, 1, mode, B);
+        if (rc)
+            break;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < npx; ++i) {
+            int b0, bn;
+            band_of(lo, len, cap, i, &b0, &bn);
+            int64_t fm = ORC_INF, bm = ORC_INF;
+            for (int j = 0; j < bn; ++j) {
+                if (F[i * cap + j] < fm)
+                    fm = F[i * cap + j];
+                if (B[i * cap + j] < bm)
+                    bm = B[i * cap + j];
+            }
+            for (int j = 0; j < cap; ++j) {
+                int64_t v = ORC_INF;
+                if (j < bn) {
+                    int64_t f = F[i * cap + j] - fm, b = B[i * cap + j] - bm;
+                    v = k == 0 ? (f < b ? f : b) : (f + b) / 2;
+                }
+                M[i * cap + j] = v;
+            }
+        }
+        if (per_layer)
+            memcpy(per_layer + (long)k * n, M, sizeof(int64_t) * (size_t)n);
+        memcpy(data, M, sizeof(int64_t) * (size_t)n);
+    }
+    free(data);
+    free(F);
+    free(B);
+    return rc;
 }
 
 /* Winner-take-all and left-right check.

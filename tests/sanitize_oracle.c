@@ -1,9 +1,9 @@
 /* Test driver for the oracle under AddressSanitizer and UndefinedBehaviorSanitizer.
  *
  * Runs every oracle function on small random inputs (odd sizes, full range and random
- * bands, both transition modes, every number of paths) so that the sanitizers see each
- * code path; also checks that the fast transition equals the definition (Section 3.3)
- * on every input. Exit status 0 on success. Built and run by tests/test_oracle_sanitize.py;
+ * bands, both transition modes, every number of paths, the layered merge with and
+ * without its occlusion weight) so that the sanitizers see each code path; also checks
+ * that the fast transition equals the definition (Section 3.3) on every input. Exit status 0 on success. Built and run by tests/test_oracle_sanitize.py;
  * test infrastructure only. */
 #include <stdint.h>
 #include <stdio.h>
@@ -21,6 +21,9 @@ void orc_wta_lr(const int64_t *S, int W, int H, int D, const int16_t *lo, const 
                 int cap, int lr_max_diff, int16_t *dl_out, int16_t *dr_out, int16_t *out);
 int orc_propagate(const int16_t *dl_coarse, int Wc, int Hc, int W, int H, int Dl, int R,
                   int16_t *lo);
+int orc_layered(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                int cap, int num_layers, int lambda, int tau, int occ, int mode, int64_t *M,
+                int64_t *per_layer);
 
 static uint64_t rng = 0x9E3779B97F4A7C15ull;
 static uint32_t next(void) {
@@ -67,6 +70,16 @@ static int run(int W, int H, int D, int banded, int paths, int tau) {
             bad = 1;
             break;
         }
+    /* layered merge: both transition modes agree, with and without the occlusion weight */
+    for (int occ = 0; occ < 2; ++occ) {
+        if (orc_layered(cost, W, H, D, lo, len, cap, 4, 8, tau, occ, 0, S0, per)) bad = 1;
+        if (orc_layered(cost, W, H, D, lo, len, cap, 4, 8, tau, occ, 1, S1, NULL)) bad = 1;
+        for (long i = 0; i < n * cap; ++i)
+            if (S0[i] != S1[i]) {
+                bad = 1;
+                break;
+            }
+    }
     int16_t *dl = malloc(sizeof(int16_t) * n), *dr = malloc(sizeof(int16_t) * n);
     int16_t *out = malloc(sizeof(int16_t) * n);
     orc_wta_lr(S1, W, H, D, lo, len, cap, 1, dl, dr, out);
