@@ -50,6 +50,22 @@ typedef enum {
 #define MPV_AGG_U16 0
 #define MPV_AGG_I32 1
 
+/* Path merge (mpv_params.merge).
+ * MPV_MERGE_SUM: S(p,d) = the sum of the num_paths directed-path energies.
+ * MPV_MERGE_LAYERED: the hierarchical merge of Section 3.2 (Table alg). num_paths / 2
+ *   layers run the opposite direction pairs in the table's order (left/right, up/down,
+ *   the two diagonals); each pass's energies are taken relative to the pixel's minimum
+ *   over its band, the first (horizontal) layer keeps the smaller of the two, every other
+ *   layer their mean rounded down, and each layer's merged energy is the data term of the
+ *   next. Decisions (WTA, right disparity, LR) are taken on the last layer's merge.
+ *   num_paths must be 2, 4 or 8.
+ * MPV_MERGE_LAYERED_OCC: as MPV_MERGE_LAYERED with the paper's example strategy for
+ *   occluded areas: the left-to-right pass pays twice the transition weight when the
+ *   disparity increases along the path. */
+#define MPV_MERGE_SUM 0
+#define MPV_MERGE_LAYERED 1
+#define MPV_MERGE_LAYERED_OCC 2
+
 #define MPV_MAX_DISP 256
 #define MPV_MAX_LEVELS 4
 #define MPV_MAX_WIDTH 4096
@@ -92,6 +108,7 @@ typedef struct {
     int32_t tau;           /* truncation, >= 1; tau >= num_disp is the untruncated TV */
     int32_t lr_max_diff;   /* LR tolerance in px (1 = "1 px"); < 0 disables the check */
     int32_t agg_type;      /* MPV_AGG_U16 or MPV_AGG_I32 (exported sums only) */
+    int32_t merge;         /* MPV_MERGE_*: how the directed paths are combined (0 = sum) */
 } mpv_params;
 
 /* Human-readable status name; never NULL. */
@@ -121,7 +138,7 @@ mpv_status mpv_cost(const mpv_params *p, const mpv_image *left, const mpv_image 
  * num_paths directions (0 = all of them). Output: device [H][W][cap] of uint16 or int32
  * per agg_type; slots past a pixel's band hold the type's maximum.
  * MPV_ERR_OVERFLOW when P * (24 + lambda*min(tau, D-1)) * longest line may exceed the type;
- * MPV_ERR_UNSUPPORTED when lambda*min(tau, D-1) > 4000. */
+ * MPV_ERR_UNSUPPORTED when lambda*min(tau, D-1) > 4000 or merge is not MPV_MERGE_SUM. */
 mpv_status mpv_aggregate(const mpv_params *p, const uint8_t *cost, int32_t width, int32_t height,
                          const mpv_band *band, uint32_t path_mask, void *agg, hipStream_t stream);
 
@@ -171,8 +188,12 @@ size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params *p, int32_t width, i
  * level searches the band of cap = min(2R+1, D_l) disparities starting at
  * lo = clamp(2 * raw_{l-1}(min(x/2, W_{l-1}-1), min(y/2, H_{l-1}-1)) - R, 0, D_l - cap).
  * Each level runs cost -> all P paths -> sum -> WTA -> LR exactly as the unfused calls
- * do, so the outputs equal mpv_cost + mpv_aggregate + mpv_disparity per level.
- * Requires 24 + lambda*min(tau, D-1) <= 255, num_paths in {1,2,4,8} and every level at
+ * do, so the outputs equal mpv_cost + mpv_aggregate + mpv_disparity per level; with a
+ * layered merge each level runs the layers in turn and decides on the last layer's merge.
+ * Requires 24 + lambda*min(tau, D-1) <= 255 (layered: 24 + m*lambda*min(tau, D-1) <= 255
+ * with m = the number of layers, at least 2 for MPV_MERGE_LAYERED_OCC, so that every
+ * merged energy fits a byte; MPV_ERR_UNSUPPORTED otherwise), num_paths in {1,2,4,8}
+ * ({2,4,8} for a layered merge) and every level at
  * least 1x1 pixel, at most MPV_MAX_WIDTH wide and MPV_MAX_HEIGHT high; one direction's
  * partial volume (width * height * slots) below 2^31 bytes (MPV_ERR_INVALID_ARG otherwise). */
 mpv_status mpv_pyramid(const mpv_pyramid_params *p, const mpv_image *left, const mpv_image *right,
@@ -198,7 +219,8 @@ mpv_status mpv_match(const mpv_params *p, const mpv_image *left, const mpv_image
  * descriptor tables into the workspace and synchronises `stream`) -> run / run_graph any
  * number of times. The items' images and outputs must stay allocated while the batch
  * lives; their contents may change between runs. The handle is host memory owned by the
- * library until mpv_batch_destroy. */
+ * library until mpv_batch_destroy. Batches sum the paths: a layered merge is
+ * MPV_ERR_UNSUPPORTED here. */
 typedef struct mpv_batch_s *mpv_batch;
 typedef struct {
     mpv_image left, right; /* device images of one pair */

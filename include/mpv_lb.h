@@ -28,7 +28,9 @@ extern "C" {
  *   (disparities clamped to [0, D-1])   7: min over |d-raw| > 1 of S' (1 if none),
  * with S' = the sum of path energies minus its per-pixel minimum, channels 3..7 divided by
  * P * (24 + lambda*min(tau, D-1)); values rounded to bf16 (nearest, ties to even).
- * feat: bf16 [H0][W0][8]; raw0, disp0: int16 [H0][W0] (raw WTA, LR-checked). */
+ * feat: bf16 [H0][W0][8]; raw0, disp0: int16 [H0][W0] (raw WTA, LR-checked).
+ * The features are defined on the sum of the paths: a layered merge is MPV_ERR_UNSUPPORTED
+ * (workspace size 0). */
 size_t mpv_lb_coarse_workspace_bytes(const mpv_params *p, int32_t W0, int32_t H0);
 mpv_status mpv_lb_coarse(const mpv_params *p, const mpv_image *left0, const mpv_image *right0,
                          uint16_t *feat, int16_t *raw0, int16_t *disp0, void *workspace,

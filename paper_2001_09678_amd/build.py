@@ -30,6 +30,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 FILE_FLAGS = {
     "kern_full.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "kern_full_batch.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "kern_full_merge.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
 }
 
 

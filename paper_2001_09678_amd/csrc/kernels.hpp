@@ -639,6 +639,23 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
   uint32_t bw[PREFETCH];        // broadcast step words
   int bl[PREFETCH];             // broadcast band lengths
   const rsrc_t rcr = make_rsrc(a.cr);
+  // SRC_MERGE: the lane's 2K slots of both source volumes, loaded PREFETCH steps ahead.
+  // off = the step's pixel index times capP; uni: off is wave-uniform (scalar offset).
+  const rsrc_t rmA = make_rsrc(SRC == SRC_MERGE ? a.msrc : a.part);
+  const rsrc_t rmB = make_rsrc(SRC == SRC_MERGE ? a.msrc + a.part_stride : a.part);
+  uint32_t mring[PREFETCH][2];
+  auto fetch_m = [&](uint32_t off, bool uni, uint32_t (&dst)[2]) {
+    if constexpr (SRC == SRC_MERGE) {
+      const uint32_t vo = uni ? (uint32_t)(2 * l * K) : off + 2 * l * K, so = uni ? off : 0u;
+      if constexpr (K == 1) {
+        dst[0] = buf_ld16(rmA, vo, so);
+        dst[1] = buf_ld16(rmB, vo, so);
+      } else {
+        dst[0] = buf_ld32(rmA, vo, so);
+        dst[1] = buf_ld32(rmB, vo, so);
+      }
+    }
+  };
   auto fetch_c = [&](uint32_t c, uint32_t (&dst)[NC]) {
     if constexpr (SRC == SRC_CENSUS) {
       // c >= census margin > SPAN, so every offset below is non-negative
@@ -657,6 +674,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
     if constexpr (BANDED) bl[q] = group_bcast<LPL, q>((int)cur.y);
     fetch_c(la.cen(q), ring[q]);
+    fetch_m(la.pix(q) * (uint32_t)a.capP, false, mring[q]);
   });
   // loop-invariant masks: halves for d >= D are absent nodes (unbanded path)
   uint32_t dmask[K];
@@ -680,12 +698,15 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     uint32_t cr[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) cr[q] = ring[slot][q];
-    {  // step t + PREFETCH: broadcast its word and issue its census loads
+    const uint32_t mA = mring[slot][0], mB = mring[slot][1];
+    {  // step t + PREFETCH: broadcast its word and issue its census (or source) loads
       constexpr int kn = (k + PREFETCH) % CHUNK;
       const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
       bw[slot] = (uint32_t)group_bcast<LPL, kn>((int)src.x);
       if constexpr (BANDED) bl[slot] = group_bcast<LPL, kn>((int)src.y);
       fetch_c(FAST ? cpf : la.cen(t + PREFETCH), ring[slot]);
+      fetch_m(FAST ? pst + (uint32_t)PREFETCH * pstep : la.pix(t + PREFETCH) * (uint32_t)a.capP,
+              FAST && LPL == 64, mring[slot]);
     }
     // ---- matching cost of this pixel, two disparities per pair
     uint32_t C[K];
@@ -702,6 +723,13 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
           c0 = (x - d0 >= 0) ? c0 : 24u;
           c1 = (x - d0 - 1 >= 0) ? c1 : 24u;
         }
+      } else if constexpr (SRC == SRC_MERGE) {
+        // bytes 2q, 2q+1 of both sources as a 16-bit pair, merged per node
+        const uint32_t sel = 0x0c000c00u | ((uint32_t)(2 * q + 1) << 16) | (uint32_t)(2 * q);
+        const uint32_t ua = __builtin_amdgcn_perm(0u, mA, sel), ub = __builtin_amdgcn_perm(0u, mB, sel);
+        const uint32_t cm = a.mop == MERGE_MEAN ? ((ua + ub) >> 1) & 0x7FFF7FFFu : pk_min(ua, ub);
+        c0 = cm & 0xFFFFu;
+        c1 = cm >> 16;
       } else {
         const uint8_t* cp = a.cost + (size_t)la.pix(t) * a.cap;
         const int j0 = min(max(d0 - b0, 0), a.cap - 1), j1 = min(max(d0 + 1 - b0, 0), a.cap - 1);
@@ -841,8 +869,8 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
   uint32_t P = INF32;  // normalised energies of the previous pixel (runtime-tau path)
   // compile-time-tau path: unnormalised energies in complement encoding, Pu = INF32 - L
-  // (absent 0). L never needs normalising here: the fused path has 24 + lambda*tau <= 255
-  // and lines of at most MPV_MAX_HEIGHT (or MPV_MAX_WIDTH) pixels, so L < 2^24, far from
+  // (absent 0). L never needs normalising here: the fused path has data terms plus
+  // lambda*tau of at most 255 and lines of at most MPV_MAX_HEIGHT (or MPV_MAX_WIDTH) pixels, so L < 2^24, far from
   // INF32. The line maximum then feeds only the next step's truncation candidate and the
   // stored bytes, off the step's dependent chain.
   int Pu = 0;
@@ -861,6 +889,19 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   // D + 64 words left of x = 0) keeps c - b0 - j in bounds for every lane (b0 <= D-1).
   // For 64-lane groups c and b0 are wave-uniform: scalar base, constant lane offset.
   const uint32_t loff = (uint32_t)(LPL - 1 - j) << 2;
+  // SRC_MERGE: this lane's slot of both source volumes (low and high half), loaded
+  // PREFETCH steps ahead; off and uni as in the full-range scan.
+  const rsrc_t rmA = make_rsrc(SRC == SRC_MERGE ? a.msrc : a.part);
+  const rsrc_t rmB = make_rsrc(SRC == SRC_MERGE ? a.msrc + a.part_stride : a.part);
+  uint32_t mring[PREFETCH];
+  auto fetch_m = [&](uint32_t off, bool uni) -> uint32_t {
+    if constexpr (SRC == SRC_MERGE) {
+      const uint32_t vo = uni ? (uint32_t)j : off + j, so = uni ? off : 0u;
+      return buf_ld8(rmA, vo, so) | (buf_ld8(rmB, vo, so) << 16);
+    } else {
+      return 0u;
+    }
+  };
   auto fetch_c = [&](uint32_t c, uint32_t w) -> uint32_t {
     if constexpr (SRC == SRC_CENSUS) {
       const uint32_t b0 = w >> 24;
@@ -878,6 +919,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
     if constexpr (VAR) bl[q] = group_bcast<LPL, q>((int)cur.y);
     ring[q] = fetch_c(la.cen(q), bw[q]);
+    mring[q] = fetch_m(la.pix(q) * (uint32_t)a.capP, false);
   });
   const uint32_t pstep = (uint32_t)(la.dp * a.capP);
 
@@ -891,13 +933,17 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     const int b0 = (int)(w >> 24);
     const int bn = VAR ? bl[slot] : a.cap;
     const uint32_t crv = ring[slot];
-    {  // step t + PREFETCH: broadcast its word and issue its census load
+    const uint32_t mv = mring[slot];
+    {  // step t + PREFETCH: broadcast its word and issue its census (or source) loads
       constexpr int kn = (k + PREFETCH) % CHUNK;
       const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
       const uint32_t wn = (uint32_t)group_bcast<LPL, kn>((int)src.x);
       if constexpr (VAR) bl[slot] = group_bcast<LPL, kn>((int)src.y);
       bw[slot] = wn;
       ring[slot] = fetch_c(FAST ? cpf : la.cen(t + PREFETCH), wn);
+      mring[slot] = fetch_m(FAST ? pst + (uint32_t)PREFETCH * pstep
+                                 : la.pix(t + PREFETCH) * (uint32_t)a.capP,
+                            FAST && LPL == 64);
     }
     uint32_t C;
     if constexpr (SRC == SRC_CENSUS) {
@@ -907,6 +953,9 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
         pc = (x - b0 - j >= 0) ? pc : 24u;
       }
       C = pc + ((j < bn) ? 0u : INF32);
+    } else if constexpr (SRC == SRC_MERGE) {
+      const uint32_t ua = mv & 0xFFu, ub = mv >> 16;
+      C = (j < bn) ? (a.mop == MERGE_MEAN ? (ua + ub) >> 1 : min(ua, ub)) : INF32;
     } else {
       C = (j < bn) ? (uint32_t)a.cost[(size_t)la.pix(t) * a.cap + min(j, a.cap - 1)] : INF32;
     }
@@ -1144,8 +1193,9 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   }
 }
 
-// Fused-path reduce over the P uint8 partial volumes: a lane owns 16 consecutive slots of
-// one pixel (one 16-byte load per partial), LPP = stride/16 lanes per pixel, 64/LPP
+// Fused-path reduce over the P uint8 partial volumes (their sum, or for a layered merge
+// the smaller or the floor mean of the last layer's two): a lane owns 16 consecutive slots
+// of one pixel (one 16-byte load per partial), LPP = stride/16 lanes per pixel, 64/LPP
 // pixels per wave step. Sums fit 16 bits (P * 255), so two slots share a register.
 // need_lr = false (intermediate pyramid levels) writes the raw winner only.
 template <int LPP>
@@ -1178,15 +1228,28 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
     band_at(a.lo, a.len, p, a.D, a.bcap, b0, bn);
     // s[2q]: slots 4q (lo), 4q+2 (hi); s[2q+1]: slots 4q+1 (lo), 4q+3 (hi)
     uint32_t sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const uint4 w = wv[r];
-      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    if (a.merge == 1 + MERGE_MIN) {  // layered merge: the smaller of the two passes
+      const uint32_t wa[4] = {wv[0].x, wv[0].y, wv[0].z, wv[0].w};
+      const uint32_t wb[4] = {wv[1].x, wv[1].y, wv[1].z, wv[1].w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        sm[2 * q] += ws[q] & 0x00FF00FFu;
-        sm[2 * q + 1] += (ws[q] >> 8) & 0x00FF00FFu;
+        sm[2 * q] = pk_min(wa[q] & 0x00FF00FFu, wb[q] & 0x00FF00FFu);
+        sm[2 * q + 1] = pk_min((wa[q] >> 8) & 0x00FF00FFu, (wb[q] >> 8) & 0x00FF00FFu);
       }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const uint4 w = wv[r];
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          sm[2 * q] += ws[q] & 0x00FF00FFu;
+          sm[2 * q + 1] += (ws[q] >> 8) & 0x00FF00FFu;
+        }
+      }
+      if (a.merge == 1 + MERGE_MEAN)  // layered merge: the mean of the two, rounded down
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sm[i] = (sm[i] >> 1) & 0x7FFF7FFFu;
     }
     uint32_t v[16];
 #pragma unroll

@@ -285,6 +285,12 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p) {
 __device__ __forceinline__ uint32_t buf_ld32(rsrc_t r, uint32_t voff, uint32_t soff) {
   return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
 }
+__device__ __forceinline__ uint32_t buf_ld16(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ uint32_t buf_ld8(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+}
 
 // Minimum over aligned groups of N lanes (N = 1, 2, 4, 8, 16), in every lane of the group.
 template <int N>

@@ -39,8 +39,19 @@ mpv_status check_params(const mpv_params* p, bool fused) {
     return MPV_ERR_INVALID_ARG;
   if (p->lambda < 0 || p->tau < 1) return MPV_ERR_INVALID_ARG;
   const long lt = (long)p->lambda * tau_eff(p->tau, p->num_disp);
-  if (fused ? (24 + lt > 255) : (lt > 4000)) return MPV_ERR_UNSUPPORTED;
   if (p->agg_type != MPV_AGG_U16 && p->agg_type != MPV_AGG_I32) return MPV_ERR_INVALID_ARG;
+  if (p->merge != MPV_MERGE_SUM && p->merge != MPV_MERGE_LAYERED && p->merge != MPV_MERGE_LAYERED_OCC)
+    return MPV_ERR_INVALID_ARG;
+  if (p->merge != MPV_MERGE_SUM) {
+    if (p->num_paths < 2) return MPV_ERR_INVALID_ARG;
+    // layer k's merged energies are at most 24 + (k+1)*lambda*tau (each pass adds at most
+    // lambda*tau to its data term's range; the doubled weight of the occlusion strategy
+    // enters one pass of the first layer), and every stored partial must fit a byte
+    const long m = std::max(p->num_paths / 2, p->merge == MPV_MERGE_LAYERED_OCC ? 2 : 1);
+    if (fused && 24 + m * lt > 255) return MPV_ERR_UNSUPPORTED;
+    if (p->merge == MPV_MERGE_LAYERED_OCC) return MPV_ERR_UNSUPPORTED;  // not implemented yet
+  }
+  if (fused ? (24 + lt > 255) : (lt > 4000)) return MPV_ERR_UNSUPPORTED;
   return MPV_OK;
 }
 
@@ -157,10 +168,16 @@ int wpb_of(const mpv_schedule& s) { return s.waves_per_block ? s.waves_per_block
 
 void launch_scan(const ScanArgs& a, const ScanChoice& c, int src, int out, const mpv_schedule& s,
                  hipStream_t st) {
-  if (c.banded_kernel)
+  if (src == SRC_MERGE) {
+    if (c.banded_kernel)
+      mpvl::scan_band_merge(a, c.LPL, a.len != nullptr, wpb_of(s), st);
+    else
+      mpvl::scan_full_merge(a, c.LPL, c.K, c.masked, wpb_of(s), st);
+  } else if (c.banded_kernel) {
     mpvl::scan_band(a, c.LPL, src, out, a.len != nullptr, wpb_of(s), st);
-  else
+  } else {
     mpvl::scan_full(a, c.LPL, c.K, src, out, c.masked, wpb_of(s), st);
+  }
 }
 
 // ---- one fused level ---------------------------------------------------------------------
@@ -269,14 +286,38 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
     mpvl::census(L, lpitch, R, rpitch, W, H, (uint32_t*)a.cl, (uint32_t*)a.cr, lw.cpitch,
                  lw.cmargin, s);
   }
-  int dirs[8];
-  for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
-  plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
+  const int nl = p->num_paths / 2;  // layers of a layered merge
   {
     HookScope hs(MPV_STAGE_SCAN, level, s);
-    launch_scan(a, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
+    if (p->merge == MPV_MERGE_SUM) {
+      int dirs[8];
+      for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
+      plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
+      launch_scan(a, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
+    } else {
+      // Section 3.2 / Table alg: layer k scans the pair 2k, 2k+1 into partial volumes 2k and
+      // 2k+1; its data term is the census cost (k = 0) or the merge of layer k-1's volumes
+      for (int k = 0; k < nl; ++k) {
+        ScanArgs b = a;
+        const int pair[2] = {2 * k, 2 * k + 1};
+        b.dir_base = 2 * k;
+        plan_dirs(b, pair, 2, lw.sc.LPL);
+        if (k == 0) {
+          launch_scan(b, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
+        } else {
+          b.msrc = a.part + (size_t)(2 * k - 2) * a.part_stride;
+          b.mop = k == 1 ? MERGE_MIN : MERGE_MEAN;
+          launch_scan(b, lw.sc, SRC_MERGE, OUT_PART, sched, s);
+        }
+      }
+    }
   }
-  const RedArgs ra = level_red_args(p, a, lw, disp, right, raw, nb);
+  RedArgs ra = level_red_args(p, a, lw, disp, right, raw, nb);
+  if (p->merge != MPV_MERGE_SUM) {  // decide on the last layer's merge
+    ra.part = a.part + (size_t)(2 * nl - 2) * a.part_stride;
+    ra.npart = 2;
+    ra.merge = 1 + (nl == 1 ? MERGE_MIN : MERGE_MEAN);
+  }
   {
     HookScope hs(MPV_STAGE_REDUCE, level, s);
     mpvl::reduce_part(ra, ra.need_lr, s);
@@ -648,6 +689,7 @@ mpv_status mpv_aggregate(const mpv_params* p, const uint8_t* cost, int32_t W, in
                          hipStream_t stream) {
   mpv_status st = check_params(p, false);
   if (st) return st;
+  if (p->merge != MPV_MERGE_SUM) return MPV_ERR_UNSUPPORTED;
   if (!cost || !agg || W < 1 || H < 1) return MPV_ERR_INVALID_ARG;
   if ((st = check_band(band, p->num_disp))) return st;
   const bool banded = band && band->lo;
@@ -817,6 +859,8 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
 mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* items, int32_t n,
                             mpv_batch* out) {
   if (!p || !items || n < 1 || !out) return MPV_ERR_INVALID_ARG;
+  if (p->base.merge != MPV_MERGE_SUM) return check_params(&p->base, true) ? MPV_ERR_INVALID_ARG
+                                                                         : MPV_ERR_UNSUPPORTED;
   mpv_batch_s* b = new (std::nothrow) mpv_batch_s();
   if (!b) return MPV_ERR_INVALID_ARG;
   b->p = *p;
@@ -943,7 +987,8 @@ void mpv_batch_destroy(mpv_batch b) {
 
 // ---- learned band proposal: coarse level + features --------------------------------------
 size_t mpv_lb_coarse_workspace_bytes(const mpv_params* p, int32_t W0, int32_t H0) {
-  if (check_params(p, true) || W0 < 1 || H0 < 1 || W0 > MPV_MAX_WIDTH) return 0;
+  if (check_params(p, true) || p->merge != MPV_MERGE_SUM || W0 < 1 || H0 < 1 || W0 > MPV_MAX_WIDTH)
+    return 0;
   const LevelWs lw = level_ws(p, W0, H0, nullptr, mpv_schedule{});
   return lw.fits ? lw.total : 0;
 }
@@ -953,6 +998,7 @@ mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_
                          size_t workspace_bytes, hipStream_t stream) {
   mpv_status st = check_params(p, true);
   if (st) return st;
+  if (p->merge != MPV_MERGE_SUM) return MPV_ERR_UNSUPPORTED;
   if (!valid_image(left0) || !valid_image(right0) || !feat || !raw0 || !disp0)
     return MPV_ERR_INVALID_ARG;
   if (left0->width != right0->width || left0->height != right0->height) return MPV_ERR_INVALID_ARG;

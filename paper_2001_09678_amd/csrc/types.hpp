@@ -5,7 +5,11 @@
 
 namespace mpvk {
 
-enum { SRC_CENSUS = 0, SRC_COST = 1 };
+// Scan sources: census (fused cost), a uint8 cost volume, or the merge of the previous
+// layer's two partial volumes (layered path merge).
+enum { SRC_CENSUS = 0, SRC_COST = 1, SRC_MERGE = 2 };
+// Merge of two partial volumes: the smaller, or the mean rounded down.
+enum { MERGE_MIN = 0, MERGE_MEAN = 1 };
 enum { OUT_PART = 0, OUT_U16 = 1, OUT_I32 = 2 };
 
 struct ScanArgs {
@@ -29,6 +33,10 @@ struct ScanArgs {
   int dir_base, npd;
   int dir[8];
   int gprefix[9];  // first wave of each direction (one wave = 64/LPL lines)
+  // SRC_MERGE: the previous layer's two partial volumes, msrc and msrc + part_stride, in
+  // this scan's slot layout; mop = MERGE_MIN or MERGE_MEAN.
+  const uint8_t* msrc;
+  int mop;
 };
 
 // Segment table of a batched launch: global wave u belongs to descriptor s with
@@ -52,6 +60,7 @@ struct RedArgs {
   const uint8_t* part;
   long long part_stride;
   int npart;
+  int merge;  // 0: sum of the npart partials; 1 + MERGE_MIN / MERGE_MEAN: of two partials
   const void* agg;
   int lr;
   int need_lr;  // batched launches: compute right disparity + LR for this descriptor

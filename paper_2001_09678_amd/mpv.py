@@ -24,10 +24,19 @@ class MPVParams:
     tau: int = 4
     lr_max_diff: int = 1
     agg_type: str = "u16"  # exported aggregate type: "u16" or "i32"
+    # path merge: "sum", or the hierarchical merge of Section 3.2 (Table alg), "layered",
+    # or "layered_occ" with its occlusion strategy
+    merge: str = "sum"
+
+    _MERGES = {"sum": _L.MPV_MERGE_SUM, "layered": _L.MPV_MERGE_LAYERED,
+               "layered_occ": _L.MPV_MERGE_LAYERED_OCC}
 
     def c(self) -> _L.Params:
+        if self.merge not in self._MERGES:
+            raise ValueError(f"merge must be one of {sorted(self._MERGES)}")
         return _L.Params(self.num_disp, 2, self.num_paths, self.lam, self.tau, self.lr_max_diff,
-                         _L.MPV_AGG_U16 if self.agg_type == "u16" else _L.MPV_AGG_I32)
+                         _L.MPV_AGG_U16 if self.agg_type == "u16" else _L.MPV_AGG_I32,
+                         self._MERGES[self.merge])
 
 
 def _stream():

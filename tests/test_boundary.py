@@ -115,3 +115,35 @@ def test_workspace_model(L):
     ws = lib.mpv_pyramid_workspace_bytes(C.byref(pp), 1280, 720)
     assert ws >= 8 * 1280 * 720 * 128
     assert ws < 8 * 1280 * 720 * 128 + 32 * 2**20
+
+
+def test_layered_merge_limits(L):
+    """The layered merge (Section 3.2, Table alg) needs pairs of directions and merged
+    energies that fit a byte: 24 + (layers) * lambda * min(tau, D-1) <= 255; only the fused
+    entry points run it."""
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    lay = L.MPV_MERGE_LAYERED
+    ok = _params(L, num_disp=128, num_paths=8, merge=lay)  # 24 + 4 * 32 = 152
+    assert lib.mpv_match_workspace_bytes(C.byref(ok), 320, 240, None) > 0
+    pp = L.PyramidParams(ok, 3, 4)
+    assert lib.mpv_pyramid_workspace_bytes(C.byref(pp), 1280, 720) > 0
+    # one path is no pair; an unknown merge is an argument error
+    for kw in (dict(num_paths=1, merge=lay), dict(merge=3), dict(merge=-1)):
+        p = _params(L, **kw)
+        assert lib.mpv_match_workspace_bytes(C.byref(p), 320, 240, None) == 0, kw
+        assert lib.mpv_cost(C.byref(p), None, None, None, fake, None) == L.MPV_ERR_INVALID_ARG, kw
+    # 24 + 4 * 8 * 8 = 280 > 255 with four layers, but 24 + 2 * 64 = 152 fits two
+    big = _params(L, num_disp=128, num_paths=8, tau=8, merge=lay)
+    assert lib.mpv_match_workspace_bytes(C.byref(big), 320, 240, None) == 0
+    two = _params(L, num_disp=128, num_paths=4, tau=8, merge=lay)
+    assert lib.mpv_match_workspace_bytes(C.byref(two), 320, 240, None) > 0
+    img = L.Image(fake, 320, 240, 320)
+    assert lib.mpv_match(C.byref(big), C.byref(img), C.byref(img), None, fake, None, None, fake,
+                         1 << 40, None) == L.MPV_ERR_UNSUPPORTED
+    # the unfused export, batches and the learned coarse level sum the paths
+    assert lib.mpv_aggregate(C.byref(ok), fake, 320, 240, None, 0, fake, None) == L.MPV_ERR_UNSUPPORTED
+    item = L.BatchItem(img, img, 128, fake, None, None)
+    handle = C.c_void_p()
+    assert lib.mpv_batch_create(C.byref(pp), C.byref(item), 1, C.byref(handle)) == L.MPV_ERR_UNSUPPORTED
+    assert lib.mpv_lb_coarse_workspace_bytes(C.byref(ok), 320, 180) == 0
