@@ -1,5 +1,6 @@
-// Full-range scans of the layered path merge's later layers: the data term is the merge
-// of the previous layer's two partial volumes (single-descriptor launches).
+// Full-range scans of the layered path merge (single-descriptor launches): the later
+// layers, whose data term is the merge of the previous layer's two partial volumes, and
+// the first layer with the occlusion weight (census source).
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -7,33 +8,40 @@ namespace mpvl {
 using namespace mpvk;
 
 namespace {
-template <int LPL, int K, int TAU, bool BANDED>
+template <int LPL, int K, int SRC, int TAU, bool BANDED>
 void go(const ScanArgs& a, int wpb, hipStream_t s) {
   const int units = a.gprefix[a.ndir];
-  hipLaunchKernelGGL((k_scan_full<LPL, K, SRC_MERGE, OUT_PART, TAU, BANDED>),
+  hipLaunchKernelGGL((k_scan_full<LPL, K, SRC, OUT_PART, TAU, BANDED>),
                      dim3((units + wpb - 1) / wpb), dim3(64 * wpb), 0, s, a);
 }
 
-template <int TAU, bool BANDED>
+template <int SRC, int TAU, bool BANDED>
 void layout(const ScanArgs& a, int LPL, int K, int wpb, hipStream_t s) {
   if (LPL == 16) {
-    if (K == 1) go<16, 1, TAU, BANDED>(a, wpb, s); else go<16, 2, TAU, BANDED>(a, wpb, s);
+    if (K == 1) go<16, 1, SRC, TAU, BANDED>(a, wpb, s); else go<16, 2, SRC, TAU, BANDED>(a, wpb, s);
   } else if (LPL == 32) {
-    if (K == 1) go<32, 1, TAU, BANDED>(a, wpb, s); else go<32, 2, TAU, BANDED>(a, wpb, s);
+    if (K == 1) go<32, 1, SRC, TAU, BANDED>(a, wpb, s); else go<32, 2, SRC, TAU, BANDED>(a, wpb, s);
   } else {
-    if (K == 1) go<64, 1, TAU, BANDED>(a, wpb, s); else go<64, 2, TAU, BANDED>(a, wpb, s);
+    if (K == 1) go<64, 1, SRC, TAU, BANDED>(a, wpb, s); else go<64, 2, SRC, TAU, BANDED>(a, wpb, s);
+  }
+}
+
+template <int SRC>
+void taus(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s) {
+  if (banded) return layout<SRC, 0, true>(a, LPL, K, wpb, s);
+  switch (a.tau) {
+    case 1: return layout<SRC, 1, false>(a, LPL, K, wpb, s);
+    case 2: return layout<SRC, 2, false>(a, LPL, K, wpb, s);
+    case 4: return layout<SRC, 4, false>(a, LPL, K, wpb, s);
+    default: return layout<SRC, 0, false>(a, LPL, K, wpb, s);
   }
 }
 }  // namespace
 
-void scan_full_merge(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s) {
-  if (banded) return layout<0, true>(a, LPL, K, wpb, s);
-  switch (a.tau) {
-    case 1: return layout<1, false>(a, LPL, K, wpb, s);
-    case 2: return layout<2, false>(a, LPL, K, wpb, s);
-    case 4: return layout<4, false>(a, LPL, K, wpb, s);
-    default: return layout<0, false>(a, LPL, K, wpb, s);
-  }
+void scan_full_layered(const ScanArgs& a, int src, int LPL, int K, bool banded, int wpb,
+                       hipStream_t s) {
+  if (src == SRC_CENSUS_OCC) return taus<SRC_CENSUS_OCC>(a, LPL, K, banded, wpb, s);
+  return taus<SRC_MERGE>(a, LPL, K, banded, wpb, s);
 }
 
 }  // namespace mpvl

@@ -367,7 +367,7 @@ template <bool BANDED, int SRC>
 __device__ __forceinline__ uint2 load_chunk(const ScanArgs& a, const LineAddr& la, int t0, int k) {
   int b0 = 0, bn = a.D;
   if constexpr (BANDED) band_at(a.lo, a.len, (size_t)la.pix(t0 + k), a.D, a.cap, b0, bn);
-  const uint32_t cl = SRC == SRC_CENSUS ? ld_u32(a.cl, la.cen(t0 + k)) : 0u;
+  const uint32_t cl = src_census(SRC) ? ld_u32(a.cl, la.cen(t0 + k)) : 0u;
   return make_uint2(cl | ((uint32_t)b0 << 24), (uint32_t)bn);
 }
 
@@ -458,9 +458,11 @@ __device__ __forceinline__ void shift_pairs_down_c(const uint32_t (&v)[K], uint3
 
 // Envelope min_{|k|<tau} P(d+k) + lambda|k| of packed pairs by doubling sweeps
 // (TAU > 0: compile-time tau; TAU == 0: runtime tau).
+// lam_up weighs the sweep from lower disparities (an increase along the path), lambda the
+// sweep from higher ones.
 template <int LPL, int K, int TAU>
 __device__ __forceinline__ void pair_envelope(const uint32_t (&P)[K], uint32_t (&E)[K], int tau,
-                                              int lambda) {
+                                              int lambda, int lam_up) {
   uint32_t A[K], B[K], T[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) A[q] = B[q] = P[q];
@@ -468,9 +470,10 @@ __device__ __forceinline__ void pair_envelope(const uint32_t (&P)[K], uint32_t (
     static_for<ceil_log2(TAU)>([&](auto ic) {
       constexpr int S = 1 << decltype(ic)::value;
       const uint32_t pen = splat16((uint32_t)(S * lambda));
+      const uint32_t pup = splat16((uint32_t)(S * lam_up));
       shift_pairs_up_c<LPL, K, S>(A, T);
 #pragma unroll
-      for (int q = 0; q < K; ++q) A[q] = pk_min(A[q], pk_add(T[q], pen));
+      for (int q = 0; q < K; ++q) A[q] = pk_min(A[q], pk_add(T[q], pup));
       shift_pairs_down_c<LPL, K, S>(B, T);
 #pragma unroll
       for (int q = 0; q < K; ++q) B[q] = pk_min(B[q], pk_add(T[q], pen));
@@ -478,9 +481,10 @@ __device__ __forceinline__ void pair_envelope(const uint32_t (&P)[K], uint32_t (
   } else {
     for (int s = 1; s < tau; s <<= 1) {
       const uint32_t pen = splat16((uint32_t)(s * lambda));
+      const uint32_t pup = splat16((uint32_t)(s * lam_up));
       shift_pairs_up<LPL, K>(A, T, s);
 #pragma unroll
-      for (int q = 0; q < K; ++q) A[q] = pk_min(A[q], pk_add(T[q], pen));
+      for (int q = 0; q < K; ++q) A[q] = pk_min(A[q], pk_add(T[q], pup));
       shift_pairs_down<LPL, K>(B, T, s);
 #pragma unroll
       for (int q = 0; q < K; ++q) B[q] = pk_min(B[q], pk_add(T[q], pen));
@@ -492,24 +496,22 @@ __device__ __forceinline__ void pair_envelope(const uint32_t (&P)[K], uint32_t (
 
 // Band envelope in the previous pixel's frame extended by tau-1 lanes on each side.
 template <int LPL, int TAU>
-__device__ __forceinline__ uint32_t band_envelope(uint32_t P, int tau, int lambda) {
+__device__ __forceinline__ uint32_t band_envelope(uint32_t P, int tau, int lambda, int lam_up) {
   if constexpr (TAU > 0) {
     uint32_t A = shift_up_c<LPL, TAU - 1>(P, INF32);
     uint32_t B = A;
     static_for<ceil_log2(TAU)>([&](auto ic) {
       constexpr int S = 1 << decltype(ic)::value;
-      const uint32_t pen = (uint32_t)(S * lambda);
-      A = min(A, shift_up_c<LPL, S>(A, INF32) + pen);
-      B = min(B, shift_down_c<LPL, S>(B, INF32) + pen);
+      A = min(A, shift_up_c<LPL, S>(A, INF32) + (uint32_t)(S * lam_up));
+      B = min(B, shift_down_c<LPL, S>(B, INF32) + (uint32_t)(S * lambda));
     });
     return min(A, B);
   } else {
     uint32_t A = shift_up<LPL>(P, tau - 1, INF32);
     uint32_t B = A;
     for (int s = 1; s < tau; s <<= 1) {
-      const uint32_t pen = (uint32_t)(s * lambda);
-      A = min(A, shift_up<LPL>(A, s, INF32) + pen);
-      B = min(B, shift_down<LPL>(B, s, INF32) + pen);
+      A = min(A, shift_up<LPL>(A, s, INF32) + (uint32_t)(s * lam_up));
+      B = min(B, shift_down<LPL>(B, s, INF32) + (uint32_t)(s * lambda));
     }
     return min(A, B);
   }
@@ -555,15 +557,16 @@ __device__ __forceinline__ void zshift_pairs_down(const uint32_t (&v)[K], uint32
 // max over |k| < TAU of u(d+k) - lambda|k| for packed complement pairs.
 template <int LPL, int K, int TAU>
 __device__ __forceinline__ void pair_envelope_c(const uint32_t (&Pu)[K], uint32_t (&E)[K],
-                                                int lambda) {
+                                                int lambda, int lam_up) {
   uint32_t A[K], B[K], X[K], T[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) A[q] = B[q] = Pu[q];
   static_for<ceil_log2(TAU)>([&](auto ic) {
     constexpr int S = 1 << decltype(ic)::value;
     const uint32_t pen = splat16((uint32_t)(S * lambda));
+    const uint32_t pup = splat16((uint32_t)(S * lam_up));
 #pragma unroll
-    for (int q = 0; q < K; ++q) X[q] = pk_sub_i(A[q], pen);
+    for (int q = 0; q < K; ++q) X[q] = pk_sub_i(A[q], pup);
     zshift_pairs_up<LPL, K, S>(X, T);
 #pragma unroll
     for (int q = 0; q < K; ++q) A[q] = pk_max_i(A[q], T[q]);
@@ -581,16 +584,69 @@ __device__ __forceinline__ void pair_envelope_c(const uint32_t (&Pu)[K], uint32_
 // max over |k| < TAU of u(i+k) - lambda|k| in the previous pixel's frame extended by
 // TAU-1 lanes on each side. Absent nodes stay <= 0 < every present node.
 template <int LPL, int TAU>
-__device__ __forceinline__ int band_envelope_c(int Pu, int lambda) {
+__device__ __forceinline__ int band_envelope_c(int Pu, int lambda, int lam_up) {
   int A = zshift_up<LPL, TAU - 1>(Pu);
   int B = A;
   static_for<ceil_log2(TAU)>([&](auto ic) {
     constexpr int S = 1 << decltype(ic)::value;
-    const int pen = S * lambda;
-    A = max(A, zshift_up<LPL, S>(A - pen));
-    B = max(B, zshift_down<LPL, S>(B - pen));
+    A = max(A, zshift_up<LPL, S>(A - S * lam_up));
+    B = max(B, zshift_down<LPL, S>(B - S * lambda));
   });
   return max(A, B);
+}
+
+// ---- suffix extrema along the disparity axis (occlusion weight of the layered merge:
+// every predecessor at least tau above d costs lambda*tau, at least tau below 2*lambda*tau,
+// so the truncation candidate needs the best predecessor at or above d).
+// Complement-encoded (absent 0): lane i of the group gets the maximum over lanes >= i.
+template <int LPL>
+__device__ __forceinline__ int suffix_max_lanes(int v) {
+  static_for<ceil_log2(LPL)>([&](auto ic) {
+    constexpr int S = 1 << decltype(ic)::value;
+    v = max(v, zshift_down<LPL, S>(v));
+  });
+  return v;
+}
+// Plain energies: the minimum over lanes >= i, `fill` beyond the group.
+template <int LPL>
+__device__ __forceinline__ uint32_t suffix_min_lanes(uint32_t v, uint32_t fill) {
+  static_for<ceil_log2(LPL)>([&](auto ic) {
+    constexpr int S = 1 << decltype(ic)::value;
+    v = min(v, shift_down_c<LPL, S>(v, fill));
+  });
+  return v;
+}
+// Packed pairs (lane l holds d = 2(lK+q), +1): suffix maximum of complement energies.
+template <int LPL, int K>
+__device__ __forceinline__ void pair_suffix_max_c(const uint32_t (&v)[K], uint32_t (&o)[K]) {
+  int run = 0;
+#pragma unroll
+  for (int q = K - 1; q >= 0; --q) {
+    const int hi = max(hi16s(v[q]), run);
+    const int lo = max(lo16s(v[q]), hi);
+    o[q] = ((uint32_t)lo & 0xFFFFu) | ((uint32_t)hi << 16);
+    run = lo;
+  }
+  const int above = zshift_down<LPL, 1>(suffix_max_lanes<LPL>(run));  // lanes above this one
+  const uint32_t ab = splat16((uint32_t)above & 0xFFFFu);
+#pragma unroll
+  for (int q = 0; q < K; ++q) o[q] = pk_max_i(o[q], ab);
+}
+// Packed pairs: suffix minimum of plain 16-bit energies (absent >= INF16).
+template <int LPL, int K>
+__device__ __forceinline__ void pair_suffix_min(const uint32_t (&v)[K], uint32_t (&o)[K]) {
+  uint32_t run = INF16;
+#pragma unroll
+  for (int q = K - 1; q >= 0; --q) {
+    const uint32_t hi = min(hi16(v[q]), run);
+    const uint32_t lo = min(lo16(v[q]), hi);
+    o[q] = lo | (hi << 16);
+    run = lo;
+  }
+  const uint32_t above = shift_down_c<LPL, 1>(suffix_min_lanes<LPL>(run, INF16), INF16);
+  const uint32_t ab = splat16(above);
+#pragma unroll
+  for (int q = 0; q < K; ++q) o[q] = pk_min(o[q], ab);
 }
 
 template <int OUT>
@@ -621,6 +677,9 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
   block_line<LPL>(tab, unit, r, ri, ln, nmax);
   const LineAddr la = line_addr(a, ln);
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
+  // occlusion weight of the layered merge: this direction pays 2*lambda per disparity step up
+  const bool occ = SRC == SRC_CENSUS_OCC && r == a.up_dir;
+  const int lam_up = occ ? 2 * a.lambda : a.lambda;
   uint32_t P[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) P[k] = 0;
@@ -657,7 +716,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     }
   };
   auto fetch_c = [&](uint32_t c, uint32_t (&dst)[NC]) {
-    if constexpr (SRC == SRC_CENSUS) {
+    if constexpr (src_census(SRC)) {
       // c >= census margin > SPAN, so every offset below is non-negative
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
@@ -714,7 +773,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     for (int q = 0; q < K; ++q) {
       const int d0 = d0l + 2 * q;
       uint32_t c0, c1;
-      if constexpr (SRC == SRC_CENSUS) {
+      if constexpr (src_census(SRC)) {
         const uint32_t cl = w & 0xFFFFFFu;
         c0 = (uint32_t)__popc(cl ^ cr[NC - 1 - 2 * q]);
         c1 = (uint32_t)__popc(cl ^ cr[NC - 2 - 2 * q]);
@@ -751,12 +810,24 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     if constexpr (TAU > 0) {
       // complement encoding (u = INF16 - value per half, absent <= 0): max instead of min
       uint32_t E[K];
-      pair_envelope_c<LPL, K, TAU>(P, E, a.lambda);
+      pair_envelope_c<LPL, K, TAU>(P, E, a.lambda, lam_up);
       const uint32_t cap = t == 0 ? INF2 : splat16(INF16 - lt);
+      uint32_t capq[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) capq[q] = cap;
+      if constexpr (SRC == SRC_CENSUS_OCC) {
+        if (occ && t != 0) {  // the previous minimum + 2*lambda*tau, the best at or above d + lambda*tau
+          uint32_t SU[K];
+          pair_suffix_max_c<LPL, K>(P, SU);
+#pragma unroll
+          for (int q = 0; q < K; ++q)
+            capq[q] = pk_max_i(splat16(INF16 - 2 * lt), pk_sub_i(SU[q], splat16(lt)));
+        }
+      }
       int mu = -32768;
 #pragma unroll
       for (int q = 0; q < K; ++q) {
-        L[q] = pk_sub_i(pk_max_i(E[q], cap), C[q]);
+        L[q] = pk_sub_i(pk_max_i(E[q], capq[q]), C[q]);
         mu = max(mu, max(lo16s(L[q]), hi16s(L[q])));
       }
       if constexpr (LPL == 64)
@@ -775,10 +846,21 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
       }
     } else {
       uint32_t E[K];
-      pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda);
+      pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda, lam_up);
       const uint32_t mcap = t == 0 ? 0u : splat16(lt);  // the first pixel has no predecessor
+      uint32_t mc[K];
 #pragma unroll
-      for (int q = 0; q < K; ++q) L[q] = pk_add(C[q], pk_min(E[q], mcap));
+      for (int q = 0; q < K; ++q) mc[q] = mcap;
+      if constexpr (SRC == SRC_CENSUS_OCC) {
+        if (occ && t != 0) {  // the previous minimum (0) + 2*lambda*tau, the best at or above d + lambda*tau
+          uint32_t SM[K];
+          pair_suffix_min<LPL, K>(P, SM);
+#pragma unroll
+          for (int q = 0; q < K; ++q) mc[q] = pk_min(splat16(2 * lt), pk_add(SM[q], splat16(lt)));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < K; ++q) L[q] = pk_add(C[q], pk_min(E[q], mc[q]));
       m = min(lo16(L[0]), hi16(L[0]));
 #pragma unroll
       for (int q = 1; q < K; ++q) m = min(m, min(lo16(L[q]), hi16(L[q])));
@@ -834,7 +916,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     const uint2 nxt = load_chunk<BANDED, SRC>(a, la, t0 + CHUNK, kk);
     const int xa = la.x0 + t0 * la.dx, xb = xa + (CHUNK - 1) * la.dx;
     const bool fast = wave_all(t0 + CHUNK + PREFETCH <= la.n &&
-                               (SRC != SRC_CENSUS || min(xa, xb) >= a.D - 1));
+                               (!src_census(SRC) || min(xa, xb) >= a.D - 1));
     if (fast) {
       uint32_t pst = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;
       uint32_t cpf = (uint32_t)(la.c0 + (t0 + PREFETCH) * la.dc);
@@ -867,6 +949,9 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   const LineAddr la = line_addr(a, ln);
   const int e = a.tau - 1;
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
+  // occlusion weight of the layered merge: this direction pays 2*lambda per disparity step up
+  const bool occ = SRC == SRC_CENSUS_OCC && r == a.up_dir;
+  const int lam_up = occ ? 2 * a.lambda : a.lambda;
   uint32_t P = INF32;  // normalised energies of the previous pixel (runtime-tau path)
   // compile-time-tau path: unnormalised energies in complement encoding, Pu = INF32 - L
   // (absent 0). L never needs normalising here: the fused path has data terms plus
@@ -903,7 +988,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     }
   };
   auto fetch_c = [&](uint32_t c, uint32_t w) -> uint32_t {
-    if constexpr (SRC == SRC_CENSUS) {
+    if constexpr (src_census(SRC)) {
       const uint32_t b0 = w >> 24;
       if constexpr (LPL == 64)
         return buf_ld32(rcr, loff, (c - b0 - (uint32_t)(LPL - 1)) << 2);
@@ -946,7 +1031,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
                             FAST && LPL == 64);
     }
     uint32_t C;
-    if constexpr (SRC == SRC_CENSUS) {
+    if constexpr (src_census(SRC)) {
       uint32_t pc = (uint32_t)__popc((w & 0xFFFFFFu) ^ crv);
       if constexpr (!FAST) {
         const int x = la.x0 + la.tt(t) * la.dx;
@@ -963,10 +1048,20 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     const int src = j + (b0 - lo_prev) + e;
     if constexpr (TAU > 0) {
       // complement encoding: Pu = INF32 - P (absent 0), larger is better
-      const int E = band_envelope_c<LPL, TAU>(Pu, a.lambda);  // lane i <-> position i - e
+      int E = band_envelope_c<LPL, TAU>(Pu, a.lambda, lam_up);  // lane i <-> position i - e
+      if constexpr (SRC == SRC_CENSUS_OCC) {
+        if (occ) E = max(E, suffix_max_lanes<LPL>(zshift_up<LPL, TAU - 1>(Pu)) - (int)lt);
+      }
       const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
-      const int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
-      const int Mu = t == 0 ? (int)INF32 : max(Ev, capu);
+      int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
+      int cu = capu;
+      if constexpr (SRC == SRC_CENSUS_OCC) {
+        if (occ) {
+          if (src < 0) Ev = capu;  // every node of p-r lies at least tau above d
+          cu = capu - (int)lt;     // increases of tau or more cost 2*lambda*tau
+        }
+      }
+      const int Mu = t == 0 ? (int)INF32 : max(Ev, cu);
       const int Lu = (j < bn) ? Mu - (int)C : 0;
       Pu = Lu;  // next state
       int mu;
@@ -979,11 +1074,21 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       m = 0;                                          // (no offset to carry)
       P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;    // energy minus the line minimum
     } else {
-      const uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda);  // lane i <-> position i - e
+      uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda, lam_up);  // lane i <-> position i - e
+      if constexpr (SRC == SRC_CENSUS_OCC) {
+        if (occ) E = min(E, suffix_min_lanes<LPL>(shift_up<LPL>(P, a.tau - 1, INF32), INF32) + lt);
+      }
       const uint32_t got =
           (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, (int)E);
-      const uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
-      L = C + (t == 0 ? 0u : min(Ev, lt));
+      uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
+      uint32_t cl = lt;
+      if constexpr (SRC == SRC_CENSUS_OCC) {
+        if (occ) {
+          if (src < 0) Ev = lt;  // every node of p-r lies at least tau above d
+          cl = 2 * lt;           // increases of tau or more cost 2*lambda*tau
+        }
+      }
+      L = C + (t == 0 ? 0u : min(Ev, cl));
       m = group_min<LPL>(L);
       P = (j < bn) ? L - m : INF32;
     }
@@ -1006,7 +1111,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     const uint2 nxt = load_chunk<true, SRC>(a, la, t0 + CHUNK, kk);
     const int xa = la.x0 + t0 * la.dx, xb = xa + (CHUNK - 1) * la.dx;
     const bool fast = wave_all(t0 + CHUNK + PREFETCH <= la.n &&
-                               (SRC != SRC_CENSUS || min(xa, xb) >= a.D - 1));
+                               (!src_census(SRC) || min(xa, xb) >= a.D - 1));
     if (fast) {
       uint32_t pst = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;
       uint32_t cpf = (uint32_t)(la.c0 + (t0 + PREFETCH) * la.dc);

@@ -25,10 +25,12 @@ void scan_full_batch(const Batch<ScanArgs>& b, int units, int LPL, int K, int ta
 void scan_band(const ScanArgs& a, int LPL, int src, int out, bool var, int wpb, hipStream_t s);
 void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, bool var, int wpb,
                      hipStream_t s);
-// Later layers of the layered path merge: source = merge of the previous layer's partials
-// (a.msrc, a.mop), partial output; tau 1, 2, 4 compile-time, others runtime.
-void scan_full_merge(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
-void scan_band_merge(const ScanArgs& a, int LPL, bool var, int wpb, hipStream_t s);
+// Layered path merge: src = SRC_MERGE (later layers: the merge of the previous layer's
+// partials a.msrc, a.mop) or SRC_CENSUS_OCC (first layer with the occlusion weight on
+// a.up_dir); partial output; tau 1, 2, 4 compile-time, others runtime.
+void scan_full_layered(const ScanArgs& a, int src, int LPL, int K, bool banded, int wpb,
+                       hipStream_t s);
+void scan_band_layered(const ScanArgs& a, int src, int LPL, bool var, int wpb, hipStream_t s);
 
 // Sum + WTA (+ right disparity + LR when need_lr) over P uint8 partial volumes.
 void reduce_part(const RedArgs& a, int need_lr, hipStream_t s);

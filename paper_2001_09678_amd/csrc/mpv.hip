@@ -49,7 +49,6 @@ mpv_status check_params(const mpv_params* p, bool fused) {
     // enters one pass of the first layer), and every stored partial must fit a byte
     const long m = std::max(p->num_paths / 2, p->merge == MPV_MERGE_LAYERED_OCC ? 2 : 1);
     if (fused && 24 + m * lt > 255) return MPV_ERR_UNSUPPORTED;
-    if (p->merge == MPV_MERGE_LAYERED_OCC) return MPV_ERR_UNSUPPORTED;  // not implemented yet
   }
   if (fused ? (24 + lt > 255) : (lt > 4000)) return MPV_ERR_UNSUPPORTED;
   return MPV_OK;
@@ -168,11 +167,11 @@ int wpb_of(const mpv_schedule& s) { return s.waves_per_block ? s.waves_per_block
 
 void launch_scan(const ScanArgs& a, const ScanChoice& c, int src, int out, const mpv_schedule& s,
                  hipStream_t st) {
-  if (src == SRC_MERGE) {
+  if (src == SRC_MERGE || src == SRC_CENSUS_OCC) {
     if (c.banded_kernel)
-      mpvl::scan_band_merge(a, c.LPL, a.len != nullptr, wpb_of(s), st);
+      mpvl::scan_band_layered(a, src, c.LPL, a.len != nullptr, wpb_of(s), st);
     else
-      mpvl::scan_full_merge(a, c.LPL, c.K, c.masked, wpb_of(s), st);
+      mpvl::scan_full_layered(a, src, c.LPL, c.K, c.masked, wpb_of(s), st);
   } else if (c.banded_kernel) {
     mpvl::scan_band(a, c.LPL, src, out, a.len != nullptr, wpb_of(s), st);
   } else {
@@ -231,6 +230,7 @@ ScanArgs level_scan_args(const mpv_params* p, int W, int H, const mpv_band* band
   a.part_stride = (long long)H * W * lw.sc.capP;
   a.dir_base = 0;
   a.npd = p->num_paths;
+  a.up_dir = -1;
   return a;
 }
 
@@ -303,7 +303,9 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
         b.dir_base = 2 * k;
         plan_dirs(b, pair, 2, lw.sc.LPL);
         if (k == 0) {
-          launch_scan(b, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
+          // occlusion strategy: the left-to-right pass pays twice for disparity increases
+          b.up_dir = p->merge == MPV_MERGE_LAYERED_OCC ? 0 : -1;
+          launch_scan(b, lw.sc, b.up_dir >= 0 ? SRC_CENSUS_OCC : SRC_CENSUS, OUT_PART, sched, s);
         } else {
           b.msrc = a.part + (size_t)(2 * k - 2) * a.part_stride;
           b.mop = k == 1 ? MERGE_MIN : MERGE_MEAN;

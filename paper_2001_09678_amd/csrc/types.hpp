@@ -5,9 +5,11 @@
 
 namespace mpvk {
 
-// Scan sources: census (fused cost), a uint8 cost volume, or the merge of the previous
-// layer's two partial volumes (layered path merge).
-enum { SRC_CENSUS = 0, SRC_COST = 1, SRC_MERGE = 2 };
+// Scan sources: census (fused cost), a uint8 cost volume, the merge of the previous
+// layer's two partial volumes (layered path merge), or the census with the occlusion
+// weight of the layered merge (direction up_dir pays twice for disparity increases).
+enum { SRC_CENSUS = 0, SRC_COST = 1, SRC_MERGE = 2, SRC_CENSUS_OCC = 3 };
+constexpr bool src_census(int src) { return src == SRC_CENSUS || src == SRC_CENSUS_OCC; }
 // Merge of two partial volumes: the smaller, or the mean rounded down.
 enum { MERGE_MIN = 0, MERGE_MEAN = 1 };
 enum { OUT_PART = 0, OUT_U16 = 1, OUT_I32 = 2 };
@@ -37,6 +39,7 @@ struct ScanArgs {
   // this scan's slot layout; mop = MERGE_MIN or MERGE_MEAN.
   const uint8_t* msrc;
   int mop;
+  int up_dir;  // SRC_CENSUS_OCC: the direction whose disparity increases cost 2*lambda
 };
 
 // Segment table of a batched launch: global wave u belongs to descriptor s with

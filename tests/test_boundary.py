@@ -147,3 +147,15 @@ def test_layered_merge_limits(L):
     handle = C.c_void_p()
     assert lib.mpv_batch_create(C.byref(pp), C.byref(item), 1, C.byref(handle)) == L.MPV_ERR_UNSUPPORTED
     assert lib.mpv_lb_coarse_workspace_bytes(C.byref(ok), 320, 180) == 0
+
+
+def test_layered_occlusion_limit(L):
+    """With the occlusion strategy the left-to-right pass stores energies up to
+    24 + 2 * lambda * tau even when there is one layer."""
+    lib = L.lib()
+    one = _params(L, num_disp=128, num_paths=2, tau=16, merge=L.MPV_MERGE_LAYERED)       # 24 + 128
+    occ = _params(L, num_disp=128, num_paths=2, tau=16, merge=L.MPV_MERGE_LAYERED_OCC)   # 24 + 256
+    assert lib.mpv_match_workspace_bytes(C.byref(one), 320, 240, None) > 0
+    assert lib.mpv_match_workspace_bytes(C.byref(occ), 320, 240, None) == 0
+    occ8 = _params(L, num_disp=128, num_paths=8, merge=L.MPV_MERGE_LAYERED_OCC)
+    assert lib.mpv_match_workspace_bytes(C.byref(occ8), 320, 240, None) > 0
