@@ -247,6 +247,72 @@ def learned_bench(params, dev, steps, pairs):
     return out
 
 
+def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8):
+    """The paper's hierarchical path merge (Section 3.2, Table alg) on the measured pair:
+    multi-scale and plain full-range frame times, the finest level's scans (four dependent
+    launches, one per layer) with their roofline, per-stage times, and errors against the
+    ground truth next to the sum of the paths on held-out seeded pairs of the same shape."""
+    import dataclasses
+    import torch
+    from paper_2001_09678_amd import _lib as L
+    from paper_2001_09678_amd import learned, mpv
+    from paper_2001_09678_amd.scene import batch_scenes
+    H, W = left.shape
+    P = base.num_paths
+    out = {}
+    for merge in ("layered", "layered_occ"):
+        params = dataclasses.replace(base, merge=merge)
+        pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=sched)
+        ms, per, scan, _ = time_pipeline(pyr, left, right, steps, 10, hook_stage=L.STAGE_SCAN,
+                                         hook_level=levels - 1)
+        plain = mpv.Pyramid(params, W, H, levels=1, radius=4, device=dev, sched=psched)
+        pms, _, pscan, _ = time_pipeline(plain, left, right, max(steps // 4, 10), 3,
+                                         hook_stage=L.STAGE_SCAN, hook_level=0)
+        scan_avg = sum(scan) / len(scan)
+        pscan_avg = sum(pscan) / len(pscan)
+        # bytes of this schedule per evaluated node of the finest level: the first layer
+        # writes two uint8 partials; each later layer reads both partials of the previous
+        # layer in each of its two directions and writes two: 2 + 6 * (P/2 - 1) B per node,
+        # plus both census images once
+        wf, hf = W, H
+        nodes = wf * hf * min(9, base.num_disp)
+        scan_bytes = (2 + 6 * (P // 2 - 1)) * nodes + 2 * 4 * wf * hf
+        pnodes = W * H * 128
+        pscan_bytes = (2 + 6 * (P // 2 - 1)) * pnodes + 2 * 4 * W * H
+        ach = scan_bytes / (scan_avg * 1e-3) / 1e9
+        pach = pscan_bytes / (pscan_avg * 1e-3) / 1e9
+        out[merge] = {
+            "ms_per_step": round(ms, 4), "fps": round(1000.0 / ms, 1),
+            "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
+            "finest_scan_ms": round(scan_avg, 4),
+            "finest_scan_roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                     "algorithmic_bytes": scan_bytes, "launches": P // 2},
+            "stage_ms": stage_breakdown(pyr, left, right, levels, reps=10),
+            "plain": {"ms_per_step": round(pms, 4), "fps": round(1000.0 / pms, 1),
+                      "scan_ms": round(pscan_avg, 4),
+                      "scan_roofline": {"bound": "hbm", "achieved": round(pach, 1), "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4)}},
+        }
+    # errors against the ground truth: non-occluded pixels that are invalid or off by > 1
+    specs = learned.scene_specs(42000, pairs, W, H, base.num_disp)
+    scenes = batch_scenes(specs, workers=16)
+    q = {}
+    for merge in ("sum", "layered", "layered_occ"):
+        params = dataclasses.replace(base, merge=merge)
+        for name, lv in (("multiscale", levels), ("plain", 1)):
+            pyr = mpv.Pyramid(params, W, H, levels=lv, radius=4, device=dev)
+            bad = tot = 0
+            for sc in scenes:
+                d = pyr(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev))
+                b, t = learned.gt_errors(d.cpu(), torch.from_numpy(sc.disp), torch.from_numpy(sc.occluded))
+                bad, tot = bad + b, tot + t
+            q[f"{merge}.{name}"] = round(bad / tot, 5)
+    out["err_gt"] = q
+    out["err_gt_pairs"] = pairs
+    return out
+
+
 def serve_bench(seconds, per_rig=8, saturate=32):
     """Frame-stream service: 8 rigs at 30 fps (shapes and ranges drawn by seed 5), HBM-budget
     admission, continuous batching on 2 streams; latency is arrival to download complete,
@@ -325,6 +391,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-layered", action="store_true")
     ap.add_argument("--sched", default=None, help="multi-scale schedule 'waves,full_lanes,band_lanes,order' "
                                                   "(skips the autotuner)")
     ap.add_argument("--plain-sched", default=None, help="plain full-range schedule (skips the autotuner)")
@@ -397,6 +464,8 @@ def main():
     stream = {} if args.no_batch else stream_bench(params, levels, dev, sched, args.batch_steps * 2)
     learned_res = {} if args.no_learned else learned_bench(params, dev, args.plain_steps, args.learned_pairs)
     serve_res = {} if args.no_serve else serve_bench(args.serve_seconds)
+    layered_res = {} if args.no_layered else layered_bench(params, dev, left, right, levels, sched, psched,
+                                                           args.plain_steps * 2)
 
     result = {
         "metric": METRIC,
@@ -445,6 +514,7 @@ def main():
         "stream": stream,
         "learned": learned_res,
         "serve": serve_res,
+        "layered": layered_res,
     }
     if traffic is not None:
         result["roofline"]["traffic_fetch"] = SCAN_TRAFFIC["fetch_bytes"]
