@@ -219,8 +219,8 @@ mpv_status mpv_match(const mpv_params *p, const mpv_image *left, const mpv_image
  * descriptor tables into the workspace and synchronises `stream`) -> run / run_graph any
  * number of times. The items' images and outputs must stay allocated while the batch
  * lives; their contents may change between runs. The handle is host memory owned by the
- * library until mpv_batch_destroy. Batches sum the paths: a layered merge is
- * MPV_ERR_UNSUPPORTED here. */
+ * library until mpv_batch_destroy. With a layered merge every layer is one launch per
+ * kernel variant over all pairs, in turn. */
 typedef struct mpv_batch_s *mpv_batch;
 typedef struct {
     mpv_image left, right; /* device images of one pair */

@@ -31,6 +31,7 @@ FILE_FLAGS = {
     "kern_full.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "kern_full_batch.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "kern_full_merge.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "kern_full_batch_merge.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
 }
 
 

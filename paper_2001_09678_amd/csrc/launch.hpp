@@ -31,6 +31,10 @@ void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, bool
 void scan_full_layered(const ScanArgs& a, int src, int LPL, int K, bool banded, int wpb,
                        hipStream_t s);
 void scan_band_layered(const ScanArgs& a, int src, int LPL, bool var, int wpb, hipStream_t s);
+void scan_full_batch_layered(const Batch<ScanArgs>& b, int src, int units, int LPL, int K, int tau,
+                             bool banded, int wpb, hipStream_t s);
+void scan_band_batch_layered(const Batch<ScanArgs>& b, int src, int units, int LPL, int tau, int wpb,
+                             hipStream_t s);
 
 // Sum + WTA (+ right disparity + LR when need_lr) over P uint8 partial volumes.
 void reduce_part(const RedArgs& a, int need_lr, hipStream_t s);

@@ -270,6 +270,30 @@ RedArgs level_red_args(const mpv_params* p, const ScanArgs& a, const LevelWs& lw
   return ra;
 }
 
+// Layer k of a layered merge (Section 3.2 / Table alg) over the scan arguments of a level:
+// directions 2k, 2k+1 into partial volumes 2k, 2k+1; the data term is the census cost for
+// k = 0 (with the occlusion weight on the left-to-right pass for MPV_MERGE_LAYERED_OCC)
+// and the merge of layer k-1's two volumes (min after the horizontal layer, floor mean
+// after the others) for k > 0. Returns the scan source.
+int layered_layer(const mpv_params* p, ScanArgs& b, int k) {
+  b.dir_base = 2 * k;
+  if (k == 0) {
+    b.up_dir = p->merge == MPV_MERGE_LAYERED_OCC ? 0 : -1;
+    return b.up_dir >= 0 ? SRC_CENSUS_OCC : SRC_CENSUS;
+  }
+  b.msrc = b.part ? b.part + (size_t)(2 * k - 2) * b.part_stride : nullptr;  // null: planning only
+  b.mop = k == 1 ? MERGE_MIN : MERGE_MEAN;
+  return SRC_MERGE;
+}
+
+// The reduce of a layered merge decides on the last layer's merge of its two volumes.
+void layered_reduce(const mpv_params* p, RedArgs& ra) {
+  const int nl = p->num_paths / 2;
+  ra.part = ra.part + (size_t)(2 * nl - 2) * ra.part_stride;
+  ra.npart = 2;
+  ra.merge = 1 + (nl == 1 ? MERGE_MIN : MERGE_MEAN);
+}
+
 // census(L), census(R) -> all P directions -> reduce. disp may be null (intermediate level).
 mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const uint8_t* R,
                      int rpitch, int W, int H, const mpv_band* band, int16_t* disp,
@@ -295,31 +319,18 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
       plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
       launch_scan(a, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
     } else {
-      // Section 3.2 / Table alg: layer k scans the pair 2k, 2k+1 into partial volumes 2k and
-      // 2k+1; its data term is the census cost (k = 0) or the merge of layer k-1's volumes
+      // Section 3.2 / Table alg: one dependent launch per layer
       for (int k = 0; k < nl; ++k) {
         ScanArgs b = a;
+        const int src = layered_layer(p, b, k);
         const int pair[2] = {2 * k, 2 * k + 1};
-        b.dir_base = 2 * k;
         plan_dirs(b, pair, 2, lw.sc.LPL);
-        if (k == 0) {
-          // occlusion strategy: the left-to-right pass pays twice for disparity increases
-          b.up_dir = p->merge == MPV_MERGE_LAYERED_OCC ? 0 : -1;
-          launch_scan(b, lw.sc, b.up_dir >= 0 ? SRC_CENSUS_OCC : SRC_CENSUS, OUT_PART, sched, s);
-        } else {
-          b.msrc = a.part + (size_t)(2 * k - 2) * a.part_stride;
-          b.mop = k == 1 ? MERGE_MIN : MERGE_MEAN;
-          launch_scan(b, lw.sc, SRC_MERGE, OUT_PART, sched, s);
-        }
+        launch_scan(b, lw.sc, src, OUT_PART, sched, s);
       }
     }
   }
   RedArgs ra = level_red_args(p, a, lw, disp, right, raw, nb);
-  if (p->merge != MPV_MERGE_SUM) {  // decide on the last layer's merge
-    ra.part = a.part + (size_t)(2 * nl - 2) * a.part_stride;
-    ra.npart = 2;
-    ra.merge = 1 + (nl == 1 ? MERGE_MIN : MERGE_MEAN);
-  }
+  if (p->merge != MPV_MERGE_SUM) layered_reduce(p, ra);
   {
     HookScope hs(MPV_STAGE_REDUCE, level, s);
     mpvl::reduce_part(ra, ra.need_lr, s);
@@ -436,6 +447,7 @@ struct mpv_batch_s {
     int nseg, units;             // units: waves (scans), blocks (others)
     int LPL, K, tau, stride;
     bool masked;
+    int src;  // scans: SRC_CENSUS, or a layered merge's SRC_CENSUS_OCC / SRC_MERGE
   };
   std::vector<Launch> launches;  // execution order
   hipGraph_t graph = nullptr;
@@ -554,16 +566,24 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
     std::vector<Key> keys;
     for (int i = 0; i < n; ++i)
       if (std::find(keys.begin(), keys.end(), key_of(i)) == keys.end()) keys.push_back(key_of(i));
+    // sum: one launch per variant with every direction of every pair; layered merge: the
+    // layers in turn, each one launch per variant with its two directions of every pair
+    const bool layered = b.p.base.merge != MPV_MERGE_SUM;
+    const int nstage = layered ? b.p.base.num_paths / 2 : 1;
+    for (int stage = 0; stage < nstage; ++stage)
     for (const Key& k : keys) {
       struct Item {
         ScanArgs a;
         int len;
       };
       std::vector<Item> items;
+      int src = SRC_CENSUS;
       for (int i = 0; i < n; ++i) {
         if (!(key_of(i) == k)) continue;
-        for (int r = 0; r < b.p.base.num_paths; ++r) {
+        const int r0 = layered ? 2 * stage : 0, r1 = layered ? 2 * stage + 2 : b.p.base.num_paths;
+        for (int r = r0; r < r1; ++r) {
           ScanArgs a = sargs[i];
+          if (layered) src = layered_layer(&b.p.base, a, stage);
           a.dir_base = r;
           plan_dirs(a, &r, 1, k.LPL);
           items.push_back({a, line_len_host(r, a.W, a.H)});
@@ -592,6 +612,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       ln.K = k.K;
       ln.tau = k.tau;
       ln.masked = k.masked;
+      ln.src = src;
       b.launches.push_back(ln);
     }
     // reduce: pairs grouped by partial stride
@@ -621,6 +642,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
                                     last ? pr.item.disp_right : nullptr, raw,
                                     last || !r ? nullptr : &nb);
         if (last && pr.item.disp_raw) ra.raw = pr.item.disp_raw;
+        if (b.p.base.merge != MPV_MERGE_SUM) layered_reduce(&b.p.base, ra);
         d.push_back(ra);
         first.push_back(rows);
         rows += ra.H;
@@ -861,8 +883,6 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
 mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* items, int32_t n,
                             mpv_batch* out) {
   if (!p || !items || n < 1 || !out) return MPV_ERR_INVALID_ARG;
-  if (p->base.merge != MPV_MERGE_SUM) return check_params(&p->base, true) ? MPV_ERR_INVALID_ARG
-                                                                         : MPV_ERR_UNSUPPORTED;
   mpv_batch_s* b = new (std::nothrow) mpv_batch_s();
   if (!b) return MPV_ERR_INVALID_ARG;
   b->p = *p;
@@ -936,14 +956,22 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
       }
       case mpv_batch_s::SCAN_FULL: {
         HookScope hs(MPV_STAGE_SCAN, ln.level, s);
-        mpvl::scan_full_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.K,
-                              ln.tau, ln.masked, wpb, s);
+        if (ln.src == SRC_CENSUS)
+          mpvl::scan_full_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.K,
+                                ln.tau, ln.masked, wpb, s);
+        else
+          mpvl::scan_full_batch_layered({(const ScanArgs*)desc, first, ln.nseg}, ln.src, ln.units,
+                                        ln.LPL, ln.K, ln.tau, ln.masked, wpb, s);
         break;
       }
       case mpv_batch_s::SCAN_BAND: {
         HookScope hs(MPV_STAGE_SCAN, ln.level, s);
-        mpvl::scan_band_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.tau,
-                              false, wpb, s);
+        if (ln.src == SRC_CENSUS)
+          mpvl::scan_band_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.tau,
+                                false, wpb, s);
+        else
+          mpvl::scan_band_batch_layered({(const ScanArgs*)desc, first, ln.nseg}, ln.src, ln.units,
+                                        ln.LPL, ln.tau, wpb, s);
         break;
       }
       case mpv_batch_s::REDUCE: {

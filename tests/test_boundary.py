@@ -141,12 +141,17 @@ def test_layered_merge_limits(L):
     img = L.Image(fake, 320, 240, 320)
     assert lib.mpv_match(C.byref(big), C.byref(img), C.byref(img), None, fake, None, None, fake,
                          1 << 40, None) == L.MPV_ERR_UNSUPPORTED
-    # the unfused export, batches and the learned coarse level sum the paths
+    # the unfused export and the learned coarse level sum the paths
     assert lib.mpv_aggregate(C.byref(ok), fake, 320, 240, None, 0, fake, None) == L.MPV_ERR_UNSUPPORTED
+    assert lib.mpv_lb_coarse_workspace_bytes(C.byref(ok), 320, 180) == 0
+    # batches plan the layers (host only: no launch before bind)
     item = L.BatchItem(img, img, 128, fake, None, None)
     handle = C.c_void_p()
-    assert lib.mpv_batch_create(C.byref(pp), C.byref(item), 1, C.byref(handle)) == L.MPV_ERR_UNSUPPORTED
-    assert lib.mpv_lb_coarse_workspace_bytes(C.byref(ok), 320, 180) == 0
+    assert lib.mpv_batch_create(C.byref(pp), C.byref(item), 1, C.byref(handle)) == L.MPV_OK
+    assert lib.mpv_batch_workspace_bytes(handle) > 0
+    lib.mpv_batch_destroy(handle)
+    bad = L.PyramidParams(big, 3, 4)
+    assert lib.mpv_batch_create(C.byref(bad), C.byref(item), 1, C.byref(handle)) != L.MPV_OK
 
 
 def test_layered_occlusion_limit(L):
