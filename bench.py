@@ -154,7 +154,11 @@ def stream_bench(params, levels, dev, sched, steps, frames=16):
     torch.cuda.synchronize()
     scan_ms = sum(kb[i].elapsed_time(ka[i]) for i in range(steps)) / steps
     P = params.num_paths
-    scan_bytes = frames * (P * 1280 * 720 * 9 + 2 * 4 * 1280 * 720)
+    # bytes per finest node: one uint8 partial per direction (sum); for the layered merge the
+    # first layer writes two and every later layer reads two partials per direction and
+    # writes two
+    node_bytes = P if params.merge == "sum" else 2 + 6 * (P // 2 - 1)
+    scan_bytes = frames * (node_bytes * 1280 * 720 * 9 + 2 * 4 * 1280 * 720)
     scan_ops = frames * OPS_PER_NODE_PATH * P * 1280 * 720 * 9
     roof = {"kernel": "k_scan_band_batch (finest level of every frame)", "kernel_ms": round(scan_ms, 4),
             "hbm": {"achieved": round(scan_bytes / (scan_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -289,6 +293,7 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
                                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                                      "algorithmic_bytes": scan_bytes, "launches": P // 2},
             "stage_ms": stage_breakdown(pyr, left, right, levels, reps=10),
+            "stream16": stream_bench(params, levels, dev, sched, 20),
             "plain": {"ms_per_step": round(pms, 4), "fps": round(1000.0 / pms, 1),
                       "scan_ms": round(pscan_avg, 4),
                       "scan_roofline": {"bound": "hbm", "achieved": round(pach, 1), "peak": HBM_PEAK_GBS,

@@ -252,9 +252,11 @@ void mpv_batch_destroy(mpv_batch b);
                                  coarser level's reduce */
 #define MPV_NUM_STAGES 5
 
-/* While set, every later launch of `stage` at pyramid level `level` (0 = coarsest; the
+/* While set, every later run of `stage` at pyramid level `level` (0 = coarsest; the
  * single level of mpv_match is level 0; -1 = any level) is bracketed by
- * hipEventRecord(before) and hipEventRecord(after) on the launch stream. NULL events clear
+ * hipEventRecord(before) and hipEventRecord(after) on the launch stream; a stage made of
+ * several consecutive launches (the layers of a layered merge, kernel variants of a batch)
+ * is bracketed as a whole. NULL events clear
  * the hook. Process-wide host state, not synchronised: set it from the thread that
  * enqueues, between calls. The events are the caller's; the library never creates or
  * destroys them. */

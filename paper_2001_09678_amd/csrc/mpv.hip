@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <optional>
 #include <vector>
 
 #include "../../include/mpv.h"
@@ -940,22 +941,33 @@ mpv_status mpv_batch_bind(mpv_batch b, void* workspace, size_t bytes, hipStream_
 mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
   if (!b || !b->ws) return MPV_ERR_INVALID_ARG;
   const int wpb = wpb_of(b->p.sched);
+  // the consecutive launches of one stage at one level (kernel variants, layers of a
+  // layered merge) are bracketed together by the timing hook
+  std::optional<HookScope> hs;
+  int hs_stage = -1, hs_level = -1;
   for (const auto& ln : b->launches) {
     const void* desc = b->ws + ln.desc_off;
     const int* first = (const int*)(b->ws + ln.first_off);
+    const int stage = ln.kind == mpv_batch_s::DOWN     ? MPV_STAGE_DOWNSAMPLE
+                      : ln.kind == mpv_batch_s::CENSUS ? MPV_STAGE_CENSUS
+                      : ln.kind == mpv_batch_s::REDUCE ? MPV_STAGE_REDUCE
+                                                       : MPV_STAGE_SCAN;
+    if (stage != hs_stage || ln.level != hs_level) {
+      hs.reset();
+      hs.emplace(stage, ln.level, s);
+      hs_stage = stage;
+      hs_level = ln.level;
+    }
     switch (ln.kind) {
       case mpv_batch_s::DOWN: {
-        HookScope hs(MPV_STAGE_DOWNSAMPLE, ln.level, s);
         mpvl::downsample_batch({(const PixArgs*)desc, first, ln.nseg}, ln.units, s);
         break;
       }
       case mpv_batch_s::CENSUS: {
-        HookScope hs(MPV_STAGE_CENSUS, ln.level, s);
         mpvl::census_batch({(const PixArgs*)desc, first, ln.nseg}, ln.units, s);
         break;
       }
       case mpv_batch_s::SCAN_FULL: {
-        HookScope hs(MPV_STAGE_SCAN, ln.level, s);
         if (ln.src == SRC_CENSUS)
           mpvl::scan_full_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.K,
                                 ln.tau, ln.masked, wpb, s);
@@ -965,7 +977,6 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
         break;
       }
       case mpv_batch_s::SCAN_BAND: {
-        HookScope hs(MPV_STAGE_SCAN, ln.level, s);
         if (ln.src == SRC_CENSUS)
           mpvl::scan_band_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.tau,
                                 false, wpb, s);
@@ -975,7 +986,6 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
         break;
       }
       case mpv_batch_s::REDUCE: {
-        HookScope hs(MPV_STAGE_REDUCE, ln.level, s);
         mpvl::reduce_part_batch({(const RedArgs*)desc, first, ln.nseg}, ln.units, ln.stride, s);
         break;
       }
