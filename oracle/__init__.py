@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wextra", "-o", tmp, SRC])
+                               "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -62,6 +62,15 @@ def _load():
         lib.orc_aggregate.restype = i32
         lib.orc_layered.argtypes = [P, i32, i32, i32, P, P, i32, i32, i32, i32, i32, i32, P, P]
         lib.orc_layered.restype = i32
+        lib.orc_path_g.argtypes = [P, i32, i32, i32, P, P, i32, i32, i32, i32, P, i32, i32, P]
+        lib.orc_path_g.restype = i32
+        lib.orc_aggregate_g.argtypes = [P, i32, i32, i32, P, P, i32, i32, C.c_uint32, i32, i32, P, i32,
+                                        i32, P, P, P]
+        lib.orc_aggregate_g.restype = i32
+        lib.orc_layered_g.argtypes = [P, i32, i32, i32, P, P, i32, i32, i32, i32, i32, P, i32, i32, P, P]
+        lib.orc_layered_g.restype = i32
+        lib.orc_grad_weight.argtypes = [i32, i32, i32]
+        lib.orc_grad_weight.restype = i32
         lib.orc_wta_lr.argtypes = [P, i32, i32, i32, P, P, i32, i32, P, P, P]
         lib.orc_propagate.argtypes = [P, i32, i32, i32, i32, i32, i32, P]
         lib.orc_propagate.restype = i32
@@ -103,44 +112,50 @@ def cost(cl, cr, num_disp, lo=None, length=None, cap=None) -> np.ndarray:
     return out
 
 
-def path(cost_vol, num_disp, r, lam, tau, lo=None, length=None, mode=FAST) -> np.ndarray:
+def grad_weight(lam, sigma, g):
+    """Gradient-weighted TV weight of eq. EU for an intensity difference g."""
+    return int(_load().orc_grad_weight(lam, sigma, g))
+
+
+def path(cost_vol, num_disp, r, lam, tau, lo=None, length=None, mode=FAST, img=None, sigma=0) -> np.ndarray:
+    """Energies of direction r; img (left image) and sigma > 0: gradient-weighted TV."""
     cost_vol = _c(cost_vol, np.uint8)
     h, w, cap = cost_vol.shape
-    lo, length = _c(lo, np.int16), _c(length, np.uint8)
+    lo, length, img = _c(lo, np.int16), _c(length, np.uint8), _c(img, np.uint8)
     out = np.empty((h, w, cap), np.int64)
-    rc = _load().orc_path(_p(cost_vol), w, h, num_disp, _p(lo), _p(length), cap, r, lam, tau, mode,
-                          _p(out))
+    rc = _load().orc_path_g(_p(cost_vol), w, h, num_disp, _p(lo), _p(length), cap, r, lam, tau, _p(img),
+                            sigma, mode, _p(out))
     assert rc == 0
     return out
 
 
 def aggregate(cost_vol, num_disp, num_paths, lam, tau, lo=None, length=None, path_mask=0,
-              mode=FAST, per_path=False):
+              mode=FAST, per_path=False, img=None, sigma=0):
     cost_vol = _c(cost_vol, np.uint8)
     h, w, cap = cost_vol.shape
-    lo, length = _c(lo, np.int16), _c(length, np.uint8)
+    lo, length, img = _c(lo, np.int16), _c(length, np.uint8), _c(img, np.uint8)
     S = np.empty((h, w, cap), np.int64)
     scratch = np.empty((h, w, cap), np.int64)
     pp = np.zeros((8, h, w, cap), np.int64) if per_path else None
-    rc = _load().orc_aggregate(_p(cost_vol), w, h, num_disp, _p(lo), _p(length), cap, num_paths,
-                               path_mask, lam, tau, mode, _p(S), _p(scratch), _p(pp))
+    rc = _load().orc_aggregate_g(_p(cost_vol), w, h, num_disp, _p(lo), _p(length), cap, num_paths,
+                                 path_mask, lam, tau, _p(img), sigma, mode, _p(S), _p(scratch), _p(pp))
     assert rc == 0
     return (S, pp) if per_path else S
 
 
 def layered(cost_vol, num_disp, num_layers, lam, tau, lo=None, length=None, occ=False, mode=FAST,
-            per_layer=False):
+            per_layer=False, img=None, sigma=0):
     """The paper's hierarchical merge (Section 3.2, Table alg): layer k merges directions
     2k and 2k+1 over the previous layer's merged energy (the cost for k = 0); min for the
     horizontal layer, floor mean for the others. Returns M [H][W][cap] (int64, absent
     slots INF), and every layer's merged energies when per_layer."""
     cost_vol = _c(cost_vol, np.uint8)
     h, w, cap = cost_vol.shape
-    lo, length = _c(lo, np.int16), _c(length, np.uint8)
+    lo, length, img = _c(lo, np.int16), _c(length, np.uint8), _c(img, np.uint8)
     M = np.empty((h, w, cap), np.int64)
     pl = np.zeros((num_layers, h, w, cap), np.int64) if per_layer else None
-    rc = _load().orc_layered(_p(cost_vol), w, h, num_disp, _p(lo), _p(length), cap, num_layers, lam,
-                             tau, 1 if occ else 0, mode, _p(M), _p(pl))
+    rc = _load().orc_layered_g(_p(cost_vol), w, h, num_disp, _p(lo), _p(length), cap, num_layers, lam,
+                               tau, 1 if occ else 0, _p(img), sigma, mode, _p(M), _p(pl))
     assert rc == 0
     return (M, pl) if per_layer else M
 
@@ -185,14 +200,16 @@ class LevelResult:
 
 
 def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4,
-            lr_max_diff=1, mode=FAST, keep_sums=False, bands=None, merge="sum", occ=False):
+            lr_max_diff=1, mode=FAST, keep_sums=False, bands=None, merge="sum", occ=False,
+            grad_sigma=0):
     """Multi-scale MPV (Section 3.4). Level 0 is the coarsest and searches its full range;
     every finer level searches the band propagated from the level above. ``levels=1`` is
     plain single-scale MPV. ``bands`` optionally replaces the finest level's band by a
     given (lo, len, cap) triple (the learned-band path). ``merge`` = "sum" sums the
     ``num_paths`` directed paths; "layered" runs num_paths / 2 layers of the paper's
     hierarchical merge (``occ``: its occlusion strategy) and takes decisions on the last
-    layer's merged energies."""
+    layer's merged energies. ``grad_sigma`` > 0 weights every transition by the left image's
+    gradient along the path (eq. EU), on each level's own left image."""
     assert merge in ("sum", "layered")
     imgs = [_c(left, np.uint8)], [_c(right, np.uint8)]
     for _ in range(levels - 1):
@@ -214,10 +231,12 @@ def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4
             lo, length, cap = bands
         cl, cr = census(L_img), census(R_img)
         cv = cost(cl, cr, Dl, lo, length, cap)
+        g = L_img if grad_sigma > 0 else None
         if merge == "sum":
-            S = aggregate(cv, Dl, num_paths, lam, tau, lo, length, mode=mode)
+            S = aggregate(cv, Dl, num_paths, lam, tau, lo, length, mode=mode, img=g, sigma=grad_sigma)
         else:
-            S = layered(cv, Dl, num_paths // 2, lam, tau, lo, length, occ=occ, mode=mode)
+            S = layered(cv, Dl, num_paths // 2, lam, tau, lo, length, occ=occ, mode=mode, img=g,
+                        sigma=grad_sigma)
         dl, dr, out = wta_lr(S, Dl, lr_max_diff, lo, length)
         results.append(LevelResult(w, h, Dl, cap, lo, dl, dr, out, S if keep_sums else None))
     return results

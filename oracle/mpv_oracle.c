@@ -32,11 +32,17 @@
  *                    of opposite direction pairs, each pair merged per node (min for the
  *                    horizontal layer, the mean for the others) and passed to the next
  *                    layer as its data term, so the recurrence also runs over int64 data.
+ *
+ * Transition weight: lambda, or (the *_g variants with an image and sigma > 0) the
+ * gradient-weighted TV of eq. EU, lambda * exp(-|G|) with G the intensity difference of
+ * the left image between the two consecutive path pixels divided by sigma, rounded to the
+ * nearest integer (orc_grad_weight).
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <limits.h>
+#include <math.h>
 
 #define ORC_INF (INT64_MAX / 4)
 #define ORC_DEFINITION 0
@@ -126,6 +132,15 @@ void orc_cost(const uint32_t *cl, const uint32_t *cr, int W, int H,
         }
 }
 
+/* Gradient-weighted TV weight of eq. EU: round(lambda * exp(-g / sigma)) for an intensity
+ * difference g >= 0 between consecutive path pixels; sigma <= 0 keeps lambda. */
+int orc_grad_weight(int lambda, int sigma, int g)
+{
+    if (sigma <= 0)
+        return lambda;
+    return (int)floor((double)lambda * exp(-(double)g / (double)sigma) + 0.5);
+}
+
 /* Transition weight from disparity dp at p-r to d at p. up multiplies the weight of an
  * increase of disparity (dp < d); it is 1 except in the left-to-right pass of the layered
  * merge with the occlusion strategy (orc_layered). */
@@ -201,8 +216,8 @@ static void step_fast(const int64_t *c, int b0, int bn, const int64_t *prevL, in
 
 /* L(p, .) for one pixel i whose predecessor along the path is q (q < 0: none). */
 static void path_pixel(const int64_t *data, int D, const int16_t *lo, const uint8_t *len, int cap,
-                       long i, long q, int lambda, int tau, int up, int mode, int64_t *L,
-                       int64_t *scratch)
+                       long i, long q, int lambda, int tau, int up, const uint8_t *img, int sigma,
+                       int mode, int64_t *L, int64_t *scratch)
 {
     int b0, bn;
     band_of(lo, len, cap, i, &b0, &bn);
@@ -213,6 +228,8 @@ static void path_pixel(const int64_t *data, int D, const int16_t *lo, const uint
     }
     int q0, qn;
     band_of(lo, len, cap, q, &q0, &qn);
+    if (img && sigma > 0) /* the weight of the edge q -> i (eq. EU) */
+        lambda = orc_grad_weight(lambda, sigma, abs((int)img[i] - (int)img[q]));
     if (mode == ORC_DEFINITION)
         step_definition(data + i * cap, b0, bn, L + q * cap, q0, qn, lambda, tau, up, L + i * cap,
                         cap);
@@ -228,7 +245,8 @@ static void path_pixel(const int64_t *data, int D, const int16_t *lo, const uint
  * a row depends only on the previous row in scan order, so a row is done in parallel
  * after the one before it. Returns 0, or -1 on bad arguments. */
 static int path_run(const int64_t *data, int W, int H, int D, const int16_t *lo, const uint8_t *len,
-                    int cap, int r, int lambda, int tau, int up, int mode, int64_t *L)
+                    int cap, int r, int lambda, int tau, int up, const uint8_t *img, int sigma,
+                    int mode, int64_t *L)
 {
     if (r < 0 || r > 7 || W <= 0 || H <= 0 || cap <= 0 || D <= 0)
         return -1;
@@ -243,8 +261,8 @@ static int path_run(const int64_t *data, int W, int H, int D, const int16_t *lo,
                     int x = dx > 0 ? s : W - 1 - s;
                     int px = x - dx;
                     long q = (px < 0 || px >= W) ? -1 : (long)y * W + px;
-                    path_pixel(data, D, lo, len, cap, (long)y * W + x, q, lambda, tau, up, mode, L,
-                               scratch);
+                    path_pixel(data, D, lo, len, cap, (long)y * W + x, q, lambda, tau, up, img, sigma,
+                               mode, L, scratch);
                 }
             free(scratch);
         }
@@ -260,8 +278,8 @@ static int path_run(const int64_t *data, int W, int H, int D, const int16_t *lo,
             for (int x = 0; x < W; ++x) {
                 int px = x - dx;
                 long q = (py < 0 || py >= H || px < 0 || px >= W) ? -1 : (long)py * W + px;
-                path_pixel(data, D, lo, len, cap, (long)y * W + x, q, lambda, tau, up, mode, L,
-                           scratch);
+                path_pixel(data, D, lo, len, cap, (long)y * W + x, q, lambda, tau, up, img, sigma,
+                           mode, L, scratch);
             }
             free(scratch);
         }
@@ -269,9 +287,11 @@ static int path_run(const int64_t *data, int W, int H, int D, const int16_t *lo,
     return 0;
 }
 
-/* Energies of one directed path r over the matching cost volume cost[H][W][cap]. */
-int orc_path(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
-             int cap, int r, int lambda, int tau, int mode, int64_t *L)
+/* Energies of one directed path r over the matching cost volume cost[H][W][cap]; img
+ * (the left image [H][W]) and sigma > 0 select the gradient-weighted transition. */
+int orc_path_g(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+               int cap, int r, int lambda, int tau, const uint8_t *img, int sigma, int mode,
+               int64_t *L)
 {
     long n = (long)W * H * cap;
     if (W <= 0 || H <= 0 || cap <= 0)
@@ -279,18 +299,25 @@ int orc_path(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const 
     int64_t *data = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     for (long i = 0; i < n; ++i)
         data[i] = cost[i];
-    int rc = path_run(data, W, H, D, lo, len, cap, r, lambda, tau, 1, mode, L);
+    int rc = path_run(data, W, H, D, lo, len, cap, r, lambda, tau, 1, img, sigma, mode, L);
     free(data);
     return rc;
+}
+
+int orc_path(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+             int cap, int r, int lambda, int tau, int mode, int64_t *L)
+{
+    return orc_path_g(cost, W, H, D, lo, len, cap, r, lambda, tau, NULL, 0, mode, L);
 }
 
 /* Sum of the directed-path energies: S(p,d) = sum over the selected paths of L_r(p,d).
  * The selected paths are the first num_paths directions, further restricted to the bits
  * of path_mask when it is non-zero. Lscratch holds one [H][W][cap] int64 volume; when
  * per_path is non-NULL, path r's energies are also copied to per_path + r*H*W*cap. */
-int orc_aggregate(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
-                  int cap, int num_paths, uint32_t path_mask, int lambda, int tau, int mode,
-                  int64_t *S, int64_t *Lscratch, int64_t *per_path)
+int orc_aggregate_g(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                    int cap, int num_paths, uint32_t path_mask, int lambda, int tau,
+                    const uint8_t *img, int sigma, int mode, int64_t *S, int64_t *Lscratch,
+                    int64_t *per_path)
 {
     long n = (long)W * H * cap;
     if (num_paths < 1 || num_paths > 8)
@@ -300,7 +327,7 @@ int orc_aggregate(const uint8_t *cost, int W, int H, int D, const int16_t *lo, c
     for (int r = 0; r < num_paths; ++r) {
         if (path_mask && !(path_mask & (1u << r)))
             continue;
-        int rc = orc_path(cost, W, H, D, lo, len, cap, r, lambda, tau, mode, Lscratch);
+        int rc = orc_path_g(cost, W, H, D, lo, len, cap, r, lambda, tau, img, sigma, mode, Lscratch);
         if (rc)
             return rc;
         for (long i = 0; i < n; ++i) {
@@ -313,6 +340,14 @@ int orc_aggregate(const uint8_t *cost, int W, int H, int D, const int16_t *lo, c
             memcpy(per_path + (long)r * n, Lscratch, sizeof(int64_t) * (size_t)n);
     }
     return 0;
+}
+
+int orc_aggregate(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                  int cap, int num_paths, uint32_t path_mask, int lambda, int tau, int mode,
+                  int64_t *S, int64_t *Lscratch, int64_t *per_path)
+{
+    return orc_aggregate_g(cost, W, H, D, lo, len, cap, num_paths, path_mask, lambda, tau, NULL, 0,
+                           mode, S, Lscratch, per_path);
 }
 
 /* Layered merge of bi-directional paths (Section 3.2, the hierarchical merging of the
@@ -328,9 +363,9 @@ int orc_aggregate(const uint8_t *cost, int W, int H, int D, const int16_t *lo, c
  * transition weight when the disparity increases. M[H][W][cap] receives the last layer's
  * merged energies (absent slots ORC_INF); per_layer, when non-NULL, receives layer k's at
  * per_layer + k*H*W*cap. Returns 0, or -1 on bad arguments. */
-int orc_layered(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
-                int cap, int num_layers, int lambda, int tau, int occ, int mode, int64_t *M,
-                int64_t *per_layer)
+int orc_layered_g(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                  int cap, int num_layers, int lambda, int tau, int occ, const uint8_t *img,
+                  int sigma, int mode, int64_t *M, int64_t *per_layer)
 {
     long npx = (long)W * H, n = npx * cap;
     if (num_layers < 1 || num_layers > 4 || W <= 0 || H <= 0 || cap <= 0)
@@ -343,9 +378,9 @@ int orc_layered(const uint8_t *cost, int W, int H, int D, const int16_t *lo, con
     int rc = 0;
     for (int k = 0; k < num_layers && rc == 0; ++k) {
         rc = path_run(data, W, H, D, lo, len, cap, 2 * k, lambda, tau, (occ && k == 0) ? 2 : 1,
-                      mode, F);
+                      img, sigma, mode, F);
         if (rc == 0)
-            rc = path_run(data, W, H, D, lo, len, cap, 2 * k + 1, lambda, tau, 1, mode, B);
+            rc = path_run(data, W, H, D, lo, len, cap, 2 * k + 1, lambda, tau, 1, img, sigma, mode, B);
         if (rc)
             break;
 #pragma omp parallel for schedule(static)
@@ -376,6 +411,14 @@ int orc_layered(const uint8_t *cost, int W, int H, int D, const int16_t *lo, con
     free(F);
     free(B);
     return rc;
+}
+
+int orc_layered(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                int cap, int num_layers, int lambda, int tau, int occ, int mode, int64_t *M,
+                int64_t *per_layer)
+{
+    return orc_layered_g(cost, W, H, D, lo, len, cap, num_layers, lambda, tau, occ, NULL, 0, mode,
+                         M, per_layer);
 }
 
 /* Winner-take-all and left-right check.

@@ -24,6 +24,13 @@ int orc_propagate(const int16_t *dl_coarse, int Wc, int Hc, int W, int H, int Dl
 int orc_layered(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
                 int cap, int num_layers, int lambda, int tau, int occ, int mode, int64_t *M,
                 int64_t *per_layer);
+int orc_aggregate_g(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                    int cap, int num_paths, uint32_t path_mask, int lambda, int tau,
+                    const uint8_t *img, int sigma, int mode, int64_t *S, int64_t *Lscratch,
+                    int64_t *per_path);
+int orc_layered_g(const uint8_t *cost, int W, int H, int D, const int16_t *lo, const uint8_t *len,
+                  int cap, int num_layers, int lambda, int tau, int occ, const uint8_t *img,
+                  int sigma, int mode, int64_t *M, int64_t *per_layer);
 
 static uint64_t rng = 0x9E3779B97F4A7C15ull;
 static uint32_t next(void) {
@@ -80,6 +87,21 @@ static int run(int W, int H, int D, int banded, int paths, int tau) {
                 break;
             }
     }
+    /* gradient-weighted transition (left image as the weight source), both modes agree */
+    if (orc_aggregate_g(cost, W, H, D, lo, len, cap, paths, 0, 8, tau, L, 5, 0, S0, scr, per)) bad = 1;
+    if (orc_aggregate_g(cost, W, H, D, lo, len, cap, paths, 0, 8, tau, L, 5, 1, S1, scr, NULL)) bad = 1;
+    for (long i = 0; i < n * cap; ++i)
+        if (S0[i] != S1[i]) {
+            bad = 1;
+            break;
+        }
+    if (orc_layered_g(cost, W, H, D, lo, len, cap, 4, 8, tau, 1, L, 5, 0, S0, per)) bad = 1;
+    if (orc_layered_g(cost, W, H, D, lo, len, cap, 4, 8, tau, 1, L, 5, 1, S1, NULL)) bad = 1;
+    for (long i = 0; i < n * cap; ++i)
+        if (S0[i] != S1[i]) {
+            bad = 1;
+            break;
+        }
     int16_t *dl = malloc(sizeof(int16_t) * n), *dr = malloc(sizeof(int16_t) * n);
     int16_t *out = malloc(sizeof(int16_t) * n);
     orc_wta_lr(S1, W, H, D, lo, len, cap, 1, dl, dr, out);

@@ -16,7 +16,7 @@ def test_oracle_clean_under_asan_ubsan(tmp_path):
     exe = str(tmp_path / "sanitize_oracle")
     cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=all", "-o", exe, os.path.join(HERE, "sanitize_oracle.c"),
-           os.path.join(ROOT, "oracle", "mpv_oracle.c")]
+           os.path.join(ROOT, "oracle", "mpv_oracle.c"), "-lm"]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
     res = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
