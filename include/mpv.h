@@ -109,6 +109,10 @@ typedef struct {
     int32_t lr_max_diff;   /* LR tolerance in px (1 = "1 px"); < 0 disables the check */
     int32_t agg_type;      /* MPV_AGG_U16 or MPV_AGG_I32 (exported sums only) */
     int32_t merge;         /* MPV_MERGE_*: how the directed paths are combined (0 = sum) */
+    int32_t grad_sigma;    /* 0: every transition weighs lambda. 1..255: the gradient-weighted
+                              TV of eq. EU, the edge between consecutive path pixels p-r, p
+                              weighs round(lambda * exp(-|I(p) - I(p-r)| / grad_sigma)) with I
+                              the left image of the level (fused entry points only) */
 } mpv_params;
 
 /* Human-readable status name; never NULL. */

@@ -28,7 +28,7 @@ class Band(C.Structure):
 class Params(C.Structure):
     _fields_ = [("num_disp", C.c_int32), ("census_radius", C.c_int32), ("num_paths", C.c_int32),
                 ("lambda_", C.c_int32), ("tau", C.c_int32), ("lr_max_diff", C.c_int32),
-                ("agg_type", C.c_int32), ("merge", C.c_int32)]
+                ("agg_type", C.c_int32), ("merge", C.c_int32), ("grad_sigma", C.c_int32)]
 
 
 class Schedule(C.Structure):

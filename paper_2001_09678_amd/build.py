@@ -32,6 +32,7 @@ FILE_FLAGS = {
     "kern_full_batch.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "kern_full_merge.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "kern_full_batch_merge.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "kern_full_grad.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
 }
 
 

@@ -177,6 +177,7 @@ __global__ __launch_bounds__(256) void k_census_pyr(CenPyr cp) {
       ++bit;
     }
   cp.out[l][v][(size_t)y * cp.opitch[l] + cp.omargin[l] + x] = val;
+  if (v == 0 && cp.limg[l]) cp.limg[l][(size_t)y * W + x] = (uint8_t)c;
 }
 
 __global__ __launch_bounds__(256) void k_cost(const uint8_t* __restrict__ L, int lpitch,
@@ -345,6 +346,7 @@ struct LineAddr {
   int x0, dx;  // x
   int p0, dp;  // y*W + x
   int c0, dc;  // census offset y*cpitch + cmargin + x
+  int i0, di;  // left image offset y*ipitch + x (gradient-weighted transitions)
   __device__ __forceinline__ int tt(int t) const { return min(t, max(n - 1, 0)); }
   // offsets are non-negative and below 2^32: unsigned 32-bit, added to uniform bases
   __device__ __forceinline__ uint32_t pix(int t) const { return (uint32_t)(p0 + tt(t) * dp); }
@@ -360,6 +362,8 @@ __device__ __forceinline__ LineAddr line_addr(const ScanArgs& a, const Line& ln)
   la.dp = ln.dy * a.W + ln.dx;
   la.c0 = ln.y0 * a.cpitch + a.cmargin + ln.x0;
   la.dc = ln.dy * a.cpitch + ln.dx;
+  la.i0 = ln.y0 * a.ipitch + ln.x0;
+  la.di = ln.dy * a.ipitch + ln.dx;
   return la;
 }
 
@@ -368,7 +372,16 @@ __device__ __forceinline__ uint2 load_chunk(const ScanArgs& a, const LineAddr& l
   int b0 = 0, bn = a.D;
   if constexpr (BANDED) band_at(a.lo, a.len, (size_t)la.pix(t0 + k), a.D, a.cap, b0, bn);
   const uint32_t cl = src_census(SRC) ? ld_u32(a.cl, la.cen(t0 + k)) : 0u;
-  return make_uint2(cl | ((uint32_t)b0 << 24), (uint32_t)bn);
+  uint32_t y = (uint32_t)bn;
+  if constexpr (src_grad(SRC)) {
+    // weight of the edge from step t-1 to step t (eq. EU), in bits 16..23 beside the band
+    // length; double precision, so the rounding matches any correctly rounded exp
+    const int t = la.tt(t0 + k);
+    const int g = abs((int)a.img[la.i0 + t * la.di] - (int)a.img[la.i0 + max(t - 1, 0) * la.di]);
+    const int w = (int)floor((double)a.lambda * exp(-(double)g / (double)a.sigma) + 0.5);
+    y |= (uint32_t)w << 16;
+  }
+  return make_uint2(cl | ((uint32_t)b0 << 24), y);
 }
 
 // Packed-pair shift of the disparity axis by s (s = 1 or even s) inside the group.
@@ -678,8 +691,8 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
   const LineAddr la = line_addr(a, ln);
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
   // occlusion weight of the layered merge: this direction pays 2*lambda per disparity step up
-  const bool occ = SRC == SRC_CENSUS_OCC && r == a.up_dir;
-  const int lam_up = occ ? 2 * a.lambda : a.lambda;
+  const bool occ = src_occ(SRC) && r == a.up_dir;
+  constexpr bool GRAD = src_grad(SRC);
   uint32_t P[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) P[k] = 0;
@@ -700,11 +713,11 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
   const rsrc_t rcr = make_rsrc(a.cr);
   // SRC_MERGE: the lane's 2K slots of both source volumes, loaded PREFETCH steps ahead.
   // off = the step's pixel index times capP; uni: off is wave-uniform (scalar offset).
-  const rsrc_t rmA = make_rsrc(SRC == SRC_MERGE ? a.msrc : a.part);
-  const rsrc_t rmB = make_rsrc(SRC == SRC_MERGE ? a.msrc + a.part_stride : a.part);
+  const rsrc_t rmA = make_rsrc(src_merge(SRC) ? a.msrc : a.part);
+  const rsrc_t rmB = make_rsrc(src_merge(SRC) ? a.msrc + a.part_stride : a.part);
   uint32_t mring[PREFETCH][2];
   auto fetch_m = [&](uint32_t off, bool uni, uint32_t (&dst)[2]) {
-    if constexpr (SRC == SRC_MERGE) {
+    if constexpr (src_merge(SRC)) {
       const uint32_t vo = uni ? (uint32_t)(2 * l * K) : off + 2 * l * K, so = uni ? off : 0u;
       if constexpr (K == 1) {
         dst[0] = buf_ld16(rmA, vo, so);
@@ -731,7 +744,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
   static_for<PREFETCH>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
-    if constexpr (BANDED) bl[q] = group_bcast<LPL, q>((int)cur.y);
+    if constexpr (BANDED || GRAD) bl[q] = group_bcast<LPL, q>((int)cur.y);
     fetch_c(la.cen(q), ring[q]);
     fetch_m(la.pix(q) * (uint32_t)a.capP, false, mring[q]);
   });
@@ -753,7 +766,11 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     const int t = t0 + k;
     const uint32_t w = bw[slot];
     const int b0 = BANDED ? (int)(w >> 24) : 0;
-    const int bn = BANDED ? bl[slot] : a.D;
+    const int bn = BANDED ? (GRAD ? bl[slot] & 0xFFFF : bl[slot]) : a.D;
+    // transition weight of this step: lambda, or the edge's gradient weight (eq. EU)
+    const int lam_s = GRAD ? (int)((uint32_t)bl[slot] >> 16) : a.lambda;
+    const uint32_t lt_s = GRAD ? (uint32_t)(lam_s * a.tau) : lt;
+    const int lam_up = occ ? 2 * lam_s : lam_s;
     uint32_t cr[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) cr[q] = ring[slot][q];
@@ -762,7 +779,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
       constexpr int kn = (k + PREFETCH) % CHUNK;
       const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
       bw[slot] = (uint32_t)group_bcast<LPL, kn>((int)src.x);
-      if constexpr (BANDED) bl[slot] = group_bcast<LPL, kn>((int)src.y);
+      if constexpr (BANDED || GRAD) bl[slot] = group_bcast<LPL, kn>((int)src.y);
       fetch_c(FAST ? cpf : la.cen(t + PREFETCH), ring[slot]);
       fetch_m(FAST ? pst + (uint32_t)PREFETCH * pstep : la.pix(t + PREFETCH) * (uint32_t)a.capP,
               FAST && LPL == 64, mring[slot]);
@@ -782,7 +799,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
           c0 = (x - d0 >= 0) ? c0 : 24u;
           c1 = (x - d0 - 1 >= 0) ? c1 : 24u;
         }
-      } else if constexpr (SRC == SRC_MERGE) {
+      } else if constexpr (src_merge(SRC)) {
         // bytes 2q, 2q+1 of both sources as a 16-bit pair, merged per node
         const uint32_t sel = 0x0c000c00u | ((uint32_t)(2 * q + 1) << 16) | (uint32_t)(2 * q);
         const uint32_t ua = __builtin_amdgcn_perm(0u, mA, sel), ub = __builtin_amdgcn_perm(0u, mB, sel);
@@ -810,18 +827,18 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
     if constexpr (TAU > 0) {
       // complement encoding (u = INF16 - value per half, absent <= 0): max instead of min
       uint32_t E[K];
-      pair_envelope_c<LPL, K, TAU>(P, E, a.lambda, lam_up);
-      const uint32_t cap = t == 0 ? INF2 : splat16(INF16 - lt);
+      pair_envelope_c<LPL, K, TAU>(P, E, lam_s, lam_up);
+      const uint32_t cap = t == 0 ? INF2 : splat16(INF16 - lt_s);
       uint32_t capq[K];
 #pragma unroll
       for (int q = 0; q < K; ++q) capq[q] = cap;
-      if constexpr (SRC == SRC_CENSUS_OCC) {
+      if constexpr (src_occ(SRC)) {
         if (occ && t != 0) {  // the previous minimum + 2*lambda*tau, the best at or above d + lambda*tau
           uint32_t SU[K];
           pair_suffix_max_c<LPL, K>(P, SU);
 #pragma unroll
           for (int q = 0; q < K; ++q)
-            capq[q] = pk_max_i(splat16(INF16 - 2 * lt), pk_sub_i(SU[q], splat16(lt)));
+            capq[q] = pk_max_i(splat16(INF16 - 2 * lt_s), pk_sub_i(SU[q], splat16(lt_s)));
         }
       }
       int mu = -32768;
@@ -846,17 +863,17 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
       }
     } else {
       uint32_t E[K];
-      pair_envelope<LPL, K, TAU>(P, E, a.tau, a.lambda, lam_up);
-      const uint32_t mcap = t == 0 ? 0u : splat16(lt);  // the first pixel has no predecessor
+      pair_envelope<LPL, K, TAU>(P, E, a.tau, lam_s, lam_up);
+      const uint32_t mcap = t == 0 ? 0u : splat16(lt_s);  // the first pixel has no predecessor
       uint32_t mc[K];
 #pragma unroll
       for (int q = 0; q < K; ++q) mc[q] = mcap;
-      if constexpr (SRC == SRC_CENSUS_OCC) {
+      if constexpr (src_occ(SRC)) {
         if (occ && t != 0) {  // the previous minimum (0) + 2*lambda*tau, the best at or above d + lambda*tau
           uint32_t SM[K];
           pair_suffix_min<LPL, K>(P, SM);
 #pragma unroll
-          for (int q = 0; q < K; ++q) mc[q] = pk_min(splat16(2 * lt), pk_add(SM[q], splat16(lt)));
+          for (int q = 0; q < K; ++q) mc[q] = pk_min(splat16(2 * lt_s), pk_add(SM[q], splat16(lt_s)));
         }
       }
 #pragma unroll
@@ -950,8 +967,9 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   const int e = a.tau - 1;
   const uint32_t lt = (uint32_t)(a.lambda * a.tau);
   // occlusion weight of the layered merge: this direction pays 2*lambda per disparity step up
-  const bool occ = SRC == SRC_CENSUS_OCC && r == a.up_dir;
-  const int lam_up = occ ? 2 * a.lambda : a.lambda;
+  const bool occ = src_occ(SRC) && r == a.up_dir;
+  constexpr bool GRAD = src_grad(SRC);
+  constexpr bool BL = VAR || GRAD;  // the second step word (band length, weight) is broadcast
   uint32_t P = INF32;  // normalised energies of the previous pixel (runtime-tau path)
   // compile-time-tau path: unnormalised energies in complement encoding, Pu = INF32 - L
   // (absent 0). L never needs normalising here: the fused path has data terms plus
@@ -960,6 +978,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   // stored bytes, off the step's dependent chain.
   int Pu = 0;
   int capu = 0;  // max over the previous pixel's band of Pu, minus lambda*tau
+  int mprev = 0;  // max over the previous pixel's band of Pu (gradient weights: per step)
   int lo_prev = 0;
   uint32_t acc = 0;
   uint8_t* part = a.part + (long long)(a.dir_base + ri) * a.part_stride;
@@ -976,11 +995,11 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   const uint32_t loff = (uint32_t)(LPL - 1 - j) << 2;
   // SRC_MERGE: this lane's slot of both source volumes (low and high half), loaded
   // PREFETCH steps ahead; off and uni as in the full-range scan.
-  const rsrc_t rmA = make_rsrc(SRC == SRC_MERGE ? a.msrc : a.part);
-  const rsrc_t rmB = make_rsrc(SRC == SRC_MERGE ? a.msrc + a.part_stride : a.part);
+  const rsrc_t rmA = make_rsrc(src_merge(SRC) ? a.msrc : a.part);
+  const rsrc_t rmB = make_rsrc(src_merge(SRC) ? a.msrc + a.part_stride : a.part);
   uint32_t mring[PREFETCH];
   auto fetch_m = [&](uint32_t off, bool uni) -> uint32_t {
-    if constexpr (SRC == SRC_MERGE) {
+    if constexpr (src_merge(SRC)) {
       const uint32_t vo = uni ? (uint32_t)j : off + j, so = uni ? off : 0u;
       return buf_ld8(rmA, vo, so) | (buf_ld8(rmB, vo, so) << 16);
     } else {
@@ -1002,7 +1021,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   static_for<PREFETCH>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     bw[q] = (uint32_t)group_bcast<LPL, q>((int)cur.x);
-    if constexpr (VAR) bl[q] = group_bcast<LPL, q>((int)cur.y);
+    if constexpr (BL) bl[q] = group_bcast<LPL, q>((int)cur.y);
     ring[q] = fetch_c(la.cen(q), bw[q]);
     mring[q] = fetch_m(la.pix(q) * (uint32_t)a.capP, false);
   });
@@ -1016,14 +1035,18 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     const int t = t0 + k;
     const uint32_t w = bw[slot];
     const int b0 = (int)(w >> 24);
-    const int bn = VAR ? bl[slot] : a.cap;
+    const int bn = VAR ? (GRAD ? bl[slot] & 0xFFFF : bl[slot]) : a.cap;
+    // transition weight of this step: lambda, or the edge's gradient weight (eq. EU)
+    const int lam_s = GRAD ? (int)((uint32_t)bl[slot] >> 16) : a.lambda;
+    const uint32_t lt_s = GRAD ? (uint32_t)(lam_s * a.tau) : lt;
+    const int lam_up = occ ? 2 * lam_s : lam_s;
     const uint32_t crv = ring[slot];
     const uint32_t mv = mring[slot];
     {  // step t + PREFETCH: broadcast its word and issue its census (or source) loads
       constexpr int kn = (k + PREFETCH) % CHUNK;
       const uint2 src = k + PREFETCH < CHUNK ? cur : nxt;
       const uint32_t wn = (uint32_t)group_bcast<LPL, kn>((int)src.x);
-      if constexpr (VAR) bl[slot] = group_bcast<LPL, kn>((int)src.y);
+      if constexpr (BL) bl[slot] = group_bcast<LPL, kn>((int)src.y);
       bw[slot] = wn;
       ring[slot] = fetch_c(FAST ? cpf : la.cen(t + PREFETCH), wn);
       mring[slot] = fetch_m(FAST ? pst + (uint32_t)PREFETCH * pstep
@@ -1038,7 +1061,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
         pc = (x - b0 - j >= 0) ? pc : 24u;
       }
       C = pc + ((j < bn) ? 0u : INF32);
-    } else if constexpr (SRC == SRC_MERGE) {
+    } else if constexpr (src_merge(SRC)) {
       const uint32_t ua = mv & 0xFFu, ub = mv >> 16;
       C = (j < bn) ? (a.mop == MERGE_MEAN ? (ua + ub) >> 1 : min(ua, ub)) : INF32;
     } else {
@@ -1048,17 +1071,17 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     const int src = j + (b0 - lo_prev) + e;
     if constexpr (TAU > 0) {
       // complement encoding: Pu = INF32 - P (absent 0), larger is better
-      int E = band_envelope_c<LPL, TAU>(Pu, a.lambda, lam_up);  // lane i <-> position i - e
-      if constexpr (SRC == SRC_CENSUS_OCC) {
-        if (occ) E = max(E, suffix_max_lanes<LPL>(zshift_up<LPL, TAU - 1>(Pu)) - (int)lt);
+      int E = band_envelope_c<LPL, TAU>(Pu, lam_s, lam_up);  // lane i <-> position i - e
+      if constexpr (src_occ(SRC)) {
+        if (occ) E = max(E, suffix_max_lanes<LPL>(zshift_up<LPL, TAU - 1>(Pu)) - (int)lt_s);
       }
       const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
       int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
-      int cu = capu;
-      if constexpr (SRC == SRC_CENSUS_OCC) {
+      int cu = GRAD ? mprev - (int)lt_s : capu;
+      if constexpr (src_occ(SRC)) {
         if (occ) {
-          if (src < 0) Ev = capu;  // every node of p-r lies at least tau above d
-          cu = capu - (int)lt;     // increases of tau or more cost 2*lambda*tau
+          if (src < 0) Ev = cu;  // every node of p-r lies at least tau above d
+          cu -= (int)lt_s;       // increases of tau or more cost 2*lambda*tau
         }
       }
       const int Mu = t == 0 ? (int)INF32 : max(Ev, cu);
@@ -1070,22 +1093,23 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       else
         mu = group_max<LPL>(Lu);
       capu = mu - (int)lt;
+      if constexpr (GRAD) mprev = mu;
       L = (j < bn) ? INF32 - (uint32_t)Lu : INF32;  // canonical energy itself
       m = 0;                                          // (no offset to carry)
       P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;    // energy minus the line minimum
     } else {
-      uint32_t E = band_envelope<LPL, TAU>(P, a.tau, a.lambda, lam_up);  // lane i <-> position i - e
-      if constexpr (SRC == SRC_CENSUS_OCC) {
-        if (occ) E = min(E, suffix_min_lanes<LPL>(shift_up<LPL>(P, a.tau - 1, INF32), INF32) + lt);
+      uint32_t E = band_envelope<LPL, TAU>(P, a.tau, lam_s, lam_up);  // lane i <-> position i - e
+      if constexpr (src_occ(SRC)) {
+        if (occ) E = min(E, suffix_min_lanes<LPL>(shift_up<LPL>(P, a.tau - 1, INF32), INF32) + lt_s);
       }
       const uint32_t got =
           (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, (int)E);
       uint32_t Ev = ((unsigned)src < (unsigned)LPL) ? got : INF32;
-      uint32_t cl = lt;
-      if constexpr (SRC == SRC_CENSUS_OCC) {
+      uint32_t cl = lt_s;
+      if constexpr (src_occ(SRC)) {
         if (occ) {
-          if (src < 0) Ev = lt;  // every node of p-r lies at least tau above d
-          cl = 2 * lt;           // increases of tau or more cost 2*lambda*tau
+          if (src < 0) Ev = lt_s;  // every node of p-r lies at least tau above d
+          cl = 2 * lt_s;           // increases of tau or more cost 2*lambda*tau
         }
       }
       L = C + (t == 0 ? 0u : min(Ev, cl));

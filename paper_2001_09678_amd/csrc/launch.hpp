@@ -35,6 +35,10 @@ void scan_full_batch_layered(const Batch<ScanArgs>& b, int src, int units, int L
                              bool banded, int wpb, hipStream_t s);
 void scan_band_batch_layered(const Batch<ScanArgs>& b, int src, int units, int LPL, int tau, int wpb,
                              hipStream_t s);
+// Gradient-weighted transitions (src includes SRC_GRAD; base SRC_CENSUS, SRC_CENSUS_OCC or
+// SRC_MERGE): single-descriptor launches.
+void scan_full_grad(const ScanArgs& a, int src, int LPL, int K, bool banded, int wpb, hipStream_t s);
+void scan_band_grad(const ScanArgs& a, int src, int LPL, bool var, int wpb, hipStream_t s);
 
 // Sum + WTA (+ right disparity + LR when need_lr) over P uint8 partial volumes.
 void reduce_part(const RedArgs& a, int need_lr, hipStream_t s);

@@ -43,6 +43,7 @@ mpv_status check_params(const mpv_params* p, bool fused) {
   if (p->agg_type != MPV_AGG_U16 && p->agg_type != MPV_AGG_I32) return MPV_ERR_INVALID_ARG;
   if (p->merge != MPV_MERGE_SUM && p->merge != MPV_MERGE_LAYERED && p->merge != MPV_MERGE_LAYERED_OCC)
     return MPV_ERR_INVALID_ARG;
+  if (p->grad_sigma < 0 || p->grad_sigma > 255) return MPV_ERR_INVALID_ARG;
   if (p->merge != MPV_MERGE_SUM) {
     if (p->num_paths < 2) return MPV_ERR_INVALID_ARG;
     // layer k's merged energies are at most 24 + (k+1)*lambda*tau (each pass adds at most
@@ -168,7 +169,12 @@ int wpb_of(const mpv_schedule& s) { return s.waves_per_block ? s.waves_per_block
 
 void launch_scan(const ScanArgs& a, const ScanChoice& c, int src, int out, const mpv_schedule& s,
                  hipStream_t st) {
-  if (src == SRC_MERGE || src == SRC_CENSUS_OCC) {
+  if (src_grad(src)) {
+    if (c.banded_kernel)
+      mpvl::scan_band_grad(a, src, c.LPL, a.len != nullptr, wpb_of(s), st);
+    else
+      mpvl::scan_full_grad(a, src, c.LPL, c.K, c.masked, wpb_of(s), st);
+  } else if (src == SRC_MERGE || src == SRC_CENSUS_OCC) {
     if (c.banded_kernel)
       mpvl::scan_band_layered(a, src, c.LPL, a.len != nullptr, wpb_of(s), st);
     else
@@ -296,13 +302,21 @@ void layered_reduce(const mpv_params* p, RedArgs& ra) {
 }
 
 // census(L), census(R) -> all P directions -> reduce. disp may be null (intermediate level).
+// gimg/gpitch: the left image of the level for gradient-weighted transitions (defaults to L).
 mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const uint8_t* R,
                      int rpitch, int W, int H, const mpv_band* band, int16_t* disp,
                      int16_t* right, int16_t* raw, uint8_t* ws, int level,
                      const mpv_schedule& sched, hipStream_t s, const NextBand* nb = nullptr,
-                     uint32_t* const* cen = nullptr) {
+                     uint32_t* const* cen = nullptr, const uint8_t* gimg = nullptr,
+                     int gpitch = 0) {
   const LevelWs lw = level_ws(p, W, H, band, sched, cen == nullptr);
   ScanArgs a = level_scan_args(p, W, H, band, lw, ws);
+  const int grad = p->grad_sigma > 0 ? SRC_GRAD : 0;
+  if (grad) {  // eq. EU: transitions weighted by the left image's gradient along the path
+    a.img = gimg ? gimg : L;
+    a.ipitch = gimg ? gpitch : lpitch;
+    a.sigma = p->grad_sigma;
+  }
   if (cen) {  // census computed beforehand, in the same layout (cpitch, cmargin)
     a.cl = cen[0];
     a.cr = cen[1];
@@ -318,7 +332,7 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
       int dirs[8];
       for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
       plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
-      launch_scan(a, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
+      launch_scan(a, lw.sc, SRC_CENSUS | grad, OUT_PART, sched, s);
     } else {
       // Section 3.2 / Table alg: one dependent launch per layer
       for (int k = 0; k < nl; ++k) {
@@ -326,7 +340,7 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
         const int src = layered_layer(p, b, k);
         const int pair[2] = {2 * k, 2 * k + 1};
         plan_dirs(b, pair, 2, lw.sc.LPL);
-        launch_scan(b, lw.sc, src, OUT_PART, sched, s);
+        launch_scan(b, lw.sc, src | grad, OUT_PART, sched, s);
       }
     }
   }
@@ -372,6 +386,7 @@ mpv_status pyr_geom(const mpv_pyramid_params* p, int D, int W, int H, PyrGeom& g
 
 struct PyrWs {
   size_t img_off[MPV_MAX_LEVELS];  // left at off, right at off + W*H
+  size_t gimg_off[MPV_MAX_LEVELS];  // mpv_pyramid with gradient weights: left image of level l
   size_t raw_off[MPV_MAX_LEVELS];
   size_t lo_off[2];  // band starts: level l reads buffer l & 1, its reduce writes the other
   size_t cen_off[MPV_MAX_LEVELS];  // mpv_pyramid: census of both views of every level
@@ -394,6 +409,10 @@ PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g, bool fused_census = 
   for (int l = 0; l + 1 < g.L && !fused_census; ++l) {
     w.img_off[l] = off;
     off += align_up((size_t)2 * g.W[l] * g.H[l]);
+  }
+  for (int l = 0; l + 1 < g.L && fused_census && p->base.grad_sigma > 0; ++l) {
+    w.gimg_off[l] = off;
+    off += align_up((size_t)g.W[l] * g.H[l]);
   }
   for (int l = 0; l < g.L; ++l) {
     w.raw_off[l] = off;
@@ -714,7 +733,7 @@ mpv_status mpv_aggregate(const mpv_params* p, const uint8_t* cost, int32_t W, in
                          hipStream_t stream) {
   mpv_status st = check_params(p, false);
   if (st) return st;
-  if (p->merge != MPV_MERGE_SUM) return MPV_ERR_UNSUPPORTED;
+  if (p->merge != MPV_MERGE_SUM || p->grad_sigma != 0) return MPV_ERR_UNSUPPORTED;
   if (!cost || !agg || W < 1 || H < 1) return MPV_ERR_INVALID_ARG;
   if ((st = check_band(band, p->num_disp))) return st;
   const bool banded = band && band->lo;
@@ -847,6 +866,8 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     cp.tiles_x[l] = (g.W[l] + 63) / 64;
     cp.first[l] = blocks;
     blocks += cp.tiles_x[l] * ((g.H[l] + 3) / 4);
+    // gradient-weighted transitions need the coarse levels' left images (the finest is the input)
+    cp.limg[l] = (p->base.grad_sigma > 0 && l + 1 < L) ? ws + w.gimg_off[l] : nullptr;
   }
   cp.first[L] = blocks;
   {
@@ -870,7 +891,8 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     if (last && out->disp_raw && !out->level_raw[l]) raw = out->disp_raw;
     st = run_level(&lpar, nullptr, 0, nullptr, 0, g.W[l], g.H[l], l > 0 ? &b : nullptr,
                    last ? out->disp : nullptr, last ? out->disp_right : nullptr, raw,
-                   ws + w.level_off, l, p->sched, stream, last ? nullptr : &nb, cen[l]);
+                   ws + w.level_off, l, p->sched, stream, last ? nullptr : &nb, cen[l],
+                   last ? left->data : cp.limg[l], last ? left->pitch : g.W[l]);
     if (st) return st;
     if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
       if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),
@@ -884,6 +906,8 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
 mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* items, int32_t n,
                             mpv_batch* out) {
   if (!p || !items || n < 1 || !out) return MPV_ERR_INVALID_ARG;
+  if (p->base.grad_sigma != 0)
+    return check_params(&p->base, true) ? MPV_ERR_INVALID_ARG : MPV_ERR_UNSUPPORTED;
   mpv_batch_s* b = new (std::nothrow) mpv_batch_s();
   if (!b) return MPV_ERR_INVALID_ARG;
   b->p = *p;
@@ -1027,7 +1051,8 @@ void mpv_batch_destroy(mpv_batch b) {
 
 // ---- learned band proposal: coarse level + features --------------------------------------
 size_t mpv_lb_coarse_workspace_bytes(const mpv_params* p, int32_t W0, int32_t H0) {
-  if (check_params(p, true) || p->merge != MPV_MERGE_SUM || W0 < 1 || H0 < 1 || W0 > MPV_MAX_WIDTH)
+  if (check_params(p, true) || p->merge != MPV_MERGE_SUM || p->grad_sigma != 0 || W0 < 1 || H0 < 1 ||
+      W0 > MPV_MAX_WIDTH)
     return 0;
   const LevelWs lw = level_ws(p, W0, H0, nullptr, mpv_schedule{});
   return lw.fits ? lw.total : 0;
@@ -1038,7 +1063,7 @@ mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_
                          size_t workspace_bytes, hipStream_t stream) {
   mpv_status st = check_params(p, true);
   if (st) return st;
-  if (p->merge != MPV_MERGE_SUM) return MPV_ERR_UNSUPPORTED;
+  if (p->merge != MPV_MERGE_SUM || p->grad_sigma != 0) return MPV_ERR_UNSUPPORTED;
   if (!valid_image(left0) || !valid_image(right0) || !feat || !raw0 || !disp0)
     return MPV_ERR_INVALID_ARG;
   if (left0->width != right0->width || left0->height != right0->height) return MPV_ERR_INVALID_ARG;

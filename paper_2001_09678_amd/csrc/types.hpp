@@ -8,8 +8,15 @@ namespace mpvk {
 // Scan sources: census (fused cost), a uint8 cost volume, the merge of the previous
 // layer's two partial volumes (layered path merge), or the census with the occlusion
 // weight of the layered merge (direction up_dir pays twice for disparity increases).
-enum { SRC_CENSUS = 0, SRC_COST = 1, SRC_MERGE = 2, SRC_CENSUS_OCC = 3 };
-constexpr bool src_census(int src) { return src == SRC_CENSUS || src == SRC_CENSUS_OCC; }
+// SRC_GRAD (or-ed into a source): gradient-weighted transition of eq. EU, the weight of
+// each edge along the line is round(lambda * exp(-|I(p) - I(p-r)| / sigma)) of the left
+// image of the level.
+enum { SRC_CENSUS = 0, SRC_COST = 1, SRC_MERGE = 2, SRC_CENSUS_OCC = 3, SRC_GRAD = 8 };
+constexpr int src_base(int src) { return src & 7; }
+constexpr bool src_grad(int src) { return (src & SRC_GRAD) != 0; }
+constexpr bool src_census(int src) { return src_base(src) == SRC_CENSUS || src_base(src) == SRC_CENSUS_OCC; }
+constexpr bool src_merge(int src) { return src_base(src) == SRC_MERGE; }
+constexpr bool src_occ(int src) { return src_base(src) == SRC_CENSUS_OCC; }
 // Merge of two partial volumes: the smaller, or the mean rounded down.
 enum { MERGE_MIN = 0, MERGE_MEAN = 1 };
 enum { OUT_PART = 0, OUT_U16 = 1, OUT_I32 = 2 };
@@ -40,6 +47,9 @@ struct ScanArgs {
   const uint8_t* msrc;
   int mop;
   int up_dir;  // SRC_CENSUS_OCC: the direction whose disparity increases cost 2*lambda
+  // SRC_GRAD: the left image of the level ([H][ipitch]) and sigma >= 1
+  const uint8_t* img;
+  int ipitch, sigma;
 };
 
 // Segment table of a batched launch: global wave u belongs to descriptor s with
@@ -93,6 +103,7 @@ struct CenPyr {
   int L;
   int W[4], H[4];
   uint32_t* out[4][2];  // census of level l, view v: uint32 at y*opitch + omargin + x
+  uint8_t* limg[4];     // optional: the left image of level l, [H][W] (null: not written)
   int opitch[4], omargin[4];
   int tiles_x[4];
   int first[5];  // first block of each level (64x4 outputs per block)

@@ -27,6 +27,8 @@ class MPVParams:
     # path merge: "sum", or the hierarchical merge of Section 3.2 (Table alg), "layered",
     # or "layered_occ" with its occlusion strategy
     merge: str = "sum"
+    # 0: constant lambda; 1..255: gradient-weighted TV of eq. EU (lambda * e^(-|dI| / sigma))
+    grad_sigma: int = 0
 
     _MERGES = {"sum": _L.MPV_MERGE_SUM, "layered": _L.MPV_MERGE_LAYERED,
                "layered_occ": _L.MPV_MERGE_LAYERED_OCC}
@@ -36,7 +38,7 @@ class MPVParams:
             raise ValueError(f"merge must be one of {sorted(self._MERGES)}")
         return _L.Params(self.num_disp, 2, self.num_paths, self.lam, self.tau, self.lr_max_diff,
                          _L.MPV_AGG_U16 if self.agg_type == "u16" else _L.MPV_AGG_I32,
-                         self._MERGES[self.merge])
+                         self._MERGES[self.merge], self.grad_sigma)
 
 
 def _stream():

@@ -164,3 +164,27 @@ def test_layered_occlusion_limit(L):
     assert lib.mpv_match_workspace_bytes(C.byref(occ), 320, 240, None) == 0
     occ8 = _params(L, num_disp=128, num_paths=8, merge=L.MPV_MERGE_LAYERED_OCC)
     assert lib.mpv_match_workspace_bytes(C.byref(occ8), 320, 240, None) > 0
+
+
+def test_gradient_weight_limits(L):
+    """grad_sigma is 0 (constant lambda) or 1..255; only the fused entry points, which see
+    the left image, take gradient weights."""
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    ok = _params(L, num_disp=128, num_paths=8, grad_sigma=16)
+    assert lib.mpv_match_workspace_bytes(C.byref(ok), 320, 240, None) > 0
+    pp = L.PyramidParams(ok, 3, 4)
+    plain = L.PyramidParams(_params(L, num_disp=128, num_paths=8), 3, 4)
+    # the pyramid keeps the coarse levels' left images for the weights
+    assert lib.mpv_pyramid_workspace_bytes(C.byref(pp), 1280, 720) >= \
+        lib.mpv_pyramid_workspace_bytes(C.byref(plain), 1280, 720) + 640 * 360 + 320 * 180
+    for sigma in (-1, 256):
+        p = _params(L, grad_sigma=sigma)
+        assert lib.mpv_match_workspace_bytes(C.byref(p), 320, 240, None) == 0
+        assert lib.mpv_cost(C.byref(p), None, None, None, fake, None) == L.MPV_ERR_INVALID_ARG
+    assert lib.mpv_aggregate(C.byref(ok), fake, 320, 240, None, 0, fake, None) == L.MPV_ERR_UNSUPPORTED
+    img = L.Image(fake, 320, 240, 320)
+    item = L.BatchItem(img, img, 128, fake, None, None)
+    handle = C.c_void_p()
+    assert lib.mpv_batch_create(C.byref(pp), C.byref(item), 1, C.byref(handle)) == L.MPV_ERR_UNSUPPORTED
+    assert lib.mpv_lb_coarse_workspace_bytes(C.byref(ok), 320, 180) == 0
