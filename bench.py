@@ -251,11 +251,16 @@ def learned_bench(params, dev, steps, pairs):
     return out
 
 
+GRAD_SIGMA = 16  # gradient weight scale, picked on pairs 43000-43007 (evaluated on 42000 on)
+
+
 def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8):
-    """The paper's hierarchical path merge (Section 3.2, Table alg) on the measured pair:
-    multi-scale and plain full-range frame times, the finest level's scans (four dependent
-    launches, one per layer) with their roofline, per-stage times, and errors against the
-    ground truth next to the sum of the paths on held-out seeded pairs of the same shape."""
+    """The paper's hierarchical path merge (Section 3.2, Table alg), alone, with its
+    occlusion strategy, and with the gradient-weighted TV of eq. EU as well, on the measured
+    pair: multi-scale and plain full-range frame times, the finest level's scans (four
+    dependent launches, one per layer) with their roofline, per-stage times, 16 frames in
+    flight, and errors against the ground truth next to the sum of the paths on held-out
+    seeded pairs of the same shape."""
     import dataclasses
     import torch
     from paper_2001_09678_amd import _lib as L
@@ -264,8 +269,10 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
     H, W = left.shape
     P = base.num_paths
     out = {}
-    for merge in ("layered", "layered_occ"):
-        params = dataclasses.replace(base, merge=merge)
+    variants = {"layered": ("layered", 0), "layered_occ": ("layered_occ", 0),
+                "layered_occ_grad": ("layered_occ", GRAD_SIGMA)}
+    for name_v, (merge, sigma) in variants.items():
+        params = dataclasses.replace(base, merge=merge, grad_sigma=sigma)
         pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=sched)
         ms, per, scan, _ = time_pipeline(pyr, left, right, steps, 10, hook_stage=L.STAGE_SCAN,
                                          hook_level=levels - 1)
@@ -285,7 +292,8 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
         pscan_bytes = (2 + 6 * (P // 2 - 1)) * pnodes + 2 * 4 * W * H
         ach = scan_bytes / (scan_avg * 1e-3) / 1e9
         pach = pscan_bytes / (pscan_avg * 1e-3) / 1e9
-        out[merge] = {
+        out[name_v] = {
+            "merge": merge, "grad_sigma": sigma,
             "ms_per_step": round(ms, 4), "fps": round(1000.0 / ms, 1),
             "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
             "finest_scan_ms": round(scan_avg, 4),
@@ -293,7 +301,8 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
                                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                                      "algorithmic_bytes": scan_bytes, "launches": P // 2},
             "stage_ms": stage_breakdown(pyr, left, right, levels, reps=10),
-            "stream16": stream_bench(params, levels, dev, sched, 20),
+            # batches take no gradient weights (they have no per-level left images)
+            "stream16": stream_bench(params, levels, dev, sched, 20) if sigma == 0 else None,
             "plain": {"ms_per_step": round(pms, 4), "fps": round(1000.0 / pms, 1),
                       "scan_ms": round(pscan_avg, 4),
                       "scan_roofline": {"bound": "hbm", "achieved": round(pach, 1), "peak": HBM_PEAK_GBS,
@@ -303,8 +312,10 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
     specs = learned.scene_specs(42000, pairs, W, H, base.num_disp)
     scenes = batch_scenes(specs, workers=16)
     q = {}
-    for merge in ("sum", "layered", "layered_occ"):
-        params = dataclasses.replace(base, merge=merge)
+    for merge, sigma in (("sum", 0), ("sum", GRAD_SIGMA), ("layered", 0), ("layered_occ", 0),
+                         ("layered_occ", GRAD_SIGMA)):
+        params = dataclasses.replace(base, merge=merge, grad_sigma=sigma)
+        tag = merge + (f"_grad{sigma}" if sigma else "")
         for name, lv in (("multiscale", levels), ("plain", 1)):
             pyr = mpv.Pyramid(params, W, H, levels=lv, radius=4, device=dev)
             bad = tot = 0
@@ -312,7 +323,7 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
                 d = pyr(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev))
                 b, t = learned.gt_errors(d.cpu(), torch.from_numpy(sc.disp), torch.from_numpy(sc.occluded))
                 bad, tot = bad + b, tot + t
-            q[f"{merge}.{name}"] = round(bad / tot, 5)
+            q[f"{tag}.{name}"] = round(bad / tot, 5)
     out["err_gt"] = q
     out["err_gt_pairs"] = pairs
     return out
