@@ -25,20 +25,18 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 
 # Per-file code-generation choices, each measured on the GPU against the default: the
-# full-range scans schedule best with the backend's iterative ILP strategy (about 2.5 %
-# faster plain single-scale frames); the banded scans are fastest with the default.
-FILE_FLAGS = {
-    "kern_full.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-    "kern_full_batch.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-    "kern_full_merge.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-    "kern_full_batch_merge.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-    "kern_full_grad.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-}
+# full-range scans (units kern_full*) schedule best with the backend's iterative ILP
+# strategy (about 2.5 % faster plain single-scale frames); the banded scans are fastest
+# with the default, and so is the unfused export, which is not on the fused path.
+def file_flags(name: str) -> list[str]:
+    if name.startswith("kern_full") and name != "kern_full_export.hip":
+        return ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
+    return []
 
 
 def _compile(src: str) -> tuple[str, str]:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    extra = FILE_FLAGS.get(os.path.basename(src), [])
+    extra = file_flags(os.path.basename(src))
     res = subprocess.run([HIPCC, *FLAGS, *extra, "-c", "-o", obj, src], capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{res.stdout}{res.stderr}")
@@ -52,7 +50,9 @@ def build(force: bool = True, verbose: bool = False, jobs: int | None = None) ->
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        order = sorted(SOURCES, key=lambda f: -os.path.getsize(f) - (1 << 20) * f.endswith("mpv.hip"))
+        done = dict(zip(order, ex.map(_compile, order)))
+        results = [done[f] for f in SOURCES]
     if verbose:
         for _, err in results:
             if err.strip():

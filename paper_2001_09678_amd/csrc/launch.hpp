@@ -23,8 +23,9 @@ void scan_full(const ScanArgs& a, int LPL, int K, int src, int out, bool banded,
 void scan_full_batch(const Batch<ScanArgs>& b, int units, int LPL, int K, int tau, bool banded,
                      int wpb, hipStream_t s);
 void scan_band(const ScanArgs& a, int LPL, int src, int out, bool var, int wpb, hipStream_t s);
-void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, bool var, int wpb,
-                     hipStream_t s);
+void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, int wpb, hipStream_t s);
+// Unfused export (SRC_COST, OUT_U16 / OUT_I32) of the full-range scans.
+void scan_full_export(const ScanArgs& a, int LPL, int K, int out, bool banded, int wpb, hipStream_t s);
 // Layered path merge: src = SRC_MERGE (later layers: the merge of the previous layer's
 // partials a.msrc, a.mop) or SRC_CENSUS_OCC (first layer with the occlusion weight on
 // a.up_dir); partial output; tau 1, 2, 4 compile-time, others runtime.
@@ -33,12 +34,20 @@ void scan_full_layered(const ScanArgs& a, int src, int LPL, int K, bool banded, 
 void scan_band_layered(const ScanArgs& a, int src, int LPL, bool var, int wpb, hipStream_t s);
 void scan_full_batch_layered(const Batch<ScanArgs>& b, int src, int units, int LPL, int K, int tau,
                              bool banded, int wpb, hipStream_t s);
+// The occlusion-weight source of the layered full-range scans (units of their own).
+void scan_full_occ(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
+void scan_full_batch_occ(const Batch<ScanArgs>& b, int units, int LPL, int K, int tau, bool banded,
+                         int wpb, hipStream_t s);
 void scan_band_batch_layered(const Batch<ScanArgs>& b, int src, int units, int LPL, int tau, int wpb,
                              hipStream_t s);
 // Gradient-weighted transitions (src includes SRC_GRAD; base SRC_CENSUS, SRC_CENSUS_OCC or
 // SRC_MERGE): single-descriptor launches.
 void scan_full_grad(const ScanArgs& a, int src, int LPL, int K, bool banded, int wpb, hipStream_t s);
 void scan_band_grad(const ScanArgs& a, int src, int LPL, bool var, int wpb, hipStream_t s);
+// Units of their own behind scan_full_grad / scan_band_grad.
+void scan_full_grad_occ(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
+void scan_full_grad_merge(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
+void scan_band_grad_merge(const ScanArgs& a, int LPL, bool var, int wpb, hipStream_t s);
 
 // Sum + WTA (+ right disparity + LR when need_lr) over P uint8 partial volumes.
 void reduce_part(const RedArgs& a, int need_lr, hipStream_t s);

@@ -1002,8 +1002,8 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
       }
       case mpv_batch_s::SCAN_BAND: {
         if (ln.src == SRC_CENSUS)
-          mpvl::scan_band_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.tau,
-                                false, wpb, s);
+          mpvl::scan_band_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.tau, wpb,
+                                s);
         else
           mpvl::scan_band_batch_layered({(const ScanArgs*)desc, first, ln.nseg}, ln.src, ln.units,
                                         ln.LPL, ln.tau, wpb, s);
