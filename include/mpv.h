@@ -245,6 +245,30 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t stream);
 mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t stream);
 void mpv_batch_destroy(mpv_batch b);
 
+/* Road profile in v-disparity space (Section 3.5), downstream of the disparity map.
+ *
+ * mpv_vdisparity: the v-disparity image of eq. disp_map, hist[i][j] = the number of pixels
+ * of row j whose disparity is i, for 0 <= i < num_disp (1 .. MPV_MAX_DISP). disp: device
+ * int16 [height][pitch] (pitch >= width, in elements); -1 and values outside [0, num_disp)
+ * are not counted. hist: device uint32 [num_disp][height], every entry written.
+ *
+ * mpv_road: the road profile of eqs. P_hat and e over such a histogram: the path j = P(i)
+ * over every disparity i = 0 .. num_disp-1 whose row grows by 1 to eta-1 per step (2 <=
+ * eta <= 256) and whose sum of counts is largest; e(0,j) = hist[0][j],
+ * e(i,j) = hist[i][j] + max over 0 < j-j' < eta of e(i-1,j'). The end is the smallest row
+ * maximising e(num_disp-1, .), each predecessor the smallest maximising row. path: device
+ * int16 [num_disp] (rows), energy: device int32 [1] (the profile's sum); both -1 when no
+ * row is reachable at the last disparity. Requires height <= MPV_ROAD_MAX_HEIGHT and a
+ * workspace of mpv_road_workspace_bytes (num_disp*height bytes of back-pointers; 0 for
+ * arguments mpv_road rejects). One workgroup: a small downstream step, not a full-chip
+ * kernel. */
+#define MPV_ROAD_MAX_HEIGHT 4096
+mpv_status mpv_vdisparity(const int16_t *disp, int32_t width, int32_t height, int32_t pitch,
+                          int32_t num_disp, uint32_t *hist, hipStream_t stream);
+size_t mpv_road_workspace_bytes(int32_t num_disp, int32_t height);
+mpv_status mpv_road(const uint32_t *hist, int32_t num_disp, int32_t height, int32_t eta, int16_t *path,
+                    int32_t *energy, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Measurement hook (per-kernel timing without a profiler). Stages of one level: */
 #define MPV_STAGE_DOWNSAMPLE 0 /* batches only: mpv_pyramid builds no coarse images */
 #define MPV_STAGE_CENSUS 1     /* mpv_pyramid: one launch for every level, bracketed whatever

@@ -14,6 +14,7 @@ MPV_MERGE_SUM, MPV_MERGE_LAYERED, MPV_MERGE_LAYERED_OCC = 0, 1, 2
 MPV_MAX_LEVELS = 4
 MPV_MAX_DISP = 256
 MPV_MAX_WIDTH = 4096
+MPV_ROAD_MAX_HEIGHT = 4096
 STAGE_DOWNSAMPLE, STAGE_CENSUS, STAGE_SCAN, STAGE_REDUCE, STAGE_PROPAGATE = range(5)
 
 
@@ -83,6 +84,9 @@ def lib():
             "mpv_match": ([C.POINTER(Params), C.POINTER(Image), C.POINTER(Image), C.POINTER(Band),
                            P, P, P, P, S, P], i32),
             "mpv_set_timing_events": ([i32, i32, P, P], i32),
+            "mpv_vdisparity": ([P, i32, i32, i32, i32, P, P], i32),
+            "mpv_road_workspace_bytes": ([i32, i32], S),
+            "mpv_road": ([P, i32, i32, i32, P, P, P, S, P], i32),
             "mpv_batch_create": ([C.POINTER(PyramidParams), C.POINTER(BatchItem), i32, C.POINTER(P)], i32),
             "mpv_batch_workspace_bytes": ([P], S),
             "mpv_batch_bind": ([P, P, S, P], i32),

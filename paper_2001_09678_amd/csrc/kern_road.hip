@@ -1,0 +1,100 @@
+// Road profile in v-disparity space (Section 3.5): the v-disparity image of a disparity
+// map (eq. disp_map) and the max-sum road path over it (eqs. P_hat and e).
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+
+namespace mpvk {
+
+// One block per image row: an LDS histogram of the row's disparities, then column j of
+// the [D][H] v-disparity image. Invalid (-1) and out-of-range disparities are not counted.
+__global__ __launch_bounds__(256) void k_vdisparity(const int16_t* __restrict__ disp, int W, int H,
+                                                    int pitch, int D, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i < D; i += 256) h[i] = 0;
+  __syncthreads();
+  const int16_t* row = disp + (size_t)j * pitch;
+  for (int x = threadIdx.x; x < W; x += 256) {
+    const int d = row[x];
+    if (d >= 0 && d < D) atomicAdd(&h[d], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < D; i += 256) hist[(size_t)i * H + j] = h[i];
+}
+
+// One block: disparity steps i = 1 .. D-1 in turn, each row j a node whose predecessors
+// are the rows j-eta+1 .. j-1 of step i-1 (energies ping-pong in LDS, -1 = unreachable).
+// back[i][j] keeps j minus the chosen predecessor (the smallest row among the maxima); the
+// end is the smallest row maximising the last step, traced back by one thread.
+__global__ __launch_bounds__(1024) void k_road(const uint32_t* __restrict__ hist, int D, int H, int eta,
+                                               uint8_t* __restrict__ back, int16_t* __restrict__ path,
+                                               int32_t* __restrict__ energy) {
+  __shared__ int e[2][ROAD_MAX_HEIGHT];
+  __shared__ unsigned long long s_key[32];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = tid; j < H; j += nt) e[0][j] = (int)hist[j];
+  __syncthreads();
+  for (int i = 1; i < D; ++i) {
+    const int* ep = e[(i - 1) & 1];
+    int* ec = e[i & 1];
+    for (int j = tid; j < H; j += nt) {
+      int best = -1, arg = j;
+      for (int jp = max(0, j - eta + 1); jp < j; ++jp) {
+        const int v = ep[jp];
+        if (v > best) {
+          best = v;
+          arg = jp;
+        }
+      }
+      ec[j] = best >= 0 ? (int)hist[(size_t)i * H + j] + best : -1;
+      back[(size_t)i * H + j] = (uint8_t)(j - arg);
+    }
+    __syncthreads();
+  }
+  // end of the profile: maximum energy, smallest row on ties (key = energy, then ~row)
+  const int* el = e[(D - 1) & 1];
+  unsigned long long key = 0;
+  for (int j = tid; j < H; j += nt)
+    if (el[j] >= 0) {
+      const unsigned long long k = ((unsigned long long)(unsigned)el[j] << 32) | (0xFFFFFFFFu - (unsigned)j);
+      key = k > key ? k : key;
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(key, o);
+    key = other > key ? other : key;
+  }
+  if ((tid & 63) == 0) s_key[tid >> 6] = key;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < (nt + 63) / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
+    if (key == 0) {  // nothing reachable at the last disparity
+      for (int i = 0; i < D; ++i) path[i] = -1;
+      *energy = -1;
+    } else {
+      int j = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFu));
+      *energy = (int32_t)(key >> 32);
+      path[D - 1] = (int16_t)j;
+      for (int i = D - 1; i > 0; --i) {
+        j -= back[(size_t)i * H + j];
+        path[i - 1] = (int16_t)j;
+      }
+    }
+  }
+}
+
+}  // namespace mpvk
+
+namespace mpvl {
+using namespace mpvk;
+
+void vdisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_vdisparity, dim3(H), dim3(256), 0, s, disp, W, H, pitch, D, hist);
+}
+
+void road(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
+          hipStream_t s) {
+  hipLaunchKernelGGL(k_road, dim3(1), dim3(1024), 0, s, hist, D, H, eta, back, path, energy);
+}
+
+}  // namespace mpvl

@@ -64,6 +64,11 @@ void downsample(const uint8_t* in, int pitch, uint8_t* out, const uint8_t* in2, 
 void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int H,
           const int16_t* lo, const uint8_t* len, int cap, int D, uint8_t* cost, hipStream_t s);
 void census_pyr(const CenPyr& cp, hipStream_t s);
+// Road profile (kern_road.hip): v-disparity image [D][H] of a disparity map, and the
+// max-sum road path over it (one block; back = D*H bytes of back-pointers).
+void vdisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* hist, hipStream_t s);
+void road(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
+          hipStream_t s);
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s);
 void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 

@@ -1083,6 +1083,30 @@ mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_
   return launched();
 }
 
+// ---- road profile (Section 3.5) -----------------------------------------------------------
+static_assert(MPV_ROAD_MAX_HEIGHT == ROAD_MAX_HEIGHT, "road kernel LDS rows");
+mpv_status mpv_vdisparity(const int16_t* disp, int32_t W, int32_t H, int32_t pitch, int32_t D,
+                          uint32_t* hist, hipStream_t stream) {
+  if (!disp || !hist || W < 1 || H < 1 || pitch < W || D < 1 || D > MPV_MAX_DISP) return MPV_ERR_INVALID_ARG;
+  mpvl::vdisparity(disp, W, H, pitch, D, hist, stream);
+  return launched();
+}
+
+size_t mpv_road_workspace_bytes(int32_t D, int32_t H) {
+  if (D < 1 || D > MPV_MAX_DISP || H < 1 || H > MPV_ROAD_MAX_HEIGHT) return 0;
+  return align_up((size_t)D * H);
+}
+
+mpv_status mpv_road(const uint32_t* hist, int32_t D, int32_t H, int32_t eta, int16_t* path,
+                    int32_t* energy, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!hist || !path || !energy || D < 1 || D > MPV_MAX_DISP || H < 1 || H > MPV_ROAD_MAX_HEIGHT ||
+      eta < 2 || eta > 256)
+    return MPV_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < mpv_road_workspace_bytes(D, H)) return MPV_ERR_WORKSPACE;
+  mpvl::road(hist, D, H, eta, (uint8_t*)workspace, path, energy, stream);
+  return launched();
+}
+
 mpv_status mpv_set_timing_events(int32_t stage, int32_t level, hipEvent_t before, hipEvent_t after) {
   if (stage < 0 || stage >= MPV_NUM_STAGES || level < -1 || level >= MPV_MAX_LEVELS)
     return MPV_ERR_INVALID_ARG;

@@ -110,5 +110,6 @@ struct CenPyr {
 };
 
 constexpr int RED_MAXW = 4096;
+constexpr int ROAD_MAX_HEIGHT = 4096;  // rows of a v-disparity image the road kernel holds in LDS
 
 }  // namespace mpvk

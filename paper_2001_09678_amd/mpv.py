@@ -276,3 +276,34 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def vdisparity(disp: torch.Tensor, num_disp: int) -> torch.Tensor:
+    """v-disparity image of a disparity map (Section 3.5, eq. disp_map): [D][H] counts of
+    each row's disparities, as an int32 tensor holding the library's uint32 counts."""
+    d = _dev(disp, torch.int16, "disp")
+    if d.dim() != 2 or d.stride(1) != 1:
+        raise ValueError("disp must be a 2-D map with contiguous rows")
+    h, w = d.shape
+    hist = torch.empty((num_disp, h), dtype=torch.int32, device=d.device)
+    _L.check(_L.lib().mpv_vdisparity(d.data_ptr(), w, h, d.stride(0), num_disp, hist.data_ptr(), _stream()),
+             "mpv_vdisparity")
+    return hist
+
+
+def road(hist: torch.Tensor, eta: int = 8):
+    """Road profile over a v-disparity image (Section 3.5, eqs. P_hat and e): the row of the
+    road at every disparity (int16 [D], -1 if none) and the profile's sum of counts (int32 [1])."""
+    h = _dev(hist, torch.int32, "hist")
+    if h.dim() != 2 or not h.is_contiguous():
+        raise ValueError("hist must be a contiguous [D][H] tensor")
+    D, H = h.shape
+    need = int(_L.lib().mpv_road_workspace_bytes(D, H))
+    if need == 0:
+        raise _L.MPVError(_L.MPV_ERR_INVALID_ARG, "mpv_road_workspace_bytes")
+    ws = torch.empty(need, dtype=torch.uint8, device=h.device)
+    path = torch.empty(D, dtype=torch.int16, device=h.device)
+    energy = torch.empty(1, dtype=torch.int32, device=h.device)
+    _L.check(_L.lib().mpv_road(h.data_ptr(), D, H, eta, path.data_ptr(), energy.data_ptr(), ws.data_ptr(),
+                               need, _stream()), "mpv_road")
+    return path, energy

@@ -188,3 +188,17 @@ def test_gradient_weight_limits(L):
     handle = C.c_void_p()
     assert lib.mpv_batch_create(C.byref(pp), C.byref(item), 1, C.byref(handle)) == L.MPV_ERR_UNSUPPORTED
     assert lib.mpv_lb_coarse_workspace_bytes(C.byref(ok), 320, 180) == 0
+
+
+def test_road_limits(L):
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    assert lib.mpv_road_workspace_bytes(128, 720) >= 128 * 720
+    for D, H in [(0, 720), (257, 720), (128, 0), (128, L.MPV_ROAD_MAX_HEIGHT + 1)]:
+        assert lib.mpv_road_workspace_bytes(D, H) == 0
+        assert lib.mpv_road(fake, D, H, 8, fake, fake, fake, 1 << 30, None) == L.MPV_ERR_INVALID_ARG
+    for eta in (1, 0, 257):
+        assert lib.mpv_road(fake, 128, 720, eta, fake, fake, fake, 1 << 30, None) == L.MPV_ERR_INVALID_ARG
+    assert lib.mpv_road(fake, 128, 720, 8, fake, fake, fake, 16, None) == L.MPV_ERR_WORKSPACE
+    assert lib.mpv_vdisparity(fake, 32, 16, 31, 64, fake, None) == L.MPV_ERR_INVALID_ARG  # pitch < width
+    assert lib.mpv_vdisparity(fake, 32, 16, 32, 257, fake, None) == L.MPV_ERR_INVALID_ARG
