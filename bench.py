@@ -330,6 +330,42 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
     return out
 
 
+def road_bench(disp, num_disp, steps=50, eta=8):
+    """Road profile (Section 3.5) of the measured frame's disparity map through the C ABI
+    with caller buffers: the v-disparity image (one block per row; reads the int16 map,
+    writes D x H counts) and the road Viterbi (one workgroup), each as `steps` back-to-back
+    launches between two events (per-launch averages)."""
+    import torch
+    from paper_2001_09678_amd import _lib as L
+    from paper_2001_09678_amd import mpv
+    lib = L.lib()
+    H, W = disp.shape
+    hist = mpv.vdisparity(disp, num_disp)
+    path, energy = mpv.road(hist, eta)
+    ws = torch.empty(int(lib.mpv_road_workspace_bytes(num_disp, H)), dtype=torch.uint8, device=disp.device)
+    st = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    ev = _events(3)
+    ev[0].record()
+    for _ in range(steps):
+        L.check(lib.mpv_vdisparity(disp.data_ptr(), W, H, disp.stride(0), num_disp, hist.data_ptr(), st),
+                "mpv_vdisparity")
+    ev[1].record()
+    for _ in range(steps):
+        L.check(lib.mpv_road(hist.data_ptr(), num_disp, H, eta, path.data_ptr(), energy.data_ptr(),
+                             ws.data_ptr(), ws.numel(), st), "mpv_road")
+    ev[2].record()
+    torch.cuda.synchronize()
+    vd = ev[0].elapsed_time(ev[1]) / steps
+    rd = ev[1].elapsed_time(ev[2]) / steps
+    vbytes = 2 * W * H + 4 * num_disp * H
+    return {"vdisparity_ms": round(vd, 4), "road_ms": round(rd, 4), "eta": eta,
+            "vdisparity_roofline": {"bound": "hbm", "achieved": round(vbytes / (vd * 1e-3) / 1e9, 1),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(vbytes / (vd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "road_energy": int(energy.item()), "road_rows": [int(path[0].item()), int(path[-1].item())]}
+
+
 def serve_bench(seconds, per_rig=8, saturate=32):
     """Frame-stream service: 8 rigs at 30 fps (shapes and ranges drawn by seed 5), HBM-budget
     admission, continuous batching on 2 streams; latency is arrival to download complete,
@@ -477,6 +513,7 @@ def main():
         traffic = int(SCAN_TRAFFIC["fetch_bytes"] + SCAN_TRAFFIC["write_bytes"])
 
     breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
+    road_res = road_bench(pyr.disp, D)
     batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
     stream = {} if args.no_batch else stream_bench(params, levels, dev, sched, args.batch_steps * 2)
     learned_res = {} if args.no_learned else learned_bench(params, dev, args.plain_steps, args.learned_pairs)
@@ -532,6 +569,7 @@ def main():
         "learned": learned_res,
         "serve": serve_res,
         "layered": layered_res,
+        "road": road_res,
     }
     if traffic is not None:
         result["roofline"]["traffic_fetch"] = SCAN_TRAFFIC["fetch_bytes"]
