@@ -26,36 +26,74 @@ __global__ __launch_bounds__(256) void k_vdisparity(const int16_t* __restrict__ 
 // One block: disparity steps i = 1 .. D-1 in turn, each row j a node whose predecessors
 // are the rows j-eta+1 .. j-1 of step i-1 (energies ping-pong in LDS, -1 = unreachable).
 // back[i][j] keeps j minus the chosen predecessor (the smallest row among the maxima); the
-// end is the smallest row maximising the last step, traced back by one thread.
-__global__ __launch_bounds__(1024) void k_road(const uint32_t* __restrict__ hist, int D, int H, int eta,
-                                               uint8_t* __restrict__ back, int16_t* __restrict__ path,
-                                               int32_t* __restrict__ energy) {
+// end is the smallest row maximising the last step, traced back by one thread. The counts
+// of 16 steps are loaded together ahead of their use (so one load latency covers 16
+// dependent steps); LDS_BACK keeps the back-pointers in dynamic LDS (D*H bytes), else
+// they go to the caller's workspace.
+constexpr int ROAD_THREADS = 1024;
+constexpr int ROAD_RPT = ROAD_MAX_HEIGHT / ROAD_THREADS;  // rows per thread
+constexpr int ROAD_CHUNK = 16;
+
+template <bool LDS_BACK>
+__global__ __launch_bounds__(ROAD_THREADS) void k_road(const uint32_t* __restrict__ hist, int D, int H,
+                                                       int eta, uint8_t* __restrict__ gback,
+                                                       int16_t* __restrict__ path,
+                                                       int32_t* __restrict__ energy) {
   __shared__ int e[2][ROAD_MAX_HEIGHT];
-  __shared__ unsigned long long s_key[32];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int j = tid; j < H; j += nt) e[0][j] = (int)hist[j];
+  __shared__ unsigned long long s_key[ROAD_THREADS / 64];
+  extern __shared__ uint8_t lback[];
+  uint8_t* back = LDS_BACK ? lback : gback;
+  const int tid = threadIdx.x;
+  for (int j = tid; j < H; j += ROAD_THREADS) e[0][j] = (int)hist[j];
   __syncthreads();
-  for (int i = 1; i < D; ++i) {
-    const int* ep = e[(i - 1) & 1];
-    int* ec = e[i & 1];
-    for (int j = tid; j < H; j += nt) {
-      int best = -1, arg = j;
-      for (int jp = max(0, j - eta + 1); jp < j; ++jp) {
-        const int v = ep[jp];
-        if (v > best) {
-          best = v;
-          arg = jp;
-        }
+  for (int i0 = 1; i0 < D; i0 += ROAD_CHUNK) {
+    uint32_t hv[ROAD_CHUNK][ROAD_RPT];
+#pragma unroll
+    for (int s = 0; s < ROAD_CHUNK; ++s)
+#pragma unroll
+      for (int r = 0; r < ROAD_RPT; ++r) {
+        const int j = tid + r * ROAD_THREADS;
+        hv[s][r] = (i0 + s < D && j < H) ? hist[(size_t)(i0 + s) * H + j] : 0u;
       }
-      ec[j] = best >= 0 ? (int)hist[(size_t)i * H + j] + best : -1;
-      back[(size_t)i * H + j] = (uint8_t)(j - arg);
+#pragma unroll
+    for (int s = 0; s < ROAD_CHUNK; ++s) {
+      const int i = i0 + s;
+      if (i < D) {  // uniform over the block
+        const int* ep = e[(i - 1) & 1];
+        int* ec = e[i & 1];
+#pragma unroll
+        for (int r = 0; r < ROAD_RPT; ++r) {
+          const int j = tid + r * ROAD_THREADS;
+          if (j < H) {
+            // the window in groups of 8 independent LDS reads, compared in ascending row
+            // order (strictly greater: the smallest row wins ties)
+            int best = -1, arg = j;
+            for (int base = j - eta + 1; base < j; base += 8) {
+              int v[8];
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const int jp = base + k;
+                v[k] = (jp >= 0 && jp < j) ? ep[jp] : -1;
+              }
+#pragma unroll
+              for (int k = 0; k < 8; ++k)
+                if (v[k] > best) {
+                  best = v[k];
+                  arg = base + k;
+                }
+            }
+            ec[j] = best >= 0 ? (int)hv[s][r] + best : -1;
+            back[(size_t)i * H + j] = (uint8_t)(j - arg);
+          }
+        }
+        __syncthreads();
+      }
     }
-    __syncthreads();
   }
   // end of the profile: maximum energy, smallest row on ties (key = energy, then ~row)
   const int* el = e[(D - 1) & 1];
   unsigned long long key = 0;
-  for (int j = tid; j < H; j += nt)
+  for (int j = tid; j < H; j += ROAD_THREADS)
     if (el[j] >= 0) {
       const unsigned long long k = ((unsigned long long)(unsigned)el[j] << 32) | (0xFFFFFFFFu - (unsigned)j);
       key = k > key ? k : key;
@@ -67,7 +105,7 @@ __global__ __launch_bounds__(1024) void k_road(const uint32_t* __restrict__ hist
   if ((tid & 63) == 0) s_key[tid >> 6] = key;
   __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < (nt + 63) / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
+    for (int w = 1; w < ROAD_THREADS / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
     if (key == 0) {  // nothing reachable at the last disparity
       for (int i = 0; i < D; ++i) path[i] = -1;
       *energy = -1;
@@ -92,9 +130,21 @@ void vdisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* h
   hipLaunchKernelGGL(k_vdisparity, dim3(H), dim3(256), 0, s, disp, W, H, pitch, D, hist);
 }
 
+// Back-pointers in LDS up to this many bytes (beside the 32 KB of energies).
+constexpr size_t ROAD_LDS_BACK = 96 * 1024;
+
 void road(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
           hipStream_t s) {
-  hipLaunchKernelGGL(k_road, dim3(1), dim3(1024), 0, s, hist, D, H, eta, back, path, energy);
+  const size_t bytes = (size_t)D * H;
+  static const bool lds_ok =
+      hipFuncSetAttribute((const void*)k_road<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)ROAD_LDS_BACK) == hipSuccess;
+  if (lds_ok && bytes <= ROAD_LDS_BACK)
+    hipLaunchKernelGGL(k_road<true>, dim3(1), dim3(ROAD_THREADS), bytes, s, hist, D, H, eta, back, path,
+                       energy);
+  else
+    hipLaunchKernelGGL(k_road<false>, dim3(1), dim3(ROAD_THREADS), 0, s, hist, D, H, eta, back, path,
+                       energy);
 }
 
 }  // namespace mpvl
