@@ -302,8 +302,7 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
                                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                                      "algorithmic_bytes": scan_bytes, "launches": P // 2},
             "stage_ms": stage_breakdown(pyr, left, right, levels, reps=10),
-            # batches take no gradient weights (they have no per-level left images)
-            "stream16": stream_bench(params, levels, dev, sched, 20) if sigma == 0 else None,
+            "stream16": stream_bench(params, levels, dev, sched, 20),
             "plain": {"ms_per_step": round(pms, 4), "fps": round(1000.0 / pms, 1),
                       "scan_ms": round(pscan_avg, 4),
                       "scan_roofline": {"bound": "hbm", "achieved": round(pach, 1), "peak": HBM_PEAK_GBS,

@@ -112,7 +112,7 @@ typedef struct {
     int32_t grad_sigma;    /* 0: every transition weighs lambda. 1..255: the gradient-weighted
                               TV of eq. EU, the edge between consecutive path pixels p-r, p
                               weighs round(lambda * exp(-|I(p) - I(p-r)| / grad_sigma)) with I
-                              the left image of the level (fused entry points only) */
+                              the left image of the level (mpv_match, mpv_pyramid, batches) */
 } mpv_params;
 
 /* Human-readable status name; never NULL. */

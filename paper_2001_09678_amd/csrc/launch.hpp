@@ -48,6 +48,13 @@ void scan_band_grad(const ScanArgs& a, int src, int LPL, bool var, int wpb, hipS
 void scan_full_grad_occ(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
 void scan_full_grad_merge(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
 void scan_band_grad_merge(const ScanArgs& a, int LPL, bool var, int wpb, hipStream_t s);
+// Batched launches with gradient-weighted transitions (src includes SRC_GRAD).
+void scan_full_batch_grad(const Batch<ScanArgs>& b, int src, int units, int LPL, int K, int tau,
+                          bool banded, int wpb, hipStream_t s);
+void scan_full_batch_grad_layered(const Batch<ScanArgs>& b, int src, int units, int LPL, int K, int tau,
+                                  bool banded, int wpb, hipStream_t s);
+void scan_band_batch_grad(const Batch<ScanArgs>& b, int src, int units, int LPL, int tau, int wpb,
+                          hipStream_t s);
 
 // Sum + WTA (+ right disparity + LR when need_lr) over P uint8 partial volumes.
 void reduce_part(const RedArgs& a, int need_lr, hipStream_t s);

@@ -559,6 +559,10 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       sargs[i] = level_scan_args(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, lws[i],
                                  r ? r + pr.w.level_off : nullptr);
       if (!r) sargs[i].lo = nullptr;
+      if (b.p.base.grad_sigma > 0) {  // eq. EU weights from the level's left image
+        sargs[i].img = img_at(pr, l, 0, sargs[i].ipitch);
+        sargs[i].sigma = b.p.base.grad_sigma;
+      }
       PixArgs a{};
       a.W = pr.g.W[l];
       a.H = pr.g.H[l];
@@ -590,6 +594,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
     // layers in turn, each one launch per variant with its two directions of every pair
     const bool layered = b.p.base.merge != MPV_MERGE_SUM;
     const int nstage = layered ? b.p.base.num_paths / 2 : 1;
+    const int grad = b.p.base.grad_sigma > 0 ? SRC_GRAD : 0;
     for (int stage = 0; stage < nstage; ++stage)
     for (const Key& k : keys) {
       struct Item {
@@ -632,7 +637,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       ln.K = k.K;
       ln.tau = k.tau;
       ln.masked = k.masked;
-      ln.src = src;
+      ln.src = src | grad;
       b.launches.push_back(ln);
     }
     // reduce: pairs grouped by partial stride
@@ -906,8 +911,6 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
 mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* items, int32_t n,
                             mpv_batch* out) {
   if (!p || !items || n < 1 || !out) return MPV_ERR_INVALID_ARG;
-  if (p->base.grad_sigma != 0)
-    return check_params(&p->base, true) ? MPV_ERR_INVALID_ARG : MPV_ERR_UNSUPPORTED;
   mpv_batch_s* b = new (std::nothrow) mpv_batch_s();
   if (!b) return MPV_ERR_INVALID_ARG;
   b->p = *p;
@@ -992,7 +995,10 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
         break;
       }
       case mpv_batch_s::SCAN_FULL: {
-        if (ln.src == SRC_CENSUS)
+        if (src_grad(ln.src))
+          mpvl::scan_full_batch_grad({(const ScanArgs*)desc, first, ln.nseg}, ln.src, ln.units, ln.LPL,
+                                     ln.K, ln.tau, ln.masked, wpb, s);
+        else if (ln.src == SRC_CENSUS)
           mpvl::scan_full_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.K,
                                 ln.tau, ln.masked, wpb, s);
         else
@@ -1001,7 +1007,10 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
         break;
       }
       case mpv_batch_s::SCAN_BAND: {
-        if (ln.src == SRC_CENSUS)
+        if (src_grad(ln.src))
+          mpvl::scan_band_batch_grad({(const ScanArgs*)desc, first, ln.nseg}, ln.src, ln.units, ln.LPL,
+                                     ln.tau, wpb, s);
+        else if (ln.src == SRC_CENSUS)
           mpvl::scan_band_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.LPL, ln.tau, wpb,
                                 s);
         else

@@ -164,3 +164,31 @@ def test_grad_full_size(mpv, orc, merge):
         np.testing.assert_array_equal(_np(pyr.level_raw[l]), ref[l].dl, err_msg=f"level {l}")
     np.testing.assert_array_equal(_np(pyr.right), ref[-1].dr)
     np.testing.assert_array_equal(_np(pyr.disp), ref[-1].out)
+
+
+@pytest.mark.parametrize("merge", MERGES)
+def test_grad_batch(mpv, orc, merge):
+    """Eight pairs of their own sizes and ranges in one batch with gradient weights, eager
+    and graph-replayed twice: each output equals the oracle's pyramid of that pair."""
+    from paper_2001_09678_amd.scene import make_scene
+    rng = np.random.default_rng(8000 + len(merge))
+    levels, R, P = 3, 4, 8
+    host, pairs = [], []
+    for i in range(8):
+        w, h = int(rng.integers(32, 170)), int(rng.integers(16, 90))
+        D = int(rng.choice([16, 48, 64, 128, 256]))
+        sc = make_scene(8100 + i, w, h, D - 1, 5, ground=True)
+        host.append((sc.left, sc.right, D))
+        pairs.append((_cuda(sc.left), _cuda(sc.right), D))
+    _log("grad batch", merge, [(l.shape, D) for l, _, D in host])
+    b = mpv.Batch(pairs, mpv.MPVParams(num_disp=128, num_paths=P, merge=merge, grad_sigma=12), levels, R,
+                  want_all=True)
+    refs = [orc.pyramid(l, r, D, levels=levels, radius=R, num_paths=P, grad_sigma=12, **_orc(merge))[-1]
+            for l, r, D in host]
+    for run in ("run", "run_graph", "run_graph"):
+        getattr(b, run)()
+        for i, ref in enumerate(refs):
+            np.testing.assert_array_equal(_np(b.raw[i]), ref.dl, err_msg=f"{run} pair {i}")
+            np.testing.assert_array_equal(_np(b.right[i]), ref.dr, err_msg=f"{run} pair {i}")
+            np.testing.assert_array_equal(_np(b.disp[i]), ref.out, err_msg=f"{run} pair {i}")
+    b.close()
