@@ -36,3 +36,25 @@ def test_error_vs_ground_truth(w, h, d):
     assert e_plain < 0.15
     assert e_pyr < 0.15
     assert e_pyr < e_plain + 0.03
+
+
+@pytest.mark.parametrize("levels", [1, 3])
+def test_paper_merge_beats_the_sum(levels):
+    """The paper's layered merge with its occlusion strategy and the gradient-weighted TV
+    (Section 3.2, eq. EU) against the sum of the paths on seeded scenes with ground truth:
+    the measured gain (at full range about 6.7 % -> 3.8 % of bad pixels) must persist."""
+    import torch
+    from paper_2001_09678_amd import mpv
+    from paper_2001_09678_amd.scene import make_scene
+    print("paper merge quality, levels", levels, flush=True)
+    base = mpv.MPVParams(num_disp=128, num_paths=8)
+    paper = mpv.MPVParams(num_disp=128, num_paths=8, merge="layered_occ", grad_sigma=16)
+    e_sum, e_paper = [], []
+    for seed in (7101, 7102, 7103):
+        sc = make_scene(seed, 1280, 720, 127, 30, ground=True)
+        L, R = torch.from_numpy(sc.left).cuda(), torch.from_numpy(sc.right).cuda()
+        e_sum.append(_err(mpv.pyramid(L, R, base, levels=levels, radius=4).disp.cpu().numpy(), sc))
+        e_paper.append(_err(mpv.pyramid(L, R, paper, levels=levels, radius=4).disp.cpu().numpy(), sc))
+    s, p = float(np.mean(e_sum)), float(np.mean(e_paper))
+    print(f"error vs ground truth: sum {s:.4f}, paper merge {p:.4f}", flush=True)
+    assert p < s - 0.01
