@@ -326,6 +326,26 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
             q[f"{tag}.{name}"] = round(bad / tot, 5)
     out["err_gt"] = q
     out["err_gt_pairs"] = pairs
+    # the paper's search scope below the top level: a quarter of the full range (Section 3.4,
+    # eqs. Ot1/Ot2; radius D/8), with the sum and with the paper's merge and weights
+    R = base.num_disp // 8
+    scope = {"radius": R, "cap": 2 * R + 1}
+    caps = [-(-base.num_disp // (1 << (levels - 1)))] + [min(2 * R + 1, -(-base.num_disp // (1 << (levels - 1 - l))))
+                                                       for l in range(1, levels)]
+    scope["evaluated_nodes"] = sum((W >> (levels - 1 - l)) * (H >> (levels - 1 - l)) * c for l, c in enumerate(caps))
+    scope["fraction_of_full"] = round(scope["evaluated_nodes"] / (W * H * base.num_disp), 4)
+    for merge, sigma in (("sum", 0), ("layered_occ", GRAD_SIGMA)):
+        params = dataclasses.replace(base, merge=merge, grad_sigma=sigma)
+        tag = merge + (f"_grad{sigma}" if sigma else "")
+        pyr = mpv.Pyramid(params, W, H, levels=levels, radius=R, device=dev)
+        ms, _, _, _ = time_pipeline(pyr, left, right, steps, 10)
+        bad = tot = 0
+        for sc in scenes:
+            d = pyr(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev))
+            b, t = learned.gt_errors(d.cpu(), torch.from_numpy(sc.disp), torch.from_numpy(sc.occluded))
+            bad, tot = bad + b, tot + t
+        scope[tag] = {"ms_per_step": round(ms, 4), "fps": round(1000.0 / ms, 1), "err_gt": round(bad / tot, 5)}
+    out["paper_scope"] = scope
     return out
 
 

@@ -245,3 +245,20 @@ def test_repeatable_bits(mpv):
     a = _np(mpv.pyramid(_cuda(sc.left), _cuda(sc.right), p, levels=1).disp).copy()
     b = _np(mpv.pyramid(_cuda(sc.left), _cuda(sc.right), p, levels=1).disp)
     np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("merge,sigma", [("sum", 0), ("layered_occ", 16)])
+def test_paper_scope_full_size(mpv, orc, merge, sigma):
+    """The paper's search scope (a quarter of the full range at every level below the top,
+    Section 3.4 eqs. Ot1/Ot2: here radius D/8, 33 of 128 disparities) on the 1280x720
+    workload, every output pixel against the oracle."""
+    from paper_2001_09678_amd.scene import config_scene
+    sc, cfg = config_scene("c2")
+    _log("paper scope", merge, sigma)
+    p = mpv.MPVParams(num_disp=128, num_paths=8, merge=merge, grad_sigma=sigma)
+    pyr = mpv.pyramid(_cuda(sc.left), _cuda(sc.right), p, levels=3, radius=16, keep_levels=True)
+    kw = dict(merge="sum") if merge == "sum" else dict(merge="layered", occ=True)
+    ref = orc.pyramid(sc.left, sc.right, 128, levels=3, radius=16, num_paths=8, grad_sigma=sigma, **kw)
+    for l in range(3):
+        np.testing.assert_array_equal(_np(pyr.level_raw[l]), ref[l].dl, err_msg=f"level {l}")
+    np.testing.assert_array_equal(_np(pyr.disp), ref[-1].out)
