@@ -272,12 +272,18 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
     out = {}
     variants = {"layered": ("layered", 0), "layered_occ": ("layered_occ", 0),
                 "layered_occ_grad": ("layered_occ", GRAD_SIGMA)}
+    from paper_2001_09678_amd import autotune
     for name_v, (merge, sigma) in variants.items():
         params = dataclasses.replace(base, merge=merge, grad_sigma=sigma)
-        pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=sched)
+        # single frames take the autotuner's pick for each variant (bit-identical candidates);
+        # the 16 frames in flight keep the step's schedule (the single-frame pick favours small
+        # blocks, which batches do not)
+        vsched = autotune.tune_pyramid(left, right, params, levels, 4, use_cache=False)[0]
+        vpsched = autotune.tune_pyramid(left, right, params, 1, 4, use_cache=False)[0]
+        pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=vsched)
         ms, per, scan, _ = time_pipeline(pyr, left, right, steps, 10, hook_stage=L.STAGE_SCAN,
                                          hook_level=levels - 1)
-        plain = mpv.Pyramid(params, W, H, levels=1, radius=4, device=dev, sched=psched)
+        plain = mpv.Pyramid(params, W, H, levels=1, radius=4, device=dev, sched=vpsched)
         pms, _, pscan, _ = time_pipeline(plain, left, right, max(steps // 4, 10), 3,
                                          hook_stage=L.STAGE_SCAN, hook_level=0)
         scan_avg = sum(scan) / len(scan)
@@ -295,6 +301,7 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
         pach = pscan_bytes / (pscan_avg * 1e-3) / 1e9
         out[name_v] = {
             "merge": merge, "grad_sigma": sigma,
+            "schedule": {"multiscale": vsched.__dict__, "plain": vpsched.__dict__, "stream16": sched.__dict__},
             "ms_per_step": round(ms, 4), "fps": round(1000.0 / ms, 1),
             "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
             "finest_scan_ms": round(scan_avg, 4),

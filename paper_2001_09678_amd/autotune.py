@@ -74,7 +74,7 @@ def tune_pyramid(left, right, params: mpv.MPVParams, levels: int, radius: int, r
     """Fastest schedule for one pair shape; returns (schedule, {schedule: ms})."""
     h, w = left.shape
     key = f"{_arch()}|pyr|{w}x{h}|D{params.num_disp}|P{params.num_paths}|L{levels}|R{radius}|" \
-          f"lam{params.lam}|tau{params.tau}"
+          f"lam{params.lam}|tau{params.tau}|{params.merge}|g{params.grad_sigma}"
     cache = _load() if use_cache else {}
     if key in cache:
         return mpv.Schedule(**cache[key]["best"]), cache[key]["ms"]
@@ -102,7 +102,7 @@ def tune_batch(pairs, params: mpv.MPVParams, levels: int, radius: int, reps: int
     shapes = ",".join(f"{l.shape[1]}x{l.shape[0]}D{d}" for l, _, d in pairs)
     digest = hashlib.md5(shapes.encode()).hexdigest()[:12]
     key = f"{_arch()}|batch|{len(pairs)}|{digest}|P{params.num_paths}|L{levels}|" \
-          f"R{radius}|lam{params.lam}|tau{params.tau}{key_extra}"
+          f"R{radius}|lam{params.lam}|tau{params.tau}|{params.merge}|g{params.grad_sigma}{key_extra}"
     cache = _load() if use_cache else {}
     if key in cache:
         return mpv.Schedule(**cache[key]["best"]), cache[key]["ms"]
