@@ -73,8 +73,8 @@ void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int
                      W, H, lo, len, cap, D, out);
 }
 
-void census_pyr(const CenPyr& cp, hipStream_t s) {
-  hipLaunchKernelGGL(k_census_pyr, dim3(cp.first[cp.L], 2), dim3(256), 0, s, cp);
+void census_pyr(const CenPyr& cp, hipStream_t s, int nblocks) {
+  hipLaunchKernelGGL(k_census_pyr, dim3(nblocks < 0 ? cp.first[cp.L] : nblocks, 2), dim3(256), 0, s, cp);
 }
 
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s) {

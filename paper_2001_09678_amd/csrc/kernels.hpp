@@ -121,7 +121,6 @@ __device__ __forceinline__ uint32_t census_at(const uint8_t* img, int W, int H, 
   return v;
 }
 
-#ifdef MPV_MISC_KERNELS
 // Pixel (x, y) of the level S halvings below the input: the 2x2 rounded mean applied S
 // times (Section 3.4 pyramid), each step over the four pixels of the step below.
 template <int S>
@@ -137,21 +136,22 @@ __device__ __forceinline__ int pyr_pixel(const uint8_t* img, int pitch, int x, i
   }
 }
 
-// One block: a 64x4 tile of one level's census for one view (blockIdx.y). The tile's
-// pixels and a 2-pixel border (coordinates clamped to the level, as the census clamps its
-// neighbours) are built in LDS from the input, then each thread takes one census.
-__global__ __launch_bounds__(256) void k_census_pyr(CenPyr cp) {
+// Census tile `blk` (blocks of every level numbered from level 0, cp.first[]) of view v:
+// a 64x4 tile of one level's census. The tile's pixels and a 2-pixel border (coordinates
+// clamped to the level, as the census clamps its neighbours) are built in LDS from the
+// input, then the block's threads (any multiple of 64) take one census each.
+__device__ __forceinline__ void census_pyr_tile(const CenPyr& cp, int blk, int v) {
   __shared__ uint8_t t[8][68];
+  const int nt = blockDim.x;
   int l = 0;
-  while (l + 1 < cp.L && (int)blockIdx.x >= cp.first[l + 1]) ++l;
-  const int b = blockIdx.x - cp.first[l];
-  const int v = blockIdx.y;
+  while (l + 1 < cp.L && blk >= cp.first[l + 1]) ++l;
+  const int b = blk - cp.first[l];
   const int W = cp.W[l], H = cp.H[l];
   const int x0 = (b % cp.tiles_x[l]) * 64, y0 = (b / cp.tiles_x[l]) * 4;
   const int s = cp.L - 1 - l;
   const uint8_t* img = cp.img[v];
   const int pitch = cp.pitch[v];
-  for (int i = threadIdx.x; i < 8 * 68; i += 256) {
+  for (int i = threadIdx.x; i < 8 * 68; i += nt) {
     const int ty = i / 68, tx = i % 68;
     const int x = min(max(x0 + tx - 2, 0), W - 1), y = min(max(y0 + ty - 2, 0), H - 1);
     int p;
@@ -162,22 +162,30 @@ __global__ __launch_bounds__(256) void k_census_pyr(CenPyr cp) {
     t[ty][tx] = (uint8_t)p;
   }
   __syncthreads();
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int x = x0 + tx, y = y0 + ty;
-  if (x >= W || y >= H) return;
-  const int c = t[ty + 2][tx + 2];
-  uint32_t val = 0;
-  int bit = 0;
+  for (int o = threadIdx.x; o < 256; o += nt) {
+    const int tx = o & 63, ty = o >> 6;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= W || y >= H) continue;
+    const int c = t[ty + 2][tx + 2];
+    uint32_t val = 0;
+    int bit = 0;
 #pragma unroll
-  for (int dy = -2; dy <= 2; ++dy)
+    for (int dy = -2; dy <= 2; ++dy)
 #pragma unroll
-    for (int dx = -2; dx <= 2; ++dx) {
-      if (dx == 0 && dy == 0) continue;
-      val |= (uint32_t)(t[ty + 2 + dy][tx + 2 + dx] < c) << bit;
-      ++bit;
-    }
-  cp.out[l][v][(size_t)y * cp.opitch[l] + cp.omargin[l] + x] = val;
-  if (v == 0 && cp.limg[l]) cp.limg[l][(size_t)y * W + x] = (uint8_t)c;
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (dx == 0 && dy == 0) continue;
+        val |= (uint32_t)(t[ty + 2 + dy][tx + 2 + dx] < c) << bit;
+        ++bit;
+      }
+    cp.out[l][v][(size_t)y * cp.opitch[l] + cp.omargin[l] + x] = val;
+    if (v == 0 && cp.limg[l]) cp.limg[l][(size_t)y * W + x] = (uint8_t)c;
+  }
+}
+
+#ifdef MPV_MISC_KERNELS
+// Census of every pyramid level of both views in one launch (blockIdx.y = view).
+__global__ __launch_bounds__(256) void k_census_pyr(CenPyr cp) {
+  census_pyr_tile(cp, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(256) void k_cost(const uint8_t* __restrict__ L, int lpitch,
@@ -1153,6 +1161,22 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
 
 // Scan kernels: one descriptor (kernel argument) or a batch of descriptors (device table).
 // Blocks hold blockDim.x / 64 independent waves; waves past the work exit at once.
+// The top pyramid level's scan with the finer levels' census tiles as extra blocks: blocks
+// [0, nscan) run the scan's waves, blocks nscan + v*ncen + i the census tile cen0 + i of
+// view v. The top level's waves are too few to fill the chip, so the finer levels' census
+// runs beside them instead of before them.
+template <int LPL, int K, int TAU>
+__global__ __launch_bounds__(256) void k_scan_full_cen(ScanArgs a, CenPyr cp, int nscan, int cen0,
+                                                       int ncen) {
+  if ((int)blockIdx.x >= nscan) {
+    const int b = (int)blockIdx.x - nscan;
+    census_pyr_tile(cp, cen0 + b % ncen, b / ncen);
+    return;
+  }
+  const int u = wave_unit();
+  if (u < a.gprefix[a.ndir]) scan_full_wave<LPL, K, SRC_CENSUS, OUT_PART, TAU, false>(a, a, u);
+}
+
 template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>
 __global__ __launch_bounds__(256) void k_scan_full(ScanArgs a) {
   const int u = wave_unit();

@@ -308,7 +308,7 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
                      int16_t* right, int16_t* raw, uint8_t* ws, int level,
                      const mpv_schedule& sched, hipStream_t s, const NextBand* nb = nullptr,
                      uint32_t* const* cen = nullptr, const uint8_t* gimg = nullptr,
-                     int gpitch = 0) {
+                     int gpitch = 0, const CenPyr* fuse = nullptr, int cen0 = 0, int ncen = 0) {
   const LevelWs lw = level_ws(p, W, H, band, sched, cen == nullptr);
   ScanArgs a = level_scan_args(p, W, H, band, lw, ws);
   const int grad = p->grad_sigma > 0 ? SRC_GRAD : 0;
@@ -332,7 +332,10 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
       int dirs[8];
       for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
       plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
-      launch_scan(a, lw.sc, SRC_CENSUS | grad, OUT_PART, sched, s);
+      if (fuse && !grad && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
+        mpvl::scan_full_cen(a, *fuse, cen0, ncen, lw.sc.LPL, lw.sc.K, wpb_of(sched), s);
+      else
+        launch_scan(a, lw.sc, SRC_CENSUS | grad, OUT_PART, sched, s);
     } else {
       // Section 3.2 / Table alg: one dependent launch per layer
       for (int k = 0; k < nl; ++k) {
@@ -875,9 +878,12 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     cp.limg[l] = (p->base.grad_sigma > 0 && l + 1 < L) ? ws + w.gimg_off[l] : nullptr;
   }
   cp.first[L] = blocks;
+  // With the sum of the paths the top level's scan launch also builds the finer levels'
+  // census (its few waves leave the chip idle), so only the top level's census runs first.
+  const bool fuse = L > 1 && p->base.merge == MPV_MERGE_SUM && p->base.grad_sigma == 0;
   {
     HookScope hs(MPV_STAGE_CENSUS, HookScope::ALL_LEVELS, stream);
-    mpvl::census_pyr(cp, stream);
+    mpvl::census_pyr(cp, stream, fuse ? cp.first[1] : -1);
   }
   for (int l = 0; l < L; ++l) {
     int16_t* raw = out->level_raw[l] ? out->level_raw[l] : (int16_t*)(ws + w.raw_off[l]);
@@ -897,7 +903,8 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     st = run_level(&lpar, nullptr, 0, nullptr, 0, g.W[l], g.H[l], l > 0 ? &b : nullptr,
                    last ? out->disp : nullptr, last ? out->disp_right : nullptr, raw,
                    ws + w.level_off, l, p->sched, stream, last ? nullptr : &nb, cen[l],
-                   last ? left->data : cp.limg[l], last ? left->pitch : g.W[l]);
+                   last ? left->data : cp.limg[l], last ? left->pitch : g.W[l],
+                   fuse && l == 0 ? &cp : nullptr, cp.first[1], cp.first[L] - cp.first[1]);
     if (st) return st;
     if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
       if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),
