@@ -40,8 +40,8 @@ OPS_PER_NODE_PATH = 14
 SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp"]
-SCAN_TRAFFIC = {"sources_sha1": "556d79e9becc0a908588d12e542e0ec3a76f9600",
-                "fetch_bytes": 152968530, "write_bytes": 121679564}
+SCAN_TRAFFIC = {"sources_sha1": "b0283c6a1bcf9959bee9943f6c5f15b3850be238",
+                "fetch_bytes": 153094066, "write_bytes": 121679872}
 
 
 def scan_sources_sha1():
