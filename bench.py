@@ -452,10 +452,19 @@ def cpu_baseline(scene, cfg, budget_s=15.0, max_frames=60):
             break
     dt = time.perf_counter() - t0
     nominal = cfg["width"] * cfg["height"] * cfg["num_disp"]
+    # one frame on one thread beside the all-core rate
+    prev = oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.pyramid(scene.left, scene.right, cfg["num_disp"], levels=cfg["levels"], radius=4,
+                   num_paths=cfg["num_paths"])
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(prev)
     return {"value": round(nominal * frames / dt / 1e6, 2), "unit": "Mde/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{frames} frame(s) of the {cfg['width']}x{cfg['height']} D={cfg['num_disp']} "
-                      f"{cfg['levels']}-level workload, {dt:.1f} s wall, fast transition mode, OpenMP"}
+                      f"{cfg['levels']}-level workload, {dt:.1f} s wall, fast transition mode, OpenMP",
+            "single_thread": {"value": round(nominal / dt1 / 1e6, 2), "unit": "Mde/s",
+                              "sample": f"1 frame, {dt1:.1f} s wall"}}
 
 
 def main():

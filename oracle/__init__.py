@@ -71,6 +71,8 @@ def _load():
         lib.orc_layered_g.restype = i32
         lib.orc_grad_weight.argtypes = [i32, i32, i32]
         lib.orc_grad_weight.restype = i32
+        lib.orc_set_threads.argtypes = [i32]
+        lib.orc_set_threads.restype = i32
         lib.orc_wta_lr.argtypes = [P, i32, i32, i32, P, P, i32, i32, P, P, P]
         lib.orc_propagate.argtypes = [P, i32, i32, i32, i32, i32, i32, P]
         lib.orc_propagate.restype = i32
@@ -110,6 +112,11 @@ def cost(cl, cr, num_disp, lo=None, length=None, cap=None) -> np.ndarray:
     out = np.empty((h, w, cap), np.uint8)
     _load().orc_cost(_p(cl), _p(cr), w, h, _p(lo), _p(length), cap, _p(out))
     return out
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops; returns the previous maximum."""
+    return int(_load().orc_set_threads(n))
 
 
 def grad_weight(lam, sigma, g):

@@ -43,6 +43,9 @@
 #include <string.h>
 #include <limits.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_INF (INT64_MAX / 4)
 #define ORC_DEFINITION 0
@@ -130,6 +133,20 @@ void orc_cost(const uint32_t *cl, const uint32_t *cr, int W, int H,
                 cost[i * cap + j] = c;
             }
         }
+}
+
+/* Threads of the OpenMP loops (n >= 1); returns the previous maximum (1 without OpenMP). */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    int prev = omp_get_max_threads();
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return prev;
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* Gradient-weighted TV weight of eq. EU: round(lambda * exp(-g / sigma)) for an intensity
