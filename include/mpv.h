@@ -272,9 +272,8 @@ mpv_status mpv_road(const uint32_t *hist, int32_t num_disp, int32_t height, int3
 /* Measurement hook (per-kernel timing without a profiler). Stages of one level: */
 #define MPV_STAGE_DOWNSAMPLE 0 /* batches only: mpv_pyramid builds no coarse images */
 #define MPV_STAGE_CENSUS 1     /* mpv_pyramid: one launch, bracketed whatever level is hooked:
-                                  every level's census, or with the sum of the paths only the
-                                  top level's (the finer levels' census then runs inside the
-                                  top level's scan launch) */
+                                  the top level's census (with several levels the finer levels'
+                                  census runs inside the top level's first scan launch) */
 #define MPV_STAGE_SCAN 2      /* all P directions of one level, one launch */
 #define MPV_STAGE_REDUCE 3    /* sum + WTA + right disparity + LR of one level, and the band
                                  of the next finer level (Section 3.4 propagation) */

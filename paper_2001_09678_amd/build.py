@@ -29,7 +29,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 # strategy (about 2.5 % faster plain single-scale frames); the banded scans are fastest
 # with the default, and so is the unfused export, which is not on the fused path.
 def file_flags(name: str) -> list[str]:
-    if name.startswith("kern_full") and name != "kern_full_export.hip":
+    if name.startswith("kern_full") and name != "kern_full_export.hip":  # incl. kern_full_cen*
         return ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
     return []
 

@@ -1165,7 +1165,9 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
 // [0, nscan) run the scan's waves, blocks nscan + v*ncen + i the census tile cen0 + i of
 // view v. The top level's waves are too few to fill the chip, so the finer levels' census
 // runs beside them instead of before them.
-template <int LPL, int K, int TAU>
+// SRC: a census source (the sum of the paths or a layered merge's first layer, with or
+// without the occlusion weight and gradient weights).
+template <int LPL, int K, int SRC, int TAU>
 __global__ __launch_bounds__(256) void k_scan_full_cen(ScanArgs a, CenPyr cp, int nscan, int cen0,
                                                        int ncen) {
   if ((int)blockIdx.x >= nscan) {
@@ -1174,7 +1176,7 @@ __global__ __launch_bounds__(256) void k_scan_full_cen(ScanArgs a, CenPyr cp, in
     return;
   }
   const int u = wave_unit();
-  if (u < a.gprefix[a.ndir]) scan_full_wave<LPL, K, SRC_CENSUS, OUT_PART, TAU, false>(a, a, u);
+  if (u < a.gprefix[a.ndir]) scan_full_wave<LPL, K, SRC, OUT_PART, TAU, false>(a, a, u);
 }
 
 template <int LPL, int K, int SRC, int OUT, int TAU, bool BANDED>

@@ -72,10 +72,13 @@ void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int
           const int16_t* lo, const uint8_t* len, int cap, int D, uint8_t* cost, hipStream_t s);
 // Census tiles [0, nblocks) of every view (nblocks < 0: every level).
 void census_pyr(const CenPyr& cp, hipStream_t s, int nblocks = -1);
-// Top-level full-range scan (census source, partial output) with census tiles
-// [cen0, cen0 + ncen) of both views as extra blocks of the launch.
-void scan_full_cen(const ScanArgs& a, const CenPyr& cp, int cen0, int ncen, int LPL, int K, int wpb,
-                   hipStream_t s);
+// Top-level full-range scan (census source src: SRC_CENSUS or SRC_CENSUS_OCC, optionally
+// | SRC_GRAD; partial output) with census tiles [cen0, cen0 + ncen) of both views as extra
+// blocks of the launch.
+void scan_full_cen(const ScanArgs& a, int src, const CenPyr& cp, int cen0, int ncen, int LPL, int K,
+                   int wpb, hipStream_t s);
+void scan_full_cen_grad(const ScanArgs& a, int src, const CenPyr& cp, int cen0, int ncen, int LPL, int K,
+                        int wpb, hipStream_t s);
 // Road profile (kern_road.hip): v-disparity image [D][H] of a disparity map, and the
 // max-sum road path over it (one block; back = D*H bytes of back-pointers).
 void vdisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* hist, hipStream_t s);

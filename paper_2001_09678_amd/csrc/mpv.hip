@@ -332,8 +332,8 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
       int dirs[8];
       for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
       plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
-      if (fuse && !grad && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
-        mpvl::scan_full_cen(a, *fuse, cen0, ncen, lw.sc.LPL, lw.sc.K, wpb_of(sched), s);
+      if (fuse && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
+        mpvl::scan_full_cen(a, SRC_CENSUS | grad, *fuse, cen0, ncen, lw.sc.LPL, lw.sc.K, wpb_of(sched), s);
       else
         launch_scan(a, lw.sc, SRC_CENSUS | grad, OUT_PART, sched, s);
     } else {
@@ -343,7 +343,10 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
         const int src = layered_layer(p, b, k);
         const int pair[2] = {2 * k, 2 * k + 1};
         plan_dirs(b, pair, 2, lw.sc.LPL);
-        launch_scan(b, lw.sc, src | grad, OUT_PART, sched, s);
+        if (k == 0 && fuse && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside it
+          mpvl::scan_full_cen(b, src | grad, *fuse, cen0, ncen, lw.sc.LPL, lw.sc.K, wpb_of(sched), s);
+        else
+          launch_scan(b, lw.sc, src | grad, OUT_PART, sched, s);
       }
     }
   }
@@ -878,9 +881,9 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
     cp.limg[l] = (p->base.grad_sigma > 0 && l + 1 < L) ? ws + w.gimg_off[l] : nullptr;
   }
   cp.first[L] = blocks;
-  // With the sum of the paths the top level's scan launch also builds the finer levels'
-  // census (its few waves leave the chip idle), so only the top level's census runs first.
-  const bool fuse = L > 1 && p->base.merge == MPV_MERGE_SUM && p->base.grad_sigma == 0;
+  // The top level's (first) scan launch also builds the finer levels' census (its few waves
+  // leave the chip idle), so only the top level's census runs first.
+  const bool fuse = L > 1;
   {
     HookScope hs(MPV_STAGE_CENSUS, HookScope::ALL_LEVELS, stream);
     mpvl::census_pyr(cp, stream, fuse ? cp.first[1] : -1);
