@@ -40,8 +40,8 @@ OPS_PER_NODE_PATH = 14
 SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp"]
-SCAN_TRAFFIC = {"sources_sha1": "b0283c6a1bcf9959bee9943f6c5f15b3850be238",
-                "fetch_bytes": 153094066, "write_bytes": 121679872}
+SCAN_TRAFFIC = {"sources_sha1": "46f687c33044d60f30b5f5e0aa54d9e7b1bd7714",
+                "fetch_bytes": 153000477, "write_bytes": 121677004}
 
 
 def scan_sources_sha1():
