@@ -1,4 +1,5 @@
-"""CPU oracle of the road profile in v-disparity space — TEST INFRASTRUCTURE ONLY.
+"""CPU oracle of the road profile in v-disparity space and of the u-disparity image —
+TEST INFRASTRUCTURE ONLY.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg import this module;
 the product library never does. Plain numpy, integer throughout.
@@ -7,6 +8,9 @@ Section 3.5 of the paper:
 * eq. disp_map: H_x{U}(i, j) = the number of pixels of image row j whose disparity is i
   (the v-disparity image). Invalid disparities (-1) and values outside [0, D) are not
   counted.
+* eq. hy: H_y{U}(i, j) = the number of pixels of image column j whose disparity is i (the
+  u-disparity image); its second Kronecker delta is printed on the column index again and is
+  read as the disparity's, the column-wise counterpart of eq. disp_map.
 * eqs. P_hat and e: every (i, j) of H_x is a Viterbi node; a road profile is a path
   j = P(i) over all disparities i = 0 .. D-1 with e(0, j) = H_x(0, j) and
   e(i, j) = H_x(i, j) + max over 0 < j - j' < eta of e(i-1, j'), so the row grows by 1 to
@@ -61,3 +65,17 @@ def road(hist: np.ndarray, eta: int):
     for i in range(D - 1, 0, -1):
         path[i - 1] = back[i, path[i]]
     return path, int(e[D - 1, end])
+
+
+def udisparity(disp: np.ndarray, num_disp: int) -> np.ndarray:
+    """hist[i][j] (uint32 [D][W]): pixels of column j with disparity i (eq. hy, read with
+    its second Kronecker delta on the disparity, the column-wise counterpart of eq.
+    disp_map). Invalid (-1) and out-of-range disparities are not counted."""
+    disp = np.asarray(disp)
+    w = disp.shape[1]
+    hist = np.zeros((num_disp, w), np.uint32)
+    for j in range(w):
+        col = disp[:, j]
+        ok = (col >= 0) & (col < num_disp)
+        hist[:, j] = np.bincount(col[ok].astype(np.int64), minlength=num_disp)[:num_disp]
+    return hist

@@ -1,8 +1,11 @@
-"""Pins of the road-profile oracle (Section 3.5: the v-disparity image of eq. disp_map and
-the road Viterbi of eqs. P_hat and e) against facts that do not come from it.
+"""Pins of the road-profile oracle (Section 3.5: the v-disparity image of eq. disp_map, the
+u-disparity image of eq. hy and the road Viterbi of eqs. P_hat and e) against facts that
+do not come from it.
 
 * v-disparity: a hand-counted example and the invariants of a histogram (each row's
   counts add up to its valid pixels; invalid and out-of-range disparities are ignored);
+* u-disparity (eq. hy): a hand-counted example, each column's counts add up to its valid
+  pixels, and it equals the v-disparity image of the transposed map;
 * road Viterbi: enumeration of every admissible path (0 < row step < eta) on tiny
   histograms gives the same maximum energy, and the returned profile is admissible and
   reaches it; closed forms: a dominant straight line is recovered exactly, a ground plane
@@ -102,3 +105,22 @@ def test_road_follows_a_ground_plane(road):
 def test_road_unreachable(road):
     path, energy = road.road(np.ones((6, 4), np.uint32), eta=3)  # needs 5 row steps in 4 rows
     assert energy == -1 and (path == -1).all()
+
+
+def test_udisparity_hand_example_and_invariants(road):
+    disp = np.array([[0, 1, 1, -1],
+                     [2, 2, 1, 2],
+                     [5, 0, -1, 3]], np.int16)
+    h = road.udisparity(disp, 4)
+    assert h.shape == (4, 4) and h.dtype == np.uint32
+    np.testing.assert_array_equal(h[:, 0], [1, 0, 1, 0])  # 5 >= D is not counted
+    np.testing.assert_array_equal(h[:, 1], [1, 1, 1, 0])
+    np.testing.assert_array_equal(h[:, 2], [0, 2, 0, 0])
+    np.testing.assert_array_equal(h[:, 3], [0, 0, 1, 1])
+    rng = np.random.default_rng(63)
+    disp = rng.integers(-1, 40, (29, 47)).astype(np.int16)
+    h = road.udisparity(disp, 32)
+    valid = (disp >= 0) & (disp < 32)
+    np.testing.assert_array_equal(h.sum(axis=0), valid.sum(axis=0))
+    # the transpose of the map has the v-disparity image of this map's u-disparity
+    np.testing.assert_array_equal(h, road.vdisparity(disp.T.copy(), 32))
