@@ -359,7 +359,8 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
 def road_bench(disp, num_disp, steps=50, eta=8):
     """Road profile (Section 3.5) of the measured frame's disparity map through the C ABI
     with caller buffers: the v-disparity image (one block per row; reads the int16 map,
-    writes D x H counts) and the road Viterbi (one workgroup), each as `steps` back-to-back
+    writes D x H counts), the u-disparity image (one block per 16 columns; reads the map,
+    writes D x W counts) and the road Viterbi (one workgroup), each as `steps` back-to-back
     launches between two events (per-launch averages)."""
     import torch
     from paper_2001_09678_amd import _lib as L
@@ -367,11 +368,12 @@ def road_bench(disp, num_disp, steps=50, eta=8):
     lib = L.lib()
     H, W = disp.shape
     hist = mpv.vdisparity(disp, num_disp)
+    uhist = mpv.udisparity(disp, num_disp)
     path, energy = mpv.road(hist, eta)
     ws = torch.empty(int(lib.mpv_road_workspace_bytes(num_disp, H)), dtype=torch.uint8, device=disp.device)
     st = torch.cuda.current_stream().cuda_stream
     torch.cuda.synchronize()
-    ev = _events(3)
+    ev = _events(4)
     ev[0].record()
     for _ in range(steps):
         L.check(lib.mpv_vdisparity(disp.data_ptr(), W, H, disp.stride(0), num_disp, hist.data_ptr(), st),
@@ -381,14 +383,23 @@ def road_bench(disp, num_disp, steps=50, eta=8):
         L.check(lib.mpv_road(hist.data_ptr(), num_disp, H, eta, path.data_ptr(), energy.data_ptr(),
                              ws.data_ptr(), ws.numel(), st), "mpv_road")
     ev[2].record()
+    for _ in range(steps):
+        L.check(lib.mpv_udisparity(disp.data_ptr(), W, H, disp.stride(0), num_disp, uhist.data_ptr(), st),
+                "mpv_udisparity")
+    ev[3].record()
     torch.cuda.synchronize()
     vd = ev[0].elapsed_time(ev[1]) / steps
     rd = ev[1].elapsed_time(ev[2]) / steps
+    ud = ev[2].elapsed_time(ev[3]) / steps
     vbytes = 2 * W * H + 4 * num_disp * H
-    return {"vdisparity_ms": round(vd, 4), "road_ms": round(rd, 4), "eta": eta,
+    ubytes = 2 * W * H + 4 * num_disp * W
+    return {"vdisparity_ms": round(vd, 4), "udisparity_ms": round(ud, 4), "road_ms": round(rd, 4), "eta": eta,
             "vdisparity_roofline": {"bound": "hbm", "achieved": round(vbytes / (vd * 1e-3) / 1e9, 1),
                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(vbytes / (vd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "udisparity_roofline": {"bound": "hbm", "achieved": round(ubytes / (ud * 1e-3) / 1e9, 1),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(ubytes / (ud * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "road_energy": int(energy.item()), "road_rows": [int(path[0].item()), int(path[-1].item())]}
 
 

@@ -245,14 +245,20 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t stream);
 mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t stream);
 void mpv_batch_destroy(mpv_batch b);
 
-/* Road profile in v-disparity space (Section 3.5), downstream of the disparity map.
+/* Road profile in v-disparity space and the u-disparity image (Section 3.5), downstream of
+ * the disparity map.
  *
  * mpv_vdisparity: the v-disparity image of eq. disp_map, hist[i][j] = the number of pixels
  * of row j whose disparity is i, for 0 <= i < num_disp (1 .. MPV_MAX_DISP). disp: device
  * int16 [height][pitch] (pitch >= width, in elements); -1 and values outside [0, num_disp)
  * are not counted. hist: device uint32 [num_disp][height], every entry written.
  *
- * mpv_road: the road profile of eqs. P_hat and e over such a histogram: the path j = P(i)
+ * mpv_udisparity: the u-disparity image of eq. hy, its column-wise counterpart (read with
+ * the second Kronecker delta on the disparity: the printed one repeats the column index),
+ * hist[i][j] = the number of pixels of column j whose disparity is i. Same disp arguments
+ * and exclusions; hist: device uint32 [num_disp][width], every entry written.
+ *
+ * mpv_road: the road profile of eqs. P_hat and e over a v-disparity image: the path j = P(i)
  * over every disparity i = 0 .. num_disp-1 whose row grows by 1 to eta-1 per step (2 <=
  * eta <= 256) and whose sum of counts is largest; e(0,j) = hist[0][j],
  * e(i,j) = hist[i][j] + max over 0 < j-j' < eta of e(i-1,j'). The end is the smallest row
@@ -264,6 +270,8 @@ void mpv_batch_destroy(mpv_batch b);
  * kernel. */
 #define MPV_ROAD_MAX_HEIGHT 4096
 mpv_status mpv_vdisparity(const int16_t *disp, int32_t width, int32_t height, int32_t pitch,
+                          int32_t num_disp, uint32_t *hist, hipStream_t stream);
+mpv_status mpv_udisparity(const int16_t *disp, int32_t width, int32_t height, int32_t pitch,
                           int32_t num_disp, uint32_t *hist, hipStream_t stream);
 size_t mpv_road_workspace_bytes(int32_t num_disp, int32_t height);
 mpv_status mpv_road(const uint32_t *hist, int32_t num_disp, int32_t height, int32_t eta, int16_t *path,

@@ -85,6 +85,7 @@ def lib():
                            P, P, P, P, S, P], i32),
             "mpv_set_timing_events": ([i32, i32, P, P], i32),
             "mpv_vdisparity": ([P, i32, i32, i32, i32, P, P], i32),
+            "mpv_udisparity": ([P, i32, i32, i32, i32, P, P], i32),
             "mpv_road_workspace_bytes": ([i32, i32], S),
             "mpv_road": ([P, i32, i32, i32, P, P, P, S, P], i32),
             "mpv_batch_create": ([C.POINTER(PyramidParams), C.POINTER(BatchItem), i32, C.POINTER(P)], i32),

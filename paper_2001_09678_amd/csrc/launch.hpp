@@ -82,6 +82,7 @@ void scan_full_cen_grad(const ScanArgs& a, int src, const CenPyr& cp, int cen0, 
 // Road profile (kern_road.hip): v-disparity image [D][H] of a disparity map, and the
 // max-sum road path over it (one block; back = D*H bytes of back-pointers).
 void vdisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* hist, hipStream_t s);
+void udisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* hist, hipStream_t s);
 void road(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
           hipStream_t s);
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s);

@@ -1104,10 +1104,18 @@ mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_
 
 // ---- road profile (Section 3.5) -----------------------------------------------------------
 static_assert(MPV_ROAD_MAX_HEIGHT == ROAD_MAX_HEIGHT, "road kernel LDS rows");
+static_assert(MPV_MAX_DISP <= 256, "v- and u-disparity LDS histograms hold 256 disparities");
 mpv_status mpv_vdisparity(const int16_t* disp, int32_t W, int32_t H, int32_t pitch, int32_t D,
                           uint32_t* hist, hipStream_t stream) {
   if (!disp || !hist || W < 1 || H < 1 || pitch < W || D < 1 || D > MPV_MAX_DISP) return MPV_ERR_INVALID_ARG;
   mpvl::vdisparity(disp, W, H, pitch, D, hist, stream);
+  return launched();
+}
+
+mpv_status mpv_udisparity(const int16_t* disp, int32_t W, int32_t H, int32_t pitch, int32_t D,
+                          uint32_t* hist, hipStream_t stream) {
+  if (!disp || !hist || W < 1 || H < 1 || pitch < W || D < 1 || D > MPV_MAX_DISP) return MPV_ERR_INVALID_ARG;
+  mpvl::udisparity(disp, W, H, pitch, D, hist, stream);
   return launched();
 }
 

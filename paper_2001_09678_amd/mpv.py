@@ -291,6 +291,19 @@ def vdisparity(disp: torch.Tensor, num_disp: int) -> torch.Tensor:
     return hist
 
 
+def udisparity(disp: torch.Tensor, num_disp: int) -> torch.Tensor:
+    """u-disparity image of a disparity map (Section 3.5, eq. hy): [D][W] counts of each
+    column's disparities, as an int32 tensor holding the library's uint32 counts."""
+    d = _dev(disp, torch.int16, "disp")
+    if d.dim() != 2 or d.stride(1) != 1:
+        raise ValueError("disp must be a 2-D map with contiguous rows")
+    h, w = d.shape
+    hist = torch.empty((num_disp, w), dtype=torch.int32, device=d.device)
+    _L.check(_L.lib().mpv_udisparity(d.data_ptr(), w, h, d.stride(0), num_disp, hist.data_ptr(), _stream()),
+             "mpv_udisparity")
+    return hist
+
+
 def road(hist: torch.Tensor, eta: int = 8):
     """Road profile over a v-disparity image (Section 3.5, eqs. P_hat and e): the row of the
     road at every disparity (int16 [D], -1 if none) and the profile's sum of counts (int32 [1])."""

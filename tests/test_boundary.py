@@ -203,3 +203,6 @@ def test_road_limits(L):
     assert lib.mpv_road(fake, 128, 720, 8, fake, fake, fake, 16, None) == L.MPV_ERR_WORKSPACE
     assert lib.mpv_vdisparity(fake, 32, 16, 31, 64, fake, None) == L.MPV_ERR_INVALID_ARG  # pitch < width
     assert lib.mpv_vdisparity(fake, 32, 16, 32, 257, fake, None) == L.MPV_ERR_INVALID_ARG
+    assert lib.mpv_udisparity(fake, 32, 16, 31, 64, fake, None) == L.MPV_ERR_INVALID_ARG  # pitch < width
+    assert lib.mpv_udisparity(fake, 32, 16, 32, 257, fake, None) == L.MPV_ERR_INVALID_ARG
+    assert lib.mpv_udisparity(fake, 0, 16, 32, 64, fake, None) == L.MPV_ERR_INVALID_ARG
