@@ -58,60 +58,80 @@ __global__ __launch_bounds__(UDISP_THREADS) void k_udisparity(const int16_t* __r
 // are the rows j-eta+1 .. j-1 of step i-1 (energies ping-pong in LDS, -1 = unreachable).
 // back[i][j] keeps j minus the chosen predecessor (the smallest row among the maxima); the
 // end is the smallest row maximising the last step, traced back by one thread. The counts
-// of 16 steps are loaded together ahead of their use (so one load latency covers 16
+// of CHUNK steps are loaded together ahead of their use (so one load latency covers CHUNK
 // dependent steps); LDS_BACK keeps the back-pointers in dynamic LDS (D*H bytes), else
-// they go to the caller's workspace.
-constexpr int ROAD_THREADS = 1024;
-constexpr int ROAD_RPT = ROAD_MAX_HEIGHT / ROAD_THREADS;  // rows per thread
-constexpr int ROAD_CHUNK = 16;
+// they go to the caller's workspace. Each energy row has ROAD_PAD leading entries that stay
+// -1 (rows above the image: never a predecessor). NARROW (eta <= ROAD_PAD + 1): the window
+// lies within the ROAD_PAD entries before row j, read without range checks and masked at
+// its lower edge by a test uniform over the block; the step is bound by instruction issue
+// on the one CU, so this is what sets its speed. Otherwise the window is read in groups of
+// 8 with per-row range checks.
+constexpr int ROAD_PAD = 8;
 
-template <bool LDS_BACK>
-__global__ __launch_bounds__(ROAD_THREADS) void k_road(const uint32_t* __restrict__ hist, int D, int H,
-                                                       int eta, uint8_t* __restrict__ gback,
-                                                       int16_t* __restrict__ path,
-                                                       int32_t* __restrict__ energy) {
-  __shared__ int e[2][ROAD_MAX_HEIGHT];
-  __shared__ unsigned long long s_key[ROAD_THREADS / 64];
+template <bool LDS_BACK, bool NARROW, int THREADS, int RPT, int CHUNK>
+__global__ __launch_bounds__(THREADS) void k_road(const uint32_t* __restrict__ hist, int D, int H, int eta,
+                                                  uint8_t* __restrict__ gback, int16_t* __restrict__ path,
+                                                  int32_t* __restrict__ energy) {
+  __shared__ int e[2][ROAD_PAD + ROAD_MAX_HEIGHT];
+  __shared__ unsigned long long s_key[THREADS / 64];
   extern __shared__ uint8_t lback[];
   uint8_t* back = LDS_BACK ? lback : gback;
   const int tid = threadIdx.x;
-  for (int j = tid; j < H; j += ROAD_THREADS) e[0][j] = (int)hist[j];
+  if (tid < 2 * ROAD_PAD) e[tid / ROAD_PAD][tid % ROAD_PAD] = -1;
+  for (int j = tid; j < H; j += THREADS) e[0][ROAD_PAD + j] = (int)hist[j];
   __syncthreads();
-  for (int i0 = 1; i0 < D; i0 += ROAD_CHUNK) {
-    uint32_t hv[ROAD_CHUNK][ROAD_RPT];
+  for (int i0 = 1; i0 < D; i0 += CHUNK) {
+    uint32_t hv[CHUNK][RPT];
 #pragma unroll
-    for (int s = 0; s < ROAD_CHUNK; ++s)
+    for (int s = 0; s < CHUNK; ++s)
 #pragma unroll
-      for (int r = 0; r < ROAD_RPT; ++r) {
-        const int j = tid + r * ROAD_THREADS;
+      for (int r = 0; r < RPT; ++r) {
+        const int j = tid + r * THREADS;
         hv[s][r] = (i0 + s < D && j < H) ? hist[(size_t)(i0 + s) * H + j] : 0u;
       }
 #pragma unroll
-    for (int s = 0; s < ROAD_CHUNK; ++s) {
+    for (int s = 0; s < CHUNK; ++s) {
       const int i = i0 + s;
       if (i < D) {  // uniform over the block
-        const int* ep = e[(i - 1) & 1];
-        int* ec = e[i & 1];
+        const int* ep = e[(i - 1) & 1] + ROAD_PAD;
+        int* ec = e[i & 1] + ROAD_PAD;
 #pragma unroll
-        for (int r = 0; r < ROAD_RPT; ++r) {
-          const int j = tid + r * ROAD_THREADS;
+        for (int r = 0; r < RPT; ++r) {
+          const int j = tid + r * THREADS;
           if (j < H) {
-            // the window in groups of 8 independent LDS reads, compared in ascending row
-            // order (strictly greater: the smallest row wins ties)
             int best = -1, arg = j;
-            for (int base = j - eta + 1; base < j; base += 8) {
-              int v[8];
+            if (NARROW) {
+              // entries j-8 .. j-1 (the padding above row 0 reads -1); those below j-eta+1
+              // masked; maximum and first maximising entry in ascending row order (strictly
+              // greater: the smallest row wins ties; -1 entries never win)
+              int v[ROAD_PAD];
 #pragma unroll
-              for (int k = 0; k < 8; ++k) {
-                const int jp = base + k;
-                v[k] = (jp >= 0 && jp < j) ? ep[jp] : -1;
+              for (int k = 0; k < ROAD_PAD; ++k) v[k] = ep[j - ROAD_PAD + k];
+#pragma unroll
+              for (int k = 0; k < ROAD_PAD; ++k)
+                if (k < ROAD_PAD + 1 - eta) v[k] = -1;
+              int bk = ROAD_PAD;
+#pragma unroll
+              for (int k = 0; k < ROAD_PAD; ++k) {
+                bk = v[k] > best ? k : bk;
+                best = v[k] > best ? v[k] : best;
               }
+              arg = j - ROAD_PAD + bk;
+            } else {
+              for (int base = j - eta + 1; base < j; base += 8) {
+                int v[8];
 #pragma unroll
-              for (int k = 0; k < 8; ++k)
-                if (v[k] > best) {
-                  best = v[k];
-                  arg = base + k;
+                for (int k = 0; k < 8; ++k) {
+                  const int jp = base + k;
+                  v[k] = (jp >= 0 && jp < j) ? ep[jp] : -1;
                 }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                  if (v[k] > best) {
+                    best = v[k];
+                    arg = base + k;
+                  }
+              }
             }
             ec[j] = best >= 0 ? (int)hv[s][r] + best : -1;
             back[(size_t)i * H + j] = (uint8_t)(j - arg);
@@ -122,9 +142,9 @@ __global__ __launch_bounds__(ROAD_THREADS) void k_road(const uint32_t* __restric
     }
   }
   // end of the profile: maximum energy, smallest row on ties (key = energy, then ~row)
-  const int* el = e[(D - 1) & 1];
+  const int* el = e[(D - 1) & 1] + ROAD_PAD;
   unsigned long long key = 0;
-  for (int j = tid; j < H; j += ROAD_THREADS)
+  for (int j = tid; j < H; j += THREADS)
     if (el[j] >= 0) {
       const unsigned long long k = ((unsigned long long)(unsigned)el[j] << 32) | (0xFFFFFFFFu - (unsigned)j);
       key = k > key ? k : key;
@@ -136,7 +156,7 @@ __global__ __launch_bounds__(ROAD_THREADS) void k_road(const uint32_t* __restric
   if ((tid & 63) == 0) s_key[tid >> 6] = key;
   __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < ROAD_THREADS / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
+    for (int w = 1; w < THREADS / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
     if (key == 0) {  // nothing reachable at the last disparity
       for (int i = 0; i < D; ++i) path[i] = -1;
       *energy = -1;
@@ -177,18 +197,31 @@ void udisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* h
 // Back-pointers in LDS up to this many bytes (beside the 32 KB of energies).
 constexpr size_t ROAD_LDS_BACK = 96 * 1024;
 
-void road(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
-          hipStream_t s) {
+// One shape of the road workgroup: THREADS threads own RPT rows each (THREADS * RPT >= H)
+// and prefetch the counts of CHUNK steps (CHUNK * RPT registers).
+template <bool NARROW, int THREADS, int RPT, int CHUNK>
+void road_cfg(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
+              hipStream_t s) {
+  static_assert(THREADS * RPT <= ROAD_MAX_HEIGHT && THREADS % 64 == 0 && THREADS >= 2 * ROAD_PAD,
+                "road workgroup shape");
   const size_t bytes = (size_t)D * H;
   static const bool lds_ok =
-      hipFuncSetAttribute((const void*)k_road<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)ROAD_LDS_BACK) == hipSuccess;
+      hipFuncSetAttribute((const void*)k_road<true, NARROW, THREADS, RPT, CHUNK>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)ROAD_LDS_BACK) == hipSuccess;
   if (lds_ok && bytes <= ROAD_LDS_BACK)
-    hipLaunchKernelGGL(k_road<true>, dim3(1), dim3(ROAD_THREADS), bytes, s, hist, D, H, eta, back, path,
-                       energy);
+    hipLaunchKernelGGL((k_road<true, NARROW, THREADS, RPT, CHUNK>), dim3(1), dim3(THREADS), bytes, s, hist, D,
+                       H, eta, back, path, energy);
   else
-    hipLaunchKernelGGL(k_road<false>, dim3(1), dim3(ROAD_THREADS), 0, s, hist, D, H, eta, back, path,
-                       energy);
+    hipLaunchKernelGGL((k_road<false, NARROW, THREADS, RPT, CHUNK>), dim3(1), dim3(THREADS), 0, s, hist, D, H,
+                       eta, back, path, energy);
+}
+
+void road(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
+          hipStream_t s) {
+  if (eta <= ROAD_PAD + 1)
+    road_cfg<true, 1024, 4, 16>(hist, D, H, eta, back, path, energy, s);
+  else
+    road_cfg<false, 1024, 4, 16>(hist, D, H, eta, back, path, energy, s);
 }
 
 }  // namespace mpvl

@@ -2,7 +2,8 @@
 through the C ABI: v- and u-disparity images of random and matched disparity maps (ragged
 column tiles, pitched views, one disparity, the largest range), the road
 Viterbi on random, line and ground-plane histograms, the degenerate cases (one disparity,
-one row, eta = 2, eta beyond the height, unreachable ends) and the largest height."""
+one row, eta = 2, eta beyond the height, unreachable ends), windows on both sides of the
+narrow-window kernel (eta 9 and 10) and the largest height."""
 import numpy as np
 import pytest
 
@@ -72,7 +73,9 @@ def test_udisparity_pitched_view(mpv, road):
 
 
 @pytest.mark.parametrize("D,H,eta", [(1, 1, 2), (1, 50, 3), (5, 1, 4), (6, 4, 3), (16, 40, 2), (48, 200, 6),
-                                     (64, 200, 256), (128, 720, 8), (256, 4096, 3)])
+                                     (64, 200, 256), (128, 720, 8), (256, 4096, 3),
+                                     # both sides of the narrow-window kernel (eta <= 9)
+                                     (5, 12, 9), (40, 300, 9), (40, 300, 10), (3, 9, 10)])
 def test_road_random(mpv, road, D, H, eta):
     print("road", D, H, eta, flush=True)
     rng = np.random.default_rng(D * 7 + H + eta)
