@@ -3,7 +3,8 @@ through the C ABI: v- and u-disparity images of random and matched disparity map
 column tiles, pitched views, one disparity, the largest range), the road
 Viterbi on random, line and ground-plane histograms, the degenerate cases (one disparity,
 one row, eta = 2, eta beyond the height, unreachable ends), windows on both sides of the
-narrow-window kernel (eta 9 and 10) and the largest height."""
+narrow-window kernel (eta 9 and 10), heights at each change of rows per thread (1024,
+2048) and the largest height."""
 import numpy as np
 import pytest
 
@@ -75,7 +76,10 @@ def test_udisparity_pitched_view(mpv, road):
 @pytest.mark.parametrize("D,H,eta", [(1, 1, 2), (1, 50, 3), (5, 1, 4), (6, 4, 3), (16, 40, 2), (48, 200, 6),
                                      (64, 200, 256), (128, 720, 8), (256, 4096, 3),
                                      # both sides of the narrow-window kernel (eta <= 9)
-                                     (5, 12, 9), (40, 300, 9), (40, 300, 10), (3, 9, 10)])
+                                     (5, 12, 9), (40, 300, 9), (40, 300, 10), (3, 9, 10),
+                                     # one, two and four rows per thread, both windows
+                                     (20, 1024, 8), (20, 1025, 8), (64, 1080, 8), (32, 1500, 12),
+                                     (16, 2048, 5), (16, 2049, 9), (12, 3000, 20)])
 def test_road_random(mpv, road, D, H, eta):
     print("road", D, H, eta, flush=True)
     rng = np.random.default_rng(D * 7 + H + eta)
