@@ -2,8 +2,10 @@
 
 * brute force: every labeling of tiny lines is enumerated, the Viterbi energies must be
   the true prefix minima (Section 3.2, eqs. viterbi and e(p,u)) and forward + backward -
-  cost must be the true min-marginal of the whole line;
-* the paper's fast technique (Section 3.3) must equal the full predecessor minimum;
+  cost must be the true min-marginal of the whole line; the sum over the selected paths
+  (eq. viterbi) must be the sum of every selected direction's enumerated prefix minima;
+* the paper's fast technique (Section 3.3) must equal the full predecessor minimum, also
+  at the measured ranges D = 128 and 256;
 * special cases with a known answer (lambda = 0, width-1 bands, bands wider than the
   range, constant-disparity warps of i.i.d. noise);
 * census invariances and hand-worked census patterns (tests/golden);
@@ -273,3 +275,81 @@ def test_complexity_closed_form(orc):
     # the +/-4 band schedule of the 1280x720, D=128 workload evaluates 12,211,200 nodes
     caps = [32, 9, 9]
     assert sum(w * h * c for (w, h), c in zip(sizes, caps)) == 12_211_200
+
+
+def _bruteforce_paths(cost, lo, ln, cap, lam, tau):
+    """For every direction r, pixel and in-band label: the minimum energy over all labelings
+    of the line prefix that ends there (eq. e(p,u) by enumeration)."""
+    h, w = cost.shape[:2]
+    out = []
+    for r in range(8):
+        best = {}
+        for y in range(h):
+            for x in range(w):
+                pts = _prefix(x, y, DIRS[r], w, h)
+                bands = [_band(px, py, lo, ln, cap) for px, py in pts]
+                for labels in itertools.product(*bands):
+                    e = _energy(labels, pts, cost, lo, lam, tau)
+                    k = (x, y, labels[-1])
+                    best[k] = min(best.get(k, e), e)
+        out.append(best)
+    return out
+
+
+@pytest.mark.parametrize("banded", [False, True])
+def test_bruteforce_path_sum(orc, banded):
+    """The sum over the selected Viterbi paths (eq. viterbi): S(p,d) = sum of the
+    enumerated prefix minima of every selected direction, for P in {1, 2, 4, 8} and for
+    subsets chosen by a path mask; per-path exports equal the enumeration too. A sum that
+    drops, repeats or misselects a direction fails here."""
+    rng = np.random.default_rng(500 + banded)
+    masks = [0, 0b1, 0b10, 0b101, 0b1100, 0b10000000, 0b01010101, 0b11110000, 0b10010110, 0xFF]
+    for trial in range(5):
+        w, h = int(rng.integers(2, 5)), int(rng.integers(2, 5))
+        D = int(rng.integers(2, 5))
+        lam = int(rng.choice([1, 3, 8]))
+        tau = int(rng.choice([1, 2, 9]))
+        cost, lo, ln, cap = _random_case(rng, w, h, D, banded)
+        bf = _bruteforce_paths(cost, lo, ln, cap, lam, tau)
+        for P in (1, 2, 4, 8):
+            for mask in masks:
+                sel = [r for r in range(P) if not mask or (mask >> r) & 1]
+                S, pp = orc.aggregate(cost, D, P, lam, tau, lo, ln, path_mask=mask, per_path=True)
+                if not sel:  # the empty sum
+                    assert not S.any() and not pp.any()
+                    continue
+                for y in range(h):
+                    for x in range(w):
+                        b0 = 0 if lo is None else int(lo[y, x])
+                        band = _band(x, y, lo, ln, cap)
+                        for j in range(cap):
+                            d = b0 + j
+                            if d not in band:
+                                assert S[y, x, j] >= orc.INF
+                                continue
+                            assert S[y, x, j] == sum(bf[r][(x, y, d)] for r in sel), (trial, P, mask, x, y, d)
+                            for r in sel:
+                                assert pp[r, y, x, j] == bf[r][(x, y, d)]
+                # directions outside the selection contribute nothing and are not exported
+                for r in range(8):
+                    if r not in sel:
+                        assert not pp[r].any()
+
+
+@pytest.mark.parametrize("D", [128, 256])
+def test_fast_equals_definition_wide_range(orc, D):
+    """The two-sweep technique (Section 3.3) equals the full predecessor minimum at the
+    disparity ranges of the measured workloads (D = 128, 256), full range and banded,
+    truncated and untruncated."""
+    rng = np.random.default_rng(D)
+    for trial, tau in enumerate((4, 1, 37, D + 5)):
+        w, h = int(rng.integers(6, 12)), int(rng.integers(5, 10))
+        lam = int(rng.choice([1, 8, 13]))
+        cost, lo, ln, cap = _random_case(rng, w, h, D, trial % 2 == 1)
+        for r in range(8):
+            a = orc.path(cost, D, r, lam, tau, lo, ln, orc.DEFINITION)
+            b = orc.path(cost, D, r, lam, tau, lo, ln, orc.FAST)
+            np.testing.assert_array_equal(a, b)
+        S_def = orc.aggregate(cost, D, 8, lam, tau, lo, ln, mode=orc.DEFINITION)
+        S_fast = orc.aggregate(cost, D, 8, lam, tau, lo, ln, mode=orc.FAST)
+        np.testing.assert_array_equal(S_def, S_fast)
