@@ -6,7 +6,8 @@
   synchronisations in between, matches the eager run each time;
 * schedule invariance: every schedule an autotuner may pick gives identical bits;
 * the 64-pair workload (640x360 / 1280x720 / 1920x1080, D in {64, 128, 256}) at full size:
-  every pair equals its solo run, a sample equals the oracle.
+  every pair equals its solo run, and one pair of each of the 9 (size, range) combinations
+  equals the oracle.
 """
 import numpy as np
 import pytest
@@ -113,10 +114,10 @@ def test_schedule_invariance_full_size(mpv, levels, sched):
     np.testing.assert_array_equal(_np(got.raw), _np(ref.raw))
 
 
-def test_batch_workload_full_size(mpv, orc):
+@pytest.fixture(scope="module")
+def batch_workload(mpv):
     """The 64-pair workload at its full sizes in the launch configuration the benchmark
-    times (graph replay, longest lines first): each pair equals its solo run; three
-    pairs (one of each size) equal the oracle."""
+    times (graph replay, longest lines first); returns specs, scenes and every pair's map."""
     from paper_2001_09678_amd.scene import batch_specs, batch_scenes
     specs = batch_specs()
     _log("batch workload: generating", len(specs), "scenes")
@@ -126,14 +127,30 @@ def test_batch_workload_full_size(mpv, orc):
     _log("batch workload: run")
     b = mpv.Batch(pairs, params, levels=3, radius=4, sched=mpv.Schedule(waves_per_block=4, order=1))
     b.run_graph()
-    seen = set()
-    for i, (sc, sp) in enumerate(zip(scenes, specs)):
-        got = _np(b.disp[i])
+    got = [_np(t) for t in b.disp]
+    return specs, scenes, pairs, got
+
+
+def test_batch_workload_full_size(mpv, batch_workload):
+    """Every pair of the 64-pair batch equals its solo run."""
+    specs, scenes, pairs, got = batch_workload
+    for i, sp in enumerate(specs):
         solo = mpv.pyramid(pairs[i][0], pairs[i][1], mpv.MPVParams(num_disp=sp[3], num_paths=8),
                            levels=3, radius=4)
-        np.testing.assert_array_equal(got, _np(solo.disp), err_msg=f"pair {i} {sp}")
-        if sp[1] not in seen:
-            seen.add(sp[1])
-            _log("oracle for pair", i, sp)
-            ref = orc.pyramid(sc.left, sc.right, sp[3], levels=3, radius=4, num_paths=8)[-1]
-            np.testing.assert_array_equal(got, ref.out, err_msg=f"pair {i} vs oracle")
+        np.testing.assert_array_equal(got[i], _np(solo.disp), err_msg=f"pair {i} {sp}")
+
+
+BATCH_COMBOS = [(w, h, d) for (w, h) in [(640, 360), (1280, 720), (1920, 1080)] for d in (64, 128, 256)]
+
+
+@pytest.mark.parametrize("combo", BATCH_COMBOS, ids=[f"{w}x{h}_D{d}" for w, h, d in BATCH_COMBOS])
+def test_batch_workload_vs_oracle(orc, batch_workload, combo):
+    """The first pair of each (size, range) combination of the 64-pair batch equals the
+    oracle bit for bit (the batch's descriptors, per-pair ranges and workspace regions)."""
+    specs, scenes, _, got = batch_workload
+    idx = [i for i, sp in enumerate(specs) if (sp[1], sp[2], sp[3]) == combo]
+    assert idx, f"the workload draws no pair of {combo}"
+    i = idx[0]
+    _log("oracle for pair", i, specs[i])
+    ref = orc.pyramid(scenes[i].left, scenes[i].right, specs[i][3], levels=3, radius=4, num_paths=8)[-1]
+    np.testing.assert_array_equal(got[i], ref.out, err_msg=f"pair {i} {specs[i]} vs oracle")
