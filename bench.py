@@ -1,17 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the MPV stereo matcher on one MI355X.
 
-A step is one pass of the whole matcher over one synthetic 1280x720 stereo pair with
-disparity range D=128: image pyramid (3 levels), census, the 8-direction min-plus Viterbi
-scans of every level, path sums, winner-take-all, right disparity and LR check, and the
-+/-4 px band propagation between levels. Inputs are resident in HBM before timing starts.
+A step is one pass of the whole matcher over one batch of F synthetic 1280x720 stereo
+pairs with disparity range D=128 (F=16 by default, frame i from scene seed 2+i; frame 0
+is the workload's own pair): image pyramid (3 levels), census, the 8-direction min-plus
+Viterbi scans of every level, path sums, winner-take-all, right disparity and LR check,
+and the +/-4 px band propagation between levels, every stage one launch over all frames.
+Inputs are resident in HBM before timing starts.
 
-Prints one JSON line. ``value`` is nominal Mde/s (W*H*D disparity evaluations of the
-full-resolution problem per second). Beside it: fps, evaluated Mde/s (nodes actually
-searched), per-step p50/p99 latency, the same pair matched as plain single-scale MPV
-(full range at full resolution), the roofline of the dominant kernel (timed live with HIP
-events recorded around its launches on its own stream) and the CPU oracle timed on a
-bounded sample of the same workload on this host's cores.
+Prints one JSON line. ``value`` is nominal Mde/s (F*W*H*D disparity evaluations of the
+full-resolution problem per second of the step). Beside it: fps, evaluated Mde/s (nodes
+actually searched), per-step p50/p99, one frame alone (latency), the same pair as plain
+single-scale MPV (full range at full resolution), the 320x240 D=64 single-scale workload,
+the roofline of the dominant kernel (the finest level's scan over all frames, timed live
+with HIP events recorded around its launches on its own stream, against the algorithmic
+floor of 2 B per evaluated node plus 4 B per pixel) and the CPU oracle timed on a bounded
+sample of the same workload on this host's cores.
 """
 from __future__ import annotations
 
@@ -31,17 +35,21 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic integer operations per evaluated node and direction (cost, truncated-L1
 # envelope, transition minimum, normalisation, amortised line minimum)
 OPS_PER_NODE_PATH = 14
+# algorithmic HBM floor of the matcher: one partial-sum volume written and read once
+# (2 B per evaluated node) plus 2 B of images in and 2 B of int16 disparity out per pixel
+FLOOR_B_PER_NODE = 2
+FLOOR_B_PER_PIXEL = 4
 
-# HBM traffic of the dominant kernel (finest-level banded scan) per launch, from
-# `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of this script (see profiles/),
-# each calibrated by the same counter on a 1 GiB int32 negation kernel (1 GiB read, 1 GiB
-# written). Valid only for the kernel sources they were taken with (SHA-1 over the files
-# below); reported as null once those sources change.
+# HBM traffic of the dominant kernel (the finest level's banded scan over all frames of a
+# step, one batched launch) per launch, from `rocprofv3 --pmc FETCH_SIZE` and
+# `--pmc WRITE_SIZE` runs of this script (see profiles/), each calibrated by the same counter
+# on a 1 GiB int32 negation kernel (1 GiB read, 1 GiB written). Valid only for the kernel
+# sources and frame count they were taken with (SHA-1 over the files below); reported as
+# null otherwise.
 SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
-                "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band.hip",
+                "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band_batch.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp"]
-SCAN_TRAFFIC = {"sources_sha1": "46f687c33044d60f30b5f5e0aa54d9e7b1bd7714",
-                "fetch_bytes": 153000477, "write_bytes": 121677004}
+SCAN_TRAFFIC = {"sources_sha1": None, "frames": 16, "fetch_bytes": None, "write_bytes": None}
 
 
 def scan_sources_sha1():
@@ -478,11 +486,77 @@ def cpu_baseline(scene, cfg, budget_s=15.0, max_frames=60):
                               "sample": f"1 frame, {dt1:.1f} s wall"}}
 
 
+def cpu_model():
+    """Model name of this host's CPU (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def c1_oracle_timing(reps=3):
+    """The oracle on the 320x240, D=64, 4-path single-scale workload in both transition modes:
+    the full predecessor minimum (definition) and the two-sweep technique (fast)."""
+    import oracle
+    from paper_2001_09678_amd.scene import config_scene
+    sc, cfg = config_scene("c1")
+    nominal = cfg["width"] * cfg["height"] * cfg["num_disp"]
+    out = {}
+    for name, mode in (("definition", oracle.DEFINITION), ("fast", oracle.FAST)):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.pyramid(sc.left, sc.right, cfg["num_disp"], levels=1, num_paths=cfg["num_paths"], mode=mode)
+            ts.append(time.perf_counter() - t0)
+        t = sorted(ts)[len(ts) // 2]
+        out[name] = {"ms_per_frame": round(t * 1e3, 2), "value": round(nominal / t / 1e6, 2), "unit": "Mde/s"}
+    return out
+
+
+def c1_gpu_timing(dev, steps):
+    """The 320x240, D=64, 4-path single-scale workload on the GPU (one frame per call)."""
+    import torch
+    from paper_2001_09678_amd import mpv
+    from paper_2001_09678_amd.scene import config_scene
+    sc, cfg = config_scene("c1")
+    left = torch.from_numpy(sc.left).to(dev)
+    right = torch.from_numpy(sc.right).to(dev)
+    params = mpv.MPVParams(num_disp=cfg["num_disp"], num_paths=cfg["num_paths"], lam=8, tau=4, lr_max_diff=1)
+    pyr = mpv.Pyramid(params, cfg["width"], cfg["height"], levels=1, radius=4, device=dev)
+    ms, per, _, _ = time_pipeline(pyr, left, right, steps, 10)
+    nominal = cfg["width"] * cfg["height"] * cfg["num_disp"]
+    return {"workload": "plain MPV, 320x240, D=64, 4 paths, 1 level", "ms_per_frame": round(ms, 4),
+            "fps": round(1000.0 / ms, 1), "value": round(nominal / (ms * 1e-3) / 1e6, 1), "unit": "Mde/s",
+            "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4)}
+
+
+def roofline_floor(nodes, pixels, kernel_ms):
+    """HBM roofline against the algorithmic floor: FLOOR_B_PER_NODE per evaluated node plus
+    FLOOR_B_PER_PIXEL per pixel, over the kernel's average launch time."""
+    byts = FLOOR_B_PER_NODE * nodes + FLOOR_B_PER_PIXEL * pixels
+    ach = byts / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(byts)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=16, help="frames of the measured shape per step")
+    ap.add_argument("--single-steps", type=int, default=200)
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
@@ -491,8 +565,11 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-layered", action="store_true")
-    ap.add_argument("--sched", default=None, help="multi-scale schedule 'waves,full_lanes,band_lanes,order' "
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the step, one frame alone and plain MPV (profiling runs)")
+    ap.add_argument("--sched", default=None, help="step (batch) schedule 'waves,full_lanes,band_lanes,order' "
                                                   "(skips the autotuner)")
+    ap.add_argument("--single-sched", default=None, help="one-frame schedule (skips the autotuner)")
     ap.add_argument("--plain-sched", default=None, help="plain full-range schedule (skips the autotuner)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the measurements, run an int32 negation over this many MiB (counter calibration)")
@@ -504,43 +581,121 @@ def main():
               "frames are independent, so several GPUs would each run this same single-GPU path.",
               file=sys.stderr)
         sys.exit(2)
+    if args.no_extra:
+        args.no_batch = args.no_learned = args.no_serve = args.no_layered = args.no_breakdown = True
+        args.no_cpu_baseline = True
 
     import torch
     from paper_2001_09678_amd import _lib as L
     from paper_2001_09678_amd import autotune, mpv
-    from paper_2001_09678_amd.scene import config_scene
+    from paper_2001_09678_amd.scene import batch_scenes, config_scene, config_specs
 
-    L.lib()  # fails loudly without the HIP library
+    lib = L.lib()  # fails loudly without the HIP library
     dev = torch.device("cuda:0")
     scene, cfg = config_scene("c2")
     W, H, D, P, levels = cfg["width"], cfg["height"], cfg["num_disp"], cfg["num_paths"], cfg["levels"]
+    F = args.frames
     left = torch.from_numpy(scene.left).to(dev)
     right = torch.from_numpy(scene.right).to(dev)
     params = mpv.MPVParams(num_disp=D, num_paths=P, lam=8, tau=4, lr_max_diff=1)
+    print(f"bench: {F} frames of {W}x{H} D={D}, {levels} levels, {P} paths", file=sys.stderr, flush=True)
+
+    # ---- the step's frames (frame 0 is the workload's own pair), resident in HBM
+    specs = config_specs("c2", F)
+    scenes = batch_scenes(specs, workers=16)
+    pairs = [(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev), D) for sc in scenes]
 
     # ---- schedules picked by the autotuner (every candidate is checked bit-identical)
-    sched = parse_sched(args.sched) if args.sched else autotune.tune_pyramid(left, right, params, levels, 4,
-                                                                              use_cache=False)[0]
+    bsched = parse_sched(args.sched) if args.sched else autotune.tune_batch(pairs, params, levels, 4,
+                                                                           use_cache=False)[0]
+    sched = parse_sched(args.single_sched) if args.single_sched else autotune.tune_pyramid(
+        left, right, params, levels, 4, use_cache=False)[0]
     psched = parse_sched(args.plain_sched) if args.plain_sched else autotune.tune_pyramid(
         left, right, params, 1, 4, use_cache=False)[0]
 
-    # ---- multi-scale (the measured workload)
-    pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=sched)
-    ms, per_step, scan_ms, wall = time_pipeline(pyr, left, right, args.steps, args.warmup,
-                                                hook_stage=L.STAGE_SCAN, hook_level=levels - 1)
+    # ---- the step: one launch per stage over all F frames. The finest level's scan (the
+    # dominant kernel) is bracketed by HIP events on the launch stream in every timed step.
+    b = mpv.Batch(pairs, params, levels, 4, sched=bsched)
+    for _ in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    marks = _events(args.steps + 1)
+    kb, ka = _events(args.steps), _events(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        L.check(lib.mpv_set_timing_events(L.STAGE_SCAN, levels - 1, kb[i].cuda_event, ka[i].cuda_event),
+                "mpv_set_timing_events")
+        marks[i].record()
+        b.run()
+    marks[args.steps].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.mpv_set_timing_events(L.STAGE_SCAN, levels - 1, None, None)
+    per_step = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
+    ms = marks[0].elapsed_time(marks[args.steps]) / args.steps
+    scan_list = [kb[i].elapsed_time(ka[i]) for i in range(args.steps)]
+    scan_avg = sum(scan_list) / len(scan_list)
+    print(f"bench: step {ms:.4f} ms, finest scan {scan_avg:.4f} ms", file=sys.stderr, flush=True)
+    # the same step replayed as one captured graph
+    for _ in range(3):
+        b.run_graph()
+    torch.cuda.synchronize()
+    gev = _events(args.steps + 1)
+    for i in range(args.steps):
+        b.run_graph()
+        gev[i + 1].record()
+    torch.cuda.synchronize()
+    graph_ms = gev[0].elapsed_time(gev[args.steps]) / args.steps
+    disp0 = b.disp[0].clone()
+
     nominal = W * H * D
     caps = [min(9, -(-D // (1 << (levels - 1 - l)))) if l else -(-D // (1 << (levels - 1))) for l in range(levels)]
     sizes = [(W >> (levels - 1 - l), H >> (levels - 1 - l)) for l in range(levels)]
     evaluated = sum(w * h * c for (w, h), c in zip(sizes, caps))
-    fps = 1000.0 / ms
-    valid = (pyr.disp.cpu().numpy() >= 0).mean()
+    valid = (disp0.cpu().numpy() >= 0).mean()
 
-    # dominant kernel: the finest level's 8-direction scan. Algorithmic bytes per launch:
-    # one uint8 energy per evaluated node and direction written, plus both census images read.
+    # dominant kernel: the finest level's 8-direction banded scan of all frames (one launch).
     wf, hf = sizes[-1]
-    scan_bytes = P * wf * hf * caps[-1] + 2 * 4 * wf * hf
-    scan_avg = sum(scan_ms) / len(scan_ms)
-    achieved = scan_bytes / (scan_avg * 1e-3) / 1e9
+    fine_nodes = F * wf * hf * caps[-1]
+    roof = roofline_floor(fine_nodes, F * wf * hf, scan_avg)
+    sched_bytes = F * (P * wf * hf * caps[-1] + 2 * 4 * wf * hf)
+    scan_ops = OPS_PER_NODE_PATH * P * fine_nodes
+    traffic = None
+    if (SCAN_TRAFFIC["sources_sha1"] and SCAN_TRAFFIC["sources_sha1"] == scan_sources_sha1()
+            and SCAN_TRAFFIC["frames"] == F):
+        traffic = int(SCAN_TRAFFIC["fetch_bytes"] + SCAN_TRAFFIC["write_bytes"])
+    roof.update({"traffic": traffic, "kernel": "k_scan_band_batch<16,census,partial> (finest level, 8 directions, "
+                                                f"{F} frames per launch)",
+                 "kernel_ms": round(scan_avg, 4), "launches_timed": len(scan_list),
+                 "units": f"{fine_nodes} evaluated nodes x {FLOOR_B_PER_NODE} B + {F * wf * hf} px x "
+                          f"{FLOOR_B_PER_PIXEL} B",
+                 "schedule_model": {"bytes": sched_bytes,
+                                    "note": "one uint8 partial per evaluated node and direction written plus "
+                                            "both census images once",
+                                    "achieved": round(sched_bytes / (scan_avg * 1e-3) / 1e9, 1),
+                                    "frac": round(sched_bytes / (scan_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}})
+    if traffic is not None:
+        roof["traffic_fetch"] = SCAN_TRAFFIC["fetch_bytes"]
+        roof["traffic_write"] = SCAN_TRAFFIC["write_bytes"]
+    roof_alu = {"bound": "alu", "achieved": round(scan_ops / (scan_avg * 1e-3) / 1e12, 2),
+                "peak": round(ALU_PEAK_TOPS, 1), "unit": "Tops/s",
+                "frac": round(scan_ops / (scan_avg * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4),
+                "ops": f"{OPS_PER_NODE_PATH} integer ops per evaluated node and direction"}
+
+    # ---- one frame alone (latency): the same pair through mpv_pyramid
+    pyr = mpv.Pyramid(params, W, H, levels=levels, radius=4, device=dev, sched=sched)
+    sms, sper, sscan, _ = time_pipeline(pyr, left, right, args.single_steps, args.warmup,
+                                        hook_stage=L.STAGE_SCAN, hook_level=levels - 1)
+    sscan_avg = sum(sscan) / len(sscan)
+    same = bool(torch.equal(pyr.disp, disp0))
+    single = {"ms_per_frame": round(sms, 4), "fps": round(1000.0 / sms, 1),
+              "value": round(nominal / (sms * 1e-3) / 1e6, 1), "unit": "Mde/s",
+              "p50_ms": round(pct(sper, 50), 4), "p99_ms": round(pct(sper, 99), 4),
+              "finest_scan_ms": round(sscan_avg, 4),
+              "finest_scan_roofline": roofline_floor(wf * hf * caps[-1], wf * hf, sscan_avg),
+              "equals_frame0_of_step": same,
+              "note": "working set below the 256 MB MALL (cache-resident)"}
 
     # ---- plain single-scale MPV on the same pair (full range at full resolution)
     plain = mpv.Pyramid(params, W, H, levels=1, radius=4, device=dev, sched=psched)
@@ -553,15 +708,14 @@ def main():
     pred_avg = sum(pred) / len(pred)
     pred_bytes = P * W * H * 128 + 3 * 2 * W * H  # every partial read once; three int16 maps written
     agree = float((plain.disp == pyr.disp).float().mean().item())
-
-    traffic = None
-    if SCAN_TRAFFIC["sources_sha1"] and SCAN_TRAFFIC["sources_sha1"] == scan_sources_sha1():
-        traffic = int(SCAN_TRAFFIC["fetch_bytes"] + SCAN_TRAFFIC["write_bytes"])
+    # the S1 schedule (every direction writes a uint8 partial, one fused reduce reads them):
+    # 2P B per node for the whole plain frame
+    s1_bytes = 2 * P * W * H * D
 
     breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
-    road_res = road_bench(pyr.disp, D)
+    road_res = {} if args.no_extra else road_bench(pyr.disp, D)
+    c1_res = {} if args.no_extra else c1_gpu_timing(dev, args.plain_steps * 2)
     batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
-    stream = {} if args.no_batch else stream_bench(params, levels, dev, sched, args.batch_steps * 2)
     learned_res = {} if args.no_learned else learned_bench(params, dev, args.plain_steps, args.learned_pairs)
     serve_res = {} if args.no_serve else serve_bench(args.serve_seconds)
     layered_res = {} if args.no_layered else layered_bench(params, dev, left, right, levels, sched, psched,
@@ -569,7 +723,7 @@ def main():
 
     result = {
         "metric": METRIC,
-        "value": round(nominal / (ms * 1e-3) / 1e6, 1),
+        "value": round(F * nominal / (ms * 1e-3) / 1e6, 1),
         "unit": "Mde/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -578,20 +732,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16",
+        "dtype": "i32",
         "data": "synthetic",
-        "config": {"workload": "multi-scale MPV, 1280x720 uint8 pair, D=128, 3 levels (D 32/64/128), "
-                               "+/-4 px bands below the top, 8 paths, census 5x5, lambda=8, tau=4, LR 1 px",
-                   "width": W, "height": H, "num_disp": D, "levels": levels, "band_radius": 4,
-                   "num_paths": P, "scene_seed": cfg["seed"]},
-        "fps": round(fps, 1),
-        "mde_s_evaluated": round(evaluated / (ms * 1e-3) / 1e6, 1),
-        "evaluated_nodes": evaluated,
-        "latency_ms": {"p50": round(pct(per_step, 50), 4), "p99": round(pct(per_step, 99), 4)},
+        "config": {"workload": f"multi-scale MPV, {F} frames of a 1280x720 uint8 pair per step, D=128, 3 levels "
+                               "(D 32/64/128), +/-4 px bands below the top, 8 paths, census 5x5, lambda=8, tau=4, "
+                               "LR 1 px",
+                   "frames_per_step": F, "width": W, "height": H, "num_disp": D, "levels": levels,
+                   "band_radius": 4, "num_paths": P, "scene_seeds": [sp[0] for sp in specs]},
+        "fps": round(F * 1000.0 / ms, 1),
+        "mde_s_evaluated": round(F * evaluated / (ms * 1e-3) / 1e6, 1),
+        "evaluated_nodes_per_frame": evaluated,
+        "latency_ms": {"p50": round(pct(per_step, 50), 4), "p99": round(pct(per_step, 99), 4),
+                       "note": "per step of F frames; one frame alone under single_frame"},
+        "graph_ms_per_step": round(graph_ms, 4),
         "host_wall_ms_per_step": round(wall * 1e3 / args.steps, 4),
         "valid_fraction": round(float(valid), 4),
+        "roofline": roof,
+        "roofline_alu": roof_alu,
+        "single_frame": single,
         "plain": {"ms_per_step": round(pms, 4), "fps": round(1000.0 / pms, 1),
                   "value": round(nominal / (pms * 1e-3) / 1e6, 1), "unit": "Mde/s",
+                  "s1_schedule": {"bytes": s1_bytes, "achieved": round(s1_bytes / (pms * 1e-3) / 1e9, 1),
+                                  "frac": round(s1_bytes / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "note": "whole plain frame: 2P B per node (uint8 partials written by the "
+                                          "scan, read by the reduce)"},
                   "scan_ms": round(pscan_avg, 4),
                   "scan_roofline": {"bound": "hbm", "achieved": round(pscan_bytes / (pscan_avg * 1e-3) / 1e9, 1),
                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -604,22 +768,15 @@ def main():
                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                       "frac": round(pred_bytes / (pred_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                   "agreement_with_multiscale": round(agree, 4)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_scan_band<16,census,partial> (finest level, 8 directions)",
-                     "kernel_ms": round(scan_avg, 4), "algorithmic_bytes": scan_bytes},
+        "c1": c1_res,
         "stage_ms": breakdown,
-        "schedule": {"multiscale": sched.__dict__, "plain": psched.__dict__},
+        "schedule": {"step": bsched.__dict__, "single_frame": sched.__dict__, "plain": psched.__dict__},
         "batch": batch,
-        "stream": stream,
         "learned": learned_res,
         "serve": serve_res,
         "layered": layered_res,
         "road": road_res,
     }
-    if traffic is not None:
-        result["roofline"]["traffic_fetch"] = SCAN_TRAFFIC["fetch_bytes"]
-        result["roofline"]["traffic_write"] = SCAN_TRAFFIC["write_bytes"]
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib << 18  # int32 elements
         src = torch.ones(n, dtype=torch.int32, device=dev)
@@ -629,7 +786,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene, cfg)
+        cb = cpu_baseline(scene, cfg)
+        cb["cpu_model"] = cpu_model()
+        cb["c1_oracle"] = c1_oracle_timing()
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
 

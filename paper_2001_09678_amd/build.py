@@ -34,8 +34,23 @@ def file_flags(name: str) -> list[str]:
     return []
 
 
+def _obj(src: str) -> str:
+    return os.path.join(OBJ, os.path.basename(src) + ".o")
+
+
+def _stale(src: str) -> bool:
+    """The object is missing or older than its source or any shared header."""
+    obj = _obj(src)
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in [src, *HEADERS])
+
+
 def _compile(src: str) -> tuple[str, str]:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    obj = _obj(src)
+    if not _FORCE and not _stale(src):
+        return obj, ""
     extra = file_flags(os.path.basename(src))
     res = subprocess.run([HIPCC, *FLAGS, *extra, "-c", "-o", obj, src], capture_output=True, text=True)
     if res.returncode != 0:
@@ -43,10 +58,16 @@ def _compile(src: str) -> tuple[str, str]:
     return obj, res.stderr
 
 
+_FORCE = True
+
+
 def build(force: bool = True, verbose: bool = False, jobs: int | None = None) -> str:
+    """force: compile every translation unit; otherwise only those whose object is stale."""
+    global _FORCE
     deps = SOURCES + HEADERS
     if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in deps):
         return LIB
+    _FORCE = force
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(jobs) as ex:
@@ -67,4 +88,4 @@ def build(force: bool = True, verbose: bool = False, jobs: int | None = None) ->
 
 
 if __name__ == "__main__":
-    print(build(force=True, verbose="-v" in sys.argv))
+    print(build(force="--incremental" not in sys.argv, verbose="-v" in sys.argv))

@@ -170,6 +170,20 @@ def config_scene(name: str, seed: int | None = None) -> tuple[Scene, dict]:
     return scene, cfg
 
 
+def config_specs(name: str, n: int) -> list[tuple]:
+    """Specs (scene seed, width, height, D, planes) of n frames of a workload with a ground
+    ramp: frame i is config_scene(name, seed + i), so frame 0 is the workload's own pair."""
+    cfg = CONFIGS[name]
+    assert cfg["ground"], "frames of a spec list carry the ground ramp"
+    lo, hi = cfg["planes"]
+    out = []
+    for i in range(n):
+        s = cfg["seed"] + i
+        k = lo + int(np.random.Generator(np.random.PCG64(np.random.SeedSequence([s, 7]))).integers(0, hi - lo + 1))
+        out.append((s, cfg["width"], cfg["height"], cfg["num_disp"], k))
+    return out
+
+
 # Batched workload: 64 pairs, sizes and ranges drawn uniformly (seed 3), pair i from seed 3000+i.
 BATCH_SIZES = [(640, 360), (1280, 720), (1920, 1080)]
 BATCH_DISPS = [64, 128, 256]
