@@ -204,6 +204,22 @@ mpv_status mpv_pyramid(const mpv_pyramid_params *p, const mpv_image *left, const
                        const mpv_pyramid_out *out, void *workspace, size_t workspace_bytes,
                        hipStream_t stream);
 
+/* Allocation-free variant of mpv_pyramid, for callers that cannot allocate device memory
+ * (code under graph capture, serving loops and harnesses that forbid hipMalloc): the same
+ * computation and outputs as mpv_pyramid, with the workspace taken from a fixed device array
+ * of MPV_PYRAMID_NOALLOC_MAX_BYTES that the library owns, one copy per GPU, set up on the
+ * first call on that GPU and held until the process ends. The call allocates and frees
+ * nothing. MPV_ERR_WORKSPACE when mpv_pyramid_workspace_bytes for this shape exceeds the
+ * maximum (1280x720, D=128, 3 levels, 8 paths needs 129.3 MiB; 640x480 about 44 MiB);
+ * other arguments are checked as by mpv_pyramid; MPV_ERR_DEVICE when the current device or
+ * the array's address cannot be obtained. Every call on a GPU uses the same array and leaves
+ * its contents behind (nothing in it needs clearing between calls), so calls that overlap on
+ * one GPU (concurrent streams or threads) race: the caller serialises them. */
+#define MPV_PYRAMID_NOALLOC_MAX_BYTES ((size_t)144 << 20)
+mpv_status mpv_pyramid_noalloc(const mpv_pyramid_params *p, const mpv_image *left,
+                               const mpv_image *right, const mpv_pyramid_out *out,
+                               hipStream_t stream);
+
 /* One fused level with a caller-given band (the learned-band path: a network proposes
  * lo/len per pixel and the finest level searches only there). Same arithmetic and
  * outputs as one level of mpv_pyramid, with the same limits. band may be NULL (full range).

@@ -15,6 +15,7 @@ MPV_MAX_LEVELS = 4
 MPV_MAX_DISP = 256
 MPV_MAX_WIDTH = 4096
 MPV_ROAD_MAX_HEIGHT = 4096
+MPV_PYRAMID_NOALLOC_MAX_BYTES = 144 << 20
 STAGE_DOWNSAMPLE, STAGE_CENSUS, STAGE_SCAN, STAGE_REDUCE, STAGE_PROPAGATE = range(5)
 
 
@@ -80,6 +81,8 @@ def lib():
             "mpv_pyramid_workspace_bytes": ([C.POINTER(PyramidParams), i32, i32], S),
             "mpv_pyramid": ([C.POINTER(PyramidParams), C.POINTER(Image), C.POINTER(Image),
                              C.POINTER(PyramidOut), P, S, P], i32),
+            "mpv_pyramid_noalloc": ([C.POINTER(PyramidParams), C.POINTER(Image), C.POINTER(Image),
+                                     C.POINTER(PyramidOut), P], i32),
             "mpv_match_workspace_bytes": ([C.POINTER(Params), i32, i32, C.POINTER(Band)], S),
             "mpv_match": ([C.POINTER(Params), C.POINTER(Image), C.POINTER(Image), C.POINTER(Band),
                            P, P, P, P, S, P], i32),

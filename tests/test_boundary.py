@@ -206,3 +206,27 @@ def test_road_limits(L):
     assert lib.mpv_udisparity(fake, 32, 16, 31, 64, fake, None) == L.MPV_ERR_INVALID_ARG  # pitch < width
     assert lib.mpv_udisparity(fake, 32, 16, 32, 257, fake, None) == L.MPV_ERR_INVALID_ARG
     assert lib.mpv_udisparity(fake, 0, 16, 32, 64, fake, None) == L.MPV_ERR_INVALID_ARG
+
+
+def test_noalloc_limits_before_any_device_call(L):
+    """mpv_pyramid_noalloc checks its arguments and the size of its fixed array before it
+    touches a device: oversize shapes and bad parameters are rejected here, without a GPU."""
+    from paper_2001_09678_amd import mpv
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)  # never dereferenced
+    out = L.PyramidOut(fake, None, None, (C.c_void_p * L.MPV_MAX_LEVELS)())
+    big = mpv.pyramid_params(mpv.MPVParams(num_disp=256, num_paths=8), 3, 4)
+    img = L.Image(fake, 1920, 1080, 1920)
+    need = lib.mpv_pyramid_workspace_bytes(C.byref(big), 1920, 1080)
+    assert need > L.MPV_PYRAMID_NOALLOC_MAX_BYTES
+    assert lib.mpv_pyramid_noalloc(C.byref(big), C.byref(img), C.byref(img), C.byref(out), None) == \
+        L.MPV_ERR_WORKSPACE
+    # the measured 1280x720, D=128, 3-level frame fits the array
+    fits = mpv.pyramid_params(mpv.MPVParams(num_disp=128, num_paths=8), 3, 4)
+    assert 0 < lib.mpv_pyramid_workspace_bytes(C.byref(fits), 1280, 720) <= L.MPV_PYRAMID_NOALLOC_MAX_BYTES
+    bad = mpv.pyramid_params(mpv.MPVParams(num_disp=300, num_paths=8), 3, 4)
+    small = L.Image(fake, 64, 48, 64)
+    assert lib.mpv_pyramid_noalloc(C.byref(bad), C.byref(small), C.byref(small), C.byref(out), None) == \
+        L.MPV_ERR_INVALID_ARG
+    assert lib.mpv_pyramid_noalloc(None, C.byref(small), C.byref(small), C.byref(out), None) == \
+        L.MPV_ERR_INVALID_ARG
