@@ -76,6 +76,10 @@ def _load():
         lib.orc_wta_lr.argtypes = [P, i32, i32, i32, P, P, i32, i32, P, P, P]
         lib.orc_propagate.argtypes = [P, i32, i32, i32, i32, i32, i32, P]
         lib.orc_propagate.restype = i32
+        lib.orc_propagate_block.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, P]
+        lib.orc_propagate_block.restype = i32
+        lib.orc_propagate_interp.argtypes = [P, i32, i32, i32, i32, i32, i32, P]
+        lib.orc_propagate_interp.restype = i32
         _lib = lib
     return _lib
 
@@ -187,6 +191,33 @@ def propagate(dl_coarse, width, height, level_disp, radius):
     return lo, cap
 
 
+def propagate_block(dl_coarse, width, height, level_disp, radius, block):
+    """Section 3.4, intermediate layer: each block of block x block pixels searches around
+    twice the mode of its parents' raw disparities."""
+    dl_coarse = _c(dl_coarse, np.int16)
+    hc, wc = dl_coarse.shape
+    lo = np.empty((height, width), np.int16)
+    cap = _load().orc_propagate_block(_p(dl_coarse), wc, hc, width, height, level_disp, radius, block, _p(lo))
+    return lo, cap
+
+
+def propagate_interp(dl_coarse, width, height, level_disp, radius):
+    """Section 3.4, last layer: sampled pixels take twice the coarse raw disparity, the
+    others the linear interpolation of the samples around them."""
+    dl_coarse = _c(dl_coarse, np.int16)
+    hc, wc = dl_coarse.shape
+    lo = np.empty((height, width), np.int16)
+    cap = _load().orc_propagate_interp(_p(dl_coarse), wc, hc, width, height, level_disp, radius, _p(lo))
+    return lo, cap
+
+
+def level_block(levels: int, level: int, block: int) -> int:
+    """Block side of intermediate layer `level` (1 .. levels-2) of the paper's propagation:
+    `block` at layer 1, halved at every finer layer (never below 2); the last layer uses
+    single-pixel blocks with interpolation (Section 3.4)."""
+    return max(block >> (level - 1), 2)
+
+
 def level_disparities(num_disp: int, levels: int) -> list[int]:
     """D_l = ceil(D / 2^(L-1-l)): the top layer searches a quarter of the range for L=3
     (Section 3.4)."""
@@ -208,7 +239,7 @@ class LevelResult:
 
 def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4,
             lr_max_diff=1, mode=FAST, keep_sums=False, bands=None, merge="sum", occ=False,
-            grad_sigma=0):
+            grad_sigma=0, propagation="nearest", block=8):
     """Multi-scale MPV (Section 3.4). Level 0 is the coarsest and searches its full range;
     every finer level searches the band propagated from the level above. ``levels=1`` is
     plain single-scale MPV. ``bands`` optionally replaces the finest level's band by a
@@ -216,8 +247,12 @@ def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4
     ``num_paths`` directed paths; "layered" runs num_paths / 2 layers of the paper's
     hierarchical merge (``occ``: its occlusion strategy) and takes decisions on the last
     layer's merged energies. ``grad_sigma`` > 0 weights every transition by the left image's
-    gradient along the path (eq. EU), on each level's own left image."""
+    gradient along the path (eq. EU), on each level's own left image. ``propagation`` =
+    "nearest" centres every finer pixel's band on twice its parent's raw disparity;
+    "paper" is Section 3.4's scheme: block modes (``block`` pixels at layer 1, see
+    level_block) at intermediate layers and linear interpolation at the last layer."""
     assert merge in ("sum", "layered")
+    assert propagation in ("nearest", "paper")
     imgs = [_c(left, np.uint8)], [_c(right, np.uint8)]
     for _ in range(levels - 1):
         imgs[0].insert(0, downsample(imgs[0][0]))
@@ -233,7 +268,12 @@ def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4
             lo, cap = None, Dl
         else:
             prev = results[-1]
-            lo, cap = propagate(prev.dl, w, h, Dl, radius)
+            if propagation == "nearest":
+                lo, cap = propagate(prev.dl, w, h, Dl, radius)
+            elif l == levels - 1:
+                lo, cap = propagate_interp(prev.dl, w, h, Dl, radius)
+            else:
+                lo, cap = propagate_block(prev.dl, w, h, Dl, radius, level_block(levels, l, block))
         if bands is not None and l == levels - 1:
             lo, length, cap = bands
         cl, cr = census(L_img), census(R_img)

@@ -533,3 +533,65 @@ int orc_propagate(const int16_t *dl_coarse, int Wc, int Hc, int W, int H, int Dl
         }
     return cap;
 }
+
+/* The paper's own propagation (Section 3.4), intermediate layer. Only the pixels sampled
+ * from the coarser layer carry an initial value (twice the coarser raw WTA: the values are
+ * transformed by the sampling rate); the layer is split into blocks of block x block pixels
+ * and every pixel of a block searches around the block's mode of those initial values.
+ * The initial values of a block are those of the distinct parents of its pixels (pixel
+ * (x, y) has parent (min(x/2, Wc-1), min(y/2, Hc-1)), so border blocks past the coarse
+ * image still see their nearest parents); the mode is the most frequent value, the
+ * smallest one on ties. Band: cap = min(2R+1, Dl) disparities from
+ * lo = clamp(2*mode - R, 0, Dl - cap). Returns cap. */
+int orc_propagate_block(const int16_t *dl_coarse, int Wc, int Hc, int W, int H, int Dl, int R,
+                        int block, int16_t *lo)
+{
+    int cap = 2 * R + 1 < Dl ? 2 * R + 1 : Dl;
+    for (int by0 = 0; by0 < H; by0 += block)
+        for (int bx0 = 0; bx0 < W; bx0 += block) {
+            int bx1 = bx0 + block < W ? bx0 + block : W;
+            int by1 = by0 + block < H ? by0 + block : H;
+            int cx0 = clampi(bx0 / 2, 0, Wc - 1), cx1 = clampi((bx1 - 1) / 2, 0, Wc - 1);
+            int cy0 = clampi(by0 / 2, 0, Hc - 1), cy1 = clampi((by1 - 1) / 2, 0, Hc - 1);
+            int best_v = 0, best_n = 0;
+            for (int j = cy0; j <= cy1; ++j)
+                for (int i = cx0; i <= cx1; ++i) {
+                    int v = dl_coarse[j * Wc + i], n = 0;
+                    for (int jj = cy0; jj <= cy1; ++jj)
+                        for (int ii = cx0; ii <= cx1; ++ii)
+                            n += dl_coarse[jj * Wc + ii] == v;
+                    if (n > best_n || (n == best_n && v < best_v)) {
+                        best_n = n;
+                        best_v = v;
+                    }
+                }
+            int16_t l = (int16_t)clampi(2 * best_v - R, 0, Dl - cap);
+            for (int y = by0; y < by1; ++y)
+                for (int x = bx0; x < bx1; ++x)
+                    lo[(long)y * W + x] = l;
+        }
+    return cap;
+}
+
+/* The paper's own propagation (Section 3.4), last layer: every pixel is its own block.
+ * The sampled pixels (2i, 2j) take twice the coarser raw WTA of (i, j); the others are
+ * initialised by linear interpolation between the sampled pixels around them: midway
+ * between two samples the mean of their values, at the centre of four samples the mean
+ * of all four rounded half up (samples past the coarse image are clamped to its last
+ * row/column). Band as in orc_propagate_block. Returns cap. */
+int orc_propagate_interp(const int16_t *dl_coarse, int Wc, int Hc, int W, int H, int Dl, int R,
+                         int16_t *lo)
+{
+    int cap = 2 * R + 1 < Dl ? 2 * R + 1 : Dl;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int i0 = clampi(x / 2, 0, Wc - 1), i1 = clampi(x / 2 + (x & 1), 0, Wc - 1);
+            int j0 = clampi(y / 2, 0, Hc - 1), j1 = clampi(y / 2 + (y & 1), 0, Hc - 1);
+            /* values of the (up to) four samples, each twice the coarse disparity */
+            int s = 2 * dl_coarse[j0 * Wc + i0] + 2 * dl_coarse[j0 * Wc + i1] +
+                    2 * dl_coarse[j1 * Wc + i0] + 2 * dl_coarse[j1 * Wc + i1];
+            int c = (s + 2) >> 2;
+            lo[(long)y * W + x] = (int16_t)clampi(c - R, 0, Dl - cap);
+        }
+    return cap;
+}
