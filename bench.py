@@ -49,7 +49,8 @@ FLOOR_B_PER_PIXEL = 4
 SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band_batch.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp"]
-SCAN_TRAFFIC = {"sources_sha1": None, "frames": 16, "fetch_bytes": None, "write_bytes": None}
+SCAN_TRAFFIC = {"sources_sha1": "e9e28b15dfea887a70c2861c9a7d4e64b16166a0", "frames": 16,
+                "fetch_bytes": 3132743567, "write_bytes": 2003726400}
 
 
 def scan_sources_sha1():
