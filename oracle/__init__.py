@@ -80,6 +80,10 @@ def _load():
         lib.orc_propagate_block.restype = i32
         lib.orc_propagate_interp.argtypes = [P, i32, i32, i32, i32, i32, i32, P]
         lib.orc_propagate_interp.restype = i32
+        lib.orc_ssim_patch_cost.argtypes = [P, P]
+        lib.orc_ssim_patch_cost.restype = i32
+        lib.orc_ssim_ratio_parts.argtypes = [P, P, P, P, P, P]
+        lib.orc_ssim_cost.argtypes = [P, P, i32, i32, P, P, i32, P]
         _lib = lib
     return _lib
 
@@ -115,6 +119,34 @@ def cost(cl, cr, num_disp, lo=None, length=None, cap=None) -> np.ndarray:
     lo, length = _c(lo, np.int16), _c(length, np.uint8)
     out = np.empty((h, w, cap), np.uint8)
     _load().orc_cost(_p(cl), _p(cr), w, h, _p(lo), _p(length), cap, _p(out))
+    return out
+
+
+def ssim_patch_cost(psi, phi) -> int:
+    """Quantised SSIM cost (eq. ssim, 0 .. 24) of two 5x5 uint8 patches."""
+    psi, phi = _c(psi, np.uint8).reshape(25), _c(phi, np.uint8).reshape(25)
+    return int(_load().orc_ssim_patch_cost(_p(psi), _p(phi)))
+
+
+def ssim_ratio(psi, phi) -> tuple[int, int]:
+    """The SSIM index of two 5x5 patches as the exact ratio (num, den), den > 0."""
+    psi, phi = _c(psi, np.uint8).reshape(25), _c(phi, np.uint8).reshape(25)
+    parts = [np.zeros(1, np.int64), np.zeros(1, np.uint64), np.zeros(1, np.int64), np.zeros(1, np.uint64)]
+    _load().orc_ssim_ratio_parts(_p(psi), _p(phi), *[_p(a) for a in parts])
+    num = (int(parts[0][0]) << 64) | int(parts[1][0])
+    den = (int(parts[2][0]) << 64) | int(parts[3][0])
+    return num, den
+
+
+def ssim_cost(left, right, num_disp, lo=None, length=None, cap=None) -> np.ndarray:
+    """SSIM cost volume [H][W][cap] (slot j = disparity lo + j, 24 where x - d < 0, 0xFF
+    past a pixel's band): the SSIM data term of Section 3.2 in place of the census cost."""
+    left, right = _c(left, np.uint8), _c(right, np.uint8)
+    h, w = left.shape
+    cap = num_disp if cap is None else cap
+    lo, length = _c(lo, np.int16), _c(length, np.uint8)
+    out = np.empty((h, w, cap), np.uint8)
+    _load().orc_ssim_cost(_p(left), _p(right), w, h, _p(lo), _p(length), cap, _p(out))
     return out
 
 
@@ -239,7 +271,7 @@ class LevelResult:
 
 def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4,
             lr_max_diff=1, mode=FAST, keep_sums=False, bands=None, merge="sum", occ=False,
-            grad_sigma=0, propagation="nearest", block=8):
+            grad_sigma=0, propagation="nearest", block=8, data_term="census"):
     """Multi-scale MPV (Section 3.4). Level 0 is the coarsest and searches its full range;
     every finer level searches the band propagated from the level above. ``levels=1`` is
     plain single-scale MPV. ``bands`` optionally replaces the finest level's band by a
@@ -250,8 +282,11 @@ def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4
     gradient along the path (eq. EU), on each level's own left image. ``propagation`` =
     "nearest" centres every finer pixel's band on twice its parent's raw disparity;
     "paper" is Section 3.4's scheme: block modes (``block`` pixels at layer 1, see
-    level_block) at intermediate layers and linear interpolation at the last layer."""
+    level_block) at intermediate layers and linear interpolation at the last layer.
+    ``data_term`` = "census" (Hamming cost of 5x5 census signatures) or "ssim" (the SSIM cost
+    of Section 3.2 on each level's own images)."""
     assert merge in ("sum", "layered")
+    assert data_term in ("census", "ssim")
     assert propagation in ("nearest", "paper")
     imgs = [_c(left, np.uint8)], [_c(right, np.uint8)]
     for _ in range(levels - 1):
@@ -276,8 +311,10 @@ def pyramid(left, right, num_disp, levels=3, radius=4, num_paths=8, lam=8, tau=4
                 lo, cap = propagate_block(prev.dl, w, h, Dl, radius, level_block(levels, l, block))
         if bands is not None and l == levels - 1:
             lo, length, cap = bands
-        cl, cr = census(L_img), census(R_img)
-        cv = cost(cl, cr, Dl, lo, length, cap)
+        if data_term == "census":
+            cv = cost(census(L_img), census(R_img), Dl, lo, length, cap)
+        else:
+            cv = ssim_cost(L_img, R_img, Dl, lo, length, cap)
         g = L_img if grad_sigma > 0 else None
         if merge == "sum":
             S = aggregate(cv, Dl, num_paths, lam, tau, lo, length, mode=mode, img=g, sigma=grad_sigma)

@@ -595,3 +595,104 @@ int orc_propagate_interp(const int16_t *dl_coarse, int Wc, int Hc, int W, int H,
         }
     return cap;
 }
+
+/* SSIM data term (Section 3.2, eqs. components and ssim), following the structural
+ * similarity index of the work the paper cites for it, with that work's constants:
+ * K1 = 0.01, K2 = 0.03, L = 255 (8-bit pixels), C1 = (K1 L)^2, C2 = (K2 L)^2, C3 = C2/2 and
+ * alpha = beta = gamma = 1. psi and phi are N x N = 5 x 5 patches (uniform weights) of the
+ * left image around p and of the right image around p - (u, 0), coordinates clamped to the
+ * image. With the means, (population) variances and covariance of the patches,
+ *   l = (2 mu_psi mu_phi + C1) / (mu_psi^2 + mu_phi^2 + C1)
+ *   c = (2 sigma_psi sigma_phi + C2) / (sigma_psi^2 + sigma_phi^2 + C2)
+ *   s = (sigma_psiphi + C3) / (sigma_psi sigma_phi + C3)
+ * (the printed c has mu^2 mu^2 in its denominator and the printed s is inverted; these are
+ * the cited work's forms). Since C3 = C2/2, 2 sigma_psi sigma_phi + C2 = 2 (sigma_psi
+ * sigma_phi + C3), so c s = (2 sigma_psiphi + C2) / (sigma_psi^2 + sigma_phi^2 + C2) exactly
+ * and SSIM = l c s needs no square root. Every moment is a patch sum over n = 25 integer
+ * pixels, and C1 = 65025 / 10^4, C2 = 585225 / 10^4 are exact decimals, so scaling all four
+ * factors by n^2 10^4 makes SSIM an exact ratio of integers, num / den with den > 0.
+ * The cost (eq. ssim) is (1 - SSIM) L' / 2 with the data-term scale L' = 24, the range of the
+ * census cost, so the transition weights keep their meaning; it is rounded half up:
+ *   cost = floor((24 (den - num) + den) / (2 den)),  0 <= cost <= 24,
+ * in 128-bit integer arithmetic. A candidate with x - u < 0 costs 24. */
+#define SSIM_Q 24
+#define SSIM_SCALE 10000
+#define SSIM_C1S 65025  /* (0.01 * 255)^2 * 10^4 */
+#define SSIM_C2S 585225 /* (0.03 * 255)^2 * 10^4 */
+
+/* Exact SSIM of two 25-pixel patches: num / den. */
+void orc_ssim_ratio(const uint8_t *psi, const uint8_t *phi, __int128 *num, __int128 *den)
+{
+    const int64_t n = 25;
+    int64_t A = 0, B = 0, AA = 0, BB = 0, AB = 0;
+    for (int k = 0; k < 25; ++k) {
+        A += psi[k];
+        B += phi[k];
+        AA += (int64_t)psi[k] * psi[k];
+        BB += (int64_t)phi[k] * phi[k];
+        AB += (int64_t)psi[k] * phi[k];
+    }
+    /* n^2 10^4 (2 mu_psi mu_phi + C1), n^2 10^4 (2 sigma_psiphi + C2),
+       n^2 10^4 (mu_psi^2 + mu_phi^2 + C1), n^2 10^4 (sigma_psi^2 + sigma_phi^2 + C2) */
+    int64_t f1 = 2 * SSIM_SCALE * A * B + SSIM_C1S * n * n;
+    int64_t f2 = 2 * SSIM_SCALE * (n * AB - A * B) + SSIM_C2S * n * n;
+    int64_t g1 = SSIM_SCALE * (A * A + B * B) + SSIM_C1S * n * n;
+    int64_t g2 = SSIM_SCALE * (n * AA - A * A + n * BB - B * B) + SSIM_C2S * n * n;
+    *num = (__int128)f1 * f2;
+    *den = (__int128)g1 * g2;
+}
+
+/* SSIM as num / den in two 64-bit halves each (for callers without 128-bit integers). */
+void orc_ssim_ratio_parts(const uint8_t *psi, const uint8_t *phi, int64_t *num_hi, uint64_t *num_lo,
+                          int64_t *den_hi, uint64_t *den_lo)
+{
+    __int128 num, den;
+    orc_ssim_ratio(psi, phi, &num, &den);
+    *num_hi = (int64_t)(num >> 64);
+    *num_lo = (uint64_t)num;
+    *den_hi = (int64_t)(den >> 64);
+    *den_lo = (uint64_t)den;
+}
+
+/* Quantised SSIM cost of two patches (eq. ssim), 0 .. 24. */
+int orc_ssim_patch_cost(const uint8_t *psi, const uint8_t *phi)
+{
+    __int128 num, den;
+    orc_ssim_ratio(psi, phi, &num, &den);
+    return (int)((SSIM_Q * (den - num) + den) / (2 * den));
+}
+
+/* SSIM cost volume [H][W][cap] (slot j = disparity lo(p)+j; slots past the band 0xFF), the
+ * SSIM counterpart of orc_cost. */
+void orc_ssim_cost(const uint8_t *left, const uint8_t *right, int W, int H, const int16_t *lo,
+                   const uint8_t *len, int cap, uint8_t *cost)
+{
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            long i = (long)y * W + x;
+            int b0, bn;
+            band_of(lo, len, cap, i, &b0, &bn);
+            uint8_t psi[25], phi[25];
+            int k = 0;
+            for (int dy = -2; dy <= 2; ++dy)
+                for (int dx = -2; dx <= 2; ++dx)
+                    psi[k++] = left[clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+            for (int j = 0; j < cap; ++j) {
+                uint8_t c = 0xFF;
+                if (j < bn) {
+                    int d = b0 + j;
+                    if (x - d < 0) {
+                        c = SSIM_Q;
+                    } else {
+                        k = 0;
+                        for (int dy = -2; dy <= 2; ++dy)
+                            for (int dx = -2; dx <= 2; ++dx)
+                                phi[k++] = right[clampi(y + dy, 0, H - 1) * W + clampi(x - d + dx, 0, W - 1)];
+                        c = (uint8_t)orc_ssim_patch_cost(psi, phi);
+                    }
+                }
+                cost[i * cap + j] = c;
+            }
+        }
+}
