@@ -362,6 +362,22 @@ def layered_bench(base, dev, left, right, levels, sched, psched, steps, pairs=8)
             bad, tot = bad + b, tot + t
         scope[tag] = {"ms_per_step": round(ms, 4), "fps": round(1000.0 / ms, 1), "err_gt": round(bad / tot, 5)}
     out["paper_scope"] = scope
+    # the paper's own propagation (Section 3.4): block modes (8 px at the middle level) and
+    # linear interpolation at the last level, with the +/-4 band and with the d/4 scope
+    prop = {"block": 8}
+    for name, radius, merge, sigma in (("band4_sum", 4, "sum", 0), ("scope_sum", R, "sum", 0),
+                                       ("scope_layered_occ_grad16", R, "layered_occ", GRAD_SIGMA)):
+        params = dataclasses.replace(base, merge=merge, grad_sigma=sigma)
+        pyr = mpv.Pyramid(params, W, H, levels=levels, radius=radius, device=dev, propagation="paper", block=8)
+        ms, _, _, _ = time_pipeline(pyr, left, right, steps, 10)
+        bad = tot = 0
+        for sc in scenes:
+            d = pyr(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev))
+            b, t = learned.gt_errors(d.cpu(), torch.from_numpy(sc.disp), torch.from_numpy(sc.occluded))
+            bad, tot = bad + b, tot + t
+        prop[name] = {"radius": radius, "merge": merge, "grad_sigma": sigma, "ms_per_step": round(ms, 4),
+                      "fps": round(1000.0 / ms, 1), "err_gt": round(bad / tot, 5)}
+    out["paper_propagation"] = prop
     return out
 
 

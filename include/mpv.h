@@ -113,7 +113,24 @@ typedef struct {
                               TV of eq. EU, the edge between consecutive path pixels p-r, p
                               weighs round(lambda * exp(-|I(p) - I(p-r)| / grad_sigma)) with I
                               the left image of the level (mpv_match, mpv_pyramid, batches) */
+    int32_t data_term;     /* MPV_DATA_CENSUS (0) or MPV_DATA_SSIM: the matching cost C(p,d) */
 } mpv_params;
+
+/* Data term (mpv_params.data_term); both costs lie in 0 .. 24, so lambda and tau mean the same.
+ * MPV_DATA_CENSUS: Hamming distance of the 5x5 census signatures (mpv_census).
+ * MPV_DATA_SSIM: the structural-similarity cost of Section 3.2 (eqs. components and ssim) with
+ *   the constants of the similarity index the paper cites (K1 = 0.01, K2 = 0.03, dynamic range
+ *   255, C3 = C2/2, unit exponents). psi and phi are the 5x5 patches (uniform weights,
+ *   coordinates clamped to the image) of the left image around (x, y) and of the right image
+ *   around (x - d, y); with C3 = C2/2 the product of the three components is exactly
+ *   SSIM = (2 mu_psi mu_phi + C1)(2 cov + C2) / ((mu_psi^2 + mu_phi^2 + C1)(var_psi + var_phi + C2))
+ *   (population moments), evaluated exactly as a ratio of integers; the cost is
+ *   (1 - SSIM) * 24 / 2 rounded half up, and 24 where x - d < 0. mpv_cost writes it;
+ *   mpv_match and mpv_pyramid compute it once per level into the workspace and scan from it
+ *   (sum of the paths without gradient weights only: MPV_ERR_UNSUPPORTED otherwise); batches
+ *   and the learned coarse level take the census only. */
+#define MPV_DATA_CENSUS 0
+#define MPV_DATA_SSIM 1
 
 /* Human-readable status name; never NULL. */
 const char *mpv_status_string(mpv_status s);
@@ -129,8 +146,9 @@ mpv_status mpv_census(const mpv_image *img, uint32_t *census, hipStream_t stream
 mpv_status mpv_downsample(const mpv_image *img, uint8_t *out, hipStream_t stream);
 
 /* Matching-cost volume: cost[y][x][j] = popcount(cL(x,y) ^ cR(x-d,y)) for d = lo + j in the
- * band (24 when x-d < 0), 0xFF in slots past the pixel's band. This is the data term of
- * eq. e(p,u). Output: device uint8 [H][W][cap]. band may be NULL (full range). */
+ * band (24 when x-d < 0), or the SSIM cost of MPV_DATA_SSIM, 0xFF in slots past the pixel's
+ * band. This is the data term of eq. e(p,u). Output: device uint8 [H][W][cap]. band may be
+ * NULL (full range). */
 mpv_status mpv_cost(const mpv_params *p, const mpv_image *left, const mpv_image *right,
                     const mpv_band *band, uint8_t *cost, hipStream_t stream);
 
@@ -169,12 +187,28 @@ typedef struct {
     int32_t order;           /* batched scans: 0 = pair by pair, 1 = longest lines first */
 } mpv_schedule;
 
+/* How a finer pyramid level's search band is centred (mpv_pyramid_params.propagation).
+ * MPV_PROP_NEAREST: every pixel on twice its parent's raw winner.
+ * MPV_PROP_PAPER: the paper's own scheme (Section 3.4): only the pixels sampled from the
+ *   coarser level carry an initial value (twice the parent's raw winner); an intermediate
+ *   level is split into blocks and every pixel of a block is centred on the block's mode of
+ *   its parents' initial values (the most frequent, the smallest on ties); the last level
+ *   treats every pixel as a block and gives the pixels between samples the linear
+ *   interpolation of the samples around them (the mean of two, or of four rounded half up;
+ *   samples past the coarser image are clamped to its last row and column). */
+#define MPV_PROP_NEAREST 0
+#define MPV_PROP_PAPER 1
+#define MPV_MAX_BLOCK 32
+
 /* Multi-scale fused path (Section 3.4). */
 typedef struct {
     mpv_params base;     /* num_disp = D of the finest (input) level */
     int32_t levels;      /* 1 .. MPV_MAX_LEVELS; 1 = plain single-scale MPV */
-    int32_t band_radius; /* R: levels below the top search [c-R, c+R] around c = 2 x parent */
+    int32_t band_radius; /* R: levels below the top search [c-R, c+R] around their centre c */
     mpv_schedule sched;  /* launch schedule (zeros = defaults) */
+    int32_t propagation; /* MPV_PROP_NEAREST (0) or MPV_PROP_PAPER */
+    int32_t block;       /* MPV_PROP_PAPER: block side at level 1 (even, 2 .. MPV_MAX_BLOCK; 0 = 8),
+                            halved at every finer intermediate level, never below 2 */
 } mpv_pyramid_params;
 
 typedef struct {
@@ -190,7 +224,9 @@ size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params *p, int32_t width, i
 /* Level l of L has size floor(W / 2^(L-1-l)) x floor(H / 2^(L-1-l)) and range
  * D_l = ceil(D / 2^(L-1-l)). The top level (l = 0) searches its full range. Every finer
  * level searches the band of cap = min(2R+1, D_l) disparities starting at
- * lo = clamp(2 * raw_{l-1}(min(x/2, W_{l-1}-1), min(y/2, H_{l-1}-1)) - R, 0, D_l - cap).
+ * lo = clamp(c - R, 0, D_l - cap), with c = 2 * raw_{l-1}(min(x/2, W_{l-1}-1),
+ * min(y/2, H_{l-1}-1)) for MPV_PROP_NEAREST, the block mode or interpolated centre for
+ * MPV_PROP_PAPER. Batches (mpv_batch_*) take MPV_PROP_NEAREST only.
  * Each level runs cost -> all P paths -> sum -> WTA -> LR exactly as the unfused calls
  * do, so the outputs equal mpv_cost + mpv_aggregate + mpv_disparity per level; with a
  * layered merge each level runs the layers in turn and decides on the last layer's merge.
@@ -299,10 +335,11 @@ mpv_status mpv_road(const uint32_t *hist, int32_t num_disp, int32_t height, int3
                                   the top level's census (with several levels the finer levels'
                                   census runs inside the top level's first scan launch) */
 #define MPV_STAGE_SCAN 2      /* all P directions of one level, one launch */
-#define MPV_STAGE_REDUCE 3    /* sum + WTA + right disparity + LR of one level, and the band
-                                 of the next finer level (Section 3.4 propagation) */
-#define MPV_STAGE_PROPAGATE 4 /* no launches of its own: the band propagation runs inside the
-                                 coarser level's reduce */
+#define MPV_STAGE_REDUCE 3    /* sum + WTA + right disparity + LR of one level, and (nearest
+                                 propagation) the band of the next finer level (Section 3.4) */
+#define MPV_STAGE_PROPAGATE 4 /* MPV_PROP_PAPER: the launch that writes the next finer level's
+                                 band from this level's raw winners (nearest propagation runs
+                                 inside the coarser level's reduce and has none) */
 #define MPV_NUM_STAGES 5
 
 /* While set, every later run of `stage` at pyramid level `level` (0 = coarsest; the

@@ -11,6 +11,9 @@ LIB_PATH = os.path.join(HERE, "libmpv.so")
 MPV_OK, MPV_ERR_INVALID_ARG, MPV_ERR_UNSUPPORTED, MPV_ERR_WORKSPACE, MPV_ERR_OVERFLOW, MPV_ERR_DEVICE = range(6)
 MPV_AGG_U16, MPV_AGG_I32 = 0, 1
 MPV_MERGE_SUM, MPV_MERGE_LAYERED, MPV_MERGE_LAYERED_OCC = 0, 1, 2
+MPV_PROP_NEAREST, MPV_PROP_PAPER = 0, 1
+MPV_DATA_CENSUS, MPV_DATA_SSIM = 0, 1
+MPV_MAX_BLOCK = 32
 MPV_MAX_LEVELS = 4
 MPV_MAX_DISP = 256
 MPV_MAX_WIDTH = 4096
@@ -30,7 +33,8 @@ class Band(C.Structure):
 class Params(C.Structure):
     _fields_ = [("num_disp", C.c_int32), ("census_radius", C.c_int32), ("num_paths", C.c_int32),
                 ("lambda_", C.c_int32), ("tau", C.c_int32), ("lr_max_diff", C.c_int32),
-                ("agg_type", C.c_int32), ("merge", C.c_int32), ("grad_sigma", C.c_int32)]
+                ("agg_type", C.c_int32), ("merge", C.c_int32), ("grad_sigma", C.c_int32),
+                ("data_term", C.c_int32)]
 
 
 class Schedule(C.Structure):
@@ -40,7 +44,7 @@ class Schedule(C.Structure):
 
 class PyramidParams(C.Structure):
     _fields_ = [("base", Params), ("levels", C.c_int32), ("band_radius", C.c_int32),
-                ("sched", Schedule)]
+                ("sched", Schedule), ("propagation", C.c_int32), ("block", C.c_int32)]
 
 
 class BatchItem(C.Structure):

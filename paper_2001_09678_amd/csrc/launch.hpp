@@ -9,6 +9,7 @@ namespace mpvl {
 using mpvk::Batch;
 using mpvk::CenPyr;
 using mpvk::PixArgs;
+using mpvk::PropArgs;
 using mpvk::RedArgs;
 using mpvk::ScanArgs;
 
@@ -24,6 +25,9 @@ void scan_full_batch(const Batch<ScanArgs>& b, int units, int LPL, int K, int ta
                      int wpb, hipStream_t s);
 void scan_band(const ScanArgs& a, int LPL, int src, int out, bool var, int wpb, hipStream_t s);
 void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, int wpb, hipStream_t s);
+// Cost-volume source with partial output (the fused SSIM path; kern_cost_src.hip).
+void scan_full_cost(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
+void scan_band_cost(const ScanArgs& a, int LPL, bool var, int wpb, hipStream_t s);
 // Unfused export (SRC_COST, OUT_U16 / OUT_I32) of the full-range scans.
 void scan_full_export(const ScanArgs& a, int LPL, int K, int out, bool banded, int wpb, hipStream_t s);
 // Layered path merge: src = SRC_MERGE (later layers: the merge of the previous layer's
@@ -70,6 +74,9 @@ void downsample(const uint8_t* in, int pitch, uint8_t* out, const uint8_t* in2, 
                 uint8_t* out2, int w, int h, hipStream_t s);
 void cost(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int H,
           const int16_t* lo, const uint8_t* len, int cap, int D, uint8_t* cost, hipStream_t s);
+// SSIM cost volume (kern_ssim.hip), same layout and band rules as cost().
+void cost_ssim(const uint8_t* L, int lpitch, const uint8_t* R, int rpitch, int W, int H,
+               const int16_t* lo, const uint8_t* len, int cap, int D, uint8_t* cost, hipStream_t s);
 // Census tiles [0, nblocks) of every view (nblocks < 0: every level).
 void census_pyr(const CenPyr& cp, hipStream_t s, int nblocks = -1);
 // Top-level full-range scan (census source src: SRC_CENSUS or SRC_CENSUS_OCC, optionally
@@ -85,6 +92,8 @@ void vdisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* h
 void udisparity(const int16_t* disp, int W, int H, int pitch, int D, uint32_t* hist, hipStream_t s);
 void road(const uint32_t* hist, int D, int H, int eta, uint8_t* back, int16_t* path, int32_t* energy,
           hipStream_t s);
+// The paper's propagation (kern_prop.hip): block modes (a.block > 0) or interpolation.
+void propagate(const PropArgs& a, hipStream_t s);
 void fill_u16(uint16_t* p, size_t n, uint16_t v, hipStream_t s);
 void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 

@@ -44,6 +44,10 @@ mpv_status check_params(const mpv_params* p, bool fused) {
   if (p->merge != MPV_MERGE_SUM && p->merge != MPV_MERGE_LAYERED && p->merge != MPV_MERGE_LAYERED_OCC)
     return MPV_ERR_INVALID_ARG;
   if (p->grad_sigma < 0 || p->grad_sigma > 255) return MPV_ERR_INVALID_ARG;
+  if (p->data_term != MPV_DATA_CENSUS && p->data_term != MPV_DATA_SSIM) return MPV_ERR_INVALID_ARG;
+  // the fused path scans an SSIM cost volume for the sum of the paths with constant weights
+  if (fused && p->data_term == MPV_DATA_SSIM && (p->merge != MPV_MERGE_SUM || p->grad_sigma != 0))
+    return MPV_ERR_UNSUPPORTED;
   if (p->merge != MPV_MERGE_SUM) {
     if (p->num_paths < 2) return MPV_ERR_INVALID_ARG;
     // layer k's merged energies are at most 24 + (k+1)*lambda*tau (each pass adds at most
@@ -209,6 +213,8 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const 
   w.census_off = 0;
   const size_t cen = align_up((size_t)H * w.cpitch * sizeof(uint32_t));
   w.part_off = w.census_off + (own_census ? 2 * cen : 0);
+  if (p->data_term == MPV_DATA_SSIM)  // the level's SSIM cost volume [H][W][cap] instead
+    w.part_off = align_up((size_t)H * W * ((band && band->lo) ? band->cap : p->num_disp));
   // partial volumes, then a 256 B sink for stores past a line's end
   w.total = w.part_off + align_up((size_t)p->num_paths * H * W * w.sc.capP) + ALIGN;
   w.fits = (size_t)H * W * w.sc.capP <= 0x7FFFFFFFu && cen <= 0x7FFFFFFFu && H <= MPV_MAX_HEIGHT;
@@ -317,7 +323,16 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
     a.ipitch = gimg ? gpitch : lpitch;
     a.sigma = p->grad_sigma;
   }
-  if (cen) {  // census computed beforehand, in the same layout (cpitch, cmargin)
+  const bool ssim = p->data_term == MPV_DATA_SSIM;
+  int data = SRC_CENSUS;  // scan source of the data term
+  if (ssim) {  // the SSIM cost volume of the level, computed once, read by every direction
+    HookScope hs(MPV_STAGE_CENSUS, level, s);
+    uint8_t* cv = ws + lw.census_off;
+    mpvl::cost_ssim(L, lpitch, R, rpitch, W, H, a.lo, a.len, a.cap, a.D, cv, s);
+    a.cost = cv;
+    a.cl = a.cr = nullptr;
+    data = SRC_COST;
+  } else if (cen) {  // census computed beforehand, in the same layout (cpitch, cmargin)
     a.cl = cen[0];
     a.cr = cen[1];
   } else {
@@ -332,10 +347,10 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
       int dirs[8];
       for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
       plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
-      if (fuse && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
+      if (fuse && !ssim && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
         mpvl::scan_full_cen(a, SRC_CENSUS | grad, *fuse, cen0, ncen, lw.sc.LPL, lw.sc.K, wpb_of(sched), s);
       else
-        launch_scan(a, lw.sc, SRC_CENSUS | grad, OUT_PART, sched, s);
+        launch_scan(a, lw.sc, data | grad, OUT_PART, sched, s);
     } else {
       // Section 3.2 / Table alg: one dependent launch per layer
       for (int k = 0; k < nl; ++k) {
@@ -372,6 +387,8 @@ mpv_status pyr_geom(const mpv_pyramid_params* p, int D, int W, int H, PyrGeom& g
   if (st) return st;
   if ((st = check_sched(p->sched))) return st;
   if (p->levels < 1 || p->levels > MPV_MAX_LEVELS || p->band_radius < 0) return MPV_ERR_INVALID_ARG;
+  if (p->propagation != MPV_PROP_NEAREST && p->propagation != MPV_PROP_PAPER) return MPV_ERR_INVALID_ARG;
+  if (p->block < 0 || p->block > MPV_MAX_BLOCK || (p->block & 1)) return MPV_ERR_INVALID_ARG;
   if (W < 1 || H < 1 || W > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
   g.L = p->levels;
   for (int l = 0; l < g.L; ++l) {
@@ -405,6 +422,14 @@ mpv_params level_params(const mpv_pyramid_params* p, int Dl) {
   mpv_params lp = p->base;
   lp.num_disp = Dl;
   return lp;
+}
+
+// MPV_PROP_PAPER: block side of level l (1 .. L-1) of the paper's propagation; 0 = the last
+// level's per-pixel interpolation.
+int prop_block(const mpv_pyramid_params* p, int L, int l) {
+  if (l == L - 1) return 0;
+  const int b = p->block ? p->block : 8;
+  return std::max(b >> (l - 1), 2);
 }
 
 // fused_census (mpv_pyramid): the census of every level is computed up front from the input
@@ -692,6 +717,66 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
   }
 }
 
+// mpv_pyramid over the SSIM data term: the coarser images of both views are built first
+// (Section 3.4 pyramid, finest to coarsest), then every level computes its SSIM cost volume
+// and runs the scans and the reduce on it; the bands propagate as with the census.
+mpv_status pyramid_ssim(const mpv_pyramid_params* p, const PyrGeom& g, const PyrWs& w,
+                        const mpv_image* left, const mpv_image* right, const mpv_pyramid_out* out,
+                        uint8_t* ws, hipStream_t stream) {
+  const int L = g.L;
+  const uint8_t* img[MPV_MAX_LEVELS][2];
+  int pitch[MPV_MAX_LEVELS];
+  img[L - 1][0] = left->data;
+  img[L - 1][1] = right->data;
+  pitch[L - 1] = left->pitch;
+  for (int l = L - 2; l >= 0; --l) {
+    uint8_t* dl = ws + w.img_off[l];
+    uint8_t* dr = dl + (size_t)g.W[l] * g.H[l];
+    HookScope hs(MPV_STAGE_DOWNSAMPLE, l, stream);
+    if (l == L - 2 && left->pitch != right->pitch) {  // two launches: the views' pitches differ
+      mpvl::downsample(left->data, left->pitch, dl, nullptr, 0, nullptr, g.W[l], g.H[l], stream);
+      mpvl::downsample(right->data, right->pitch, dr, nullptr, 0, nullptr, g.W[l], g.H[l], stream);
+    } else {
+      mpvl::downsample(img[l + 1][0], pitch[l + 1], dl, img[l + 1][1], pitch[l + 1], dr, g.W[l], g.H[l],
+                       stream);
+    }
+    img[l][0] = dl;
+    img[l][1] = dr;
+    pitch[l] = g.W[l];
+  }
+  for (int l = 0; l < L; ++l) {
+    int16_t* raw = out->level_raw[l] ? out->level_raw[l] : (int16_t*)(ws + w.raw_off[l]);
+    const mpv_params lpar = level_params(p, g.D[l]);
+    mpv_band b{l > 0 ? (const int16_t*)(ws + w.lo_off[l & 1]) : nullptr, nullptr, g.cap[l]};
+    const bool last = l == L - 1;
+    NextBand nb{(int16_t*)(ws + w.lo_off[(l + 1) & 1]), 0, 0, 0, 0, 0};
+    if (!last) {
+      nb.W = g.W[l + 1];
+      nb.H = g.H[l + 1];
+      nb.D = g.D[l + 1];
+      nb.R = p->band_radius;
+      nb.cap = g.cap[l + 1];
+    }
+    if (last && out->disp_raw && !out->level_raw[l]) raw = out->disp_raw;
+    const bool paper = p->propagation == MPV_PROP_PAPER;
+    const mpv_status st = run_level(&lpar, img[l][0], pitch[l], img[l][1], last ? right->pitch : pitch[l],
+                                    g.W[l], g.H[l], l > 0 ? &b : nullptr, last ? out->disp : nullptr,
+                                    last ? out->disp_right : nullptr, raw, ws + w.level_off, l, p->sched,
+                                    stream, (last || paper) ? nullptr : &nb);
+    if (st) return st;
+    if (paper && !last) {
+      HookScope hs(MPV_STAGE_PROPAGATE, l, stream);
+      const PropArgs pa{raw, g.W[l], g.H[l], nb.lo, nb.W, nb.H, nb.D, nb.R, nb.cap, prop_block(p, L, l + 1)};
+      mpvl::propagate(pa, stream);
+    }
+    if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
+      if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),
+                         hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return MPV_ERR_DEVICE;
+  }
+  return launched();
+}
+
 }  // namespace
 
 extern "C" {
@@ -733,9 +818,9 @@ mpv_status mpv_cost(const mpv_params* p, const mpv_image* left, const mpv_image*
   const int W = left->width, H = left->height;
   if (W > MPV_MAX_WIDTH) return MPV_ERR_INVALID_ARG;
   const bool banded = band && band->lo;
-  mpvl::cost(left->data, left->pitch, right->data, right->pitch, W, H, banded ? band->lo : nullptr,
-             banded ? band->len : nullptr, banded ? band->cap : p->num_disp, p->num_disp, cost,
-             stream);
+  (p->data_term == MPV_DATA_SSIM ? mpvl::cost_ssim : mpvl::cost)(
+      left->data, left->pitch, right->data, right->pitch, W, H, banded ? band->lo : nullptr,
+      banded ? band->len : nullptr, banded ? band->cap : p->num_disp, p->num_disp, cost, stream);
   return launched();
 }
 
@@ -839,7 +924,7 @@ mpv_status mpv_match(const mpv_params* p, const mpv_image* left, const mpv_image
 size_t mpv_pyramid_workspace_bytes(const mpv_pyramid_params* p, int32_t W, int32_t H) {
   PyrGeom g;
   if (!p || pyr_geom(p, p->base.num_disp, W, H, g)) return 0;
-  return pyr_ws(p, g, true).total;
+  return pyr_ws(p, g, p->base.data_term != MPV_DATA_SSIM).total;
 }
 
 mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
@@ -851,10 +936,12 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
   PyrGeom g;
   mpv_status st = pyr_geom(p, p->base.num_disp, left->width, left->height, g);
   if (st) return st;
-  const PyrWs w = pyr_ws(p, g, true);
+  const bool ssim = p->base.data_term == MPV_DATA_SSIM;
+  const PyrWs w = pyr_ws(p, g, !ssim);
   if (!workspace || workspace_bytes < w.total) return MPV_ERR_WORKSPACE;
   uint8_t* ws = (uint8_t*)workspace;
   const int L = g.L;
+  if (ssim) return pyramid_ssim(p, g, w, left, right, out, ws, stream);
   // census of every level of both views, built from the input in one launch
   CenPyr cp{};
   cp.img[0] = left->data;
@@ -903,12 +990,19 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
       nb.cap = g.cap[l + 1];
     }
     if (last && out->disp_raw && !out->level_raw[l]) raw = out->disp_raw;
+    // nearest propagation rides in this level's reduce; the paper's runs after it
+    const bool paper = p->propagation == MPV_PROP_PAPER;
     st = run_level(&lpar, nullptr, 0, nullptr, 0, g.W[l], g.H[l], l > 0 ? &b : nullptr,
                    last ? out->disp : nullptr, last ? out->disp_right : nullptr, raw,
-                   ws + w.level_off, l, p->sched, stream, last ? nullptr : &nb, cen[l],
+                   ws + w.level_off, l, p->sched, stream, (last || paper) ? nullptr : &nb, cen[l],
                    last ? left->data : cp.limg[l], last ? left->pitch : g.W[l],
                    fuse && l == 0 ? &cp : nullptr, cp.first[1], cp.first[L] - cp.first[1]);
     if (st) return st;
+    if (paper && !last) {
+      HookScope hs(MPV_STAGE_PROPAGATE, l, stream);
+      const PropArgs pa{raw, g.W[l], g.H[l], nb.lo, nb.W, nb.H, nb.D, nb.R, nb.cap, prop_block(p, L, l + 1)};
+      mpvl::propagate(pa, stream);
+    }
     if (last && out->disp_raw && out->level_raw[l] && out->disp_raw != out->level_raw[l])
       if (hipMemcpyAsync(out->disp_raw, out->level_raw[l], (size_t)g.W[l] * g.H[l] * sizeof(int16_t),
                          hipMemcpyDeviceToDevice, stream) != hipSuccess)
@@ -921,6 +1015,7 @@ mpv_status mpv_pyramid(const mpv_pyramid_params* p, const mpv_image* left,
 mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* items, int32_t n,
                             mpv_batch* out) {
   if (!p || !items || n < 1 || !out) return MPV_ERR_INVALID_ARG;
+  if (p->propagation == MPV_PROP_PAPER || p->base.data_term != MPV_DATA_CENSUS) return MPV_ERR_UNSUPPORTED;
   mpv_batch_s* b = new (std::nothrow) mpv_batch_s();
   if (!b) return MPV_ERR_INVALID_ARG;
   b->p = *p;
@@ -1070,8 +1165,8 @@ void mpv_batch_destroy(mpv_batch b) {
 
 // ---- learned band proposal: coarse level + features --------------------------------------
 size_t mpv_lb_coarse_workspace_bytes(const mpv_params* p, int32_t W0, int32_t H0) {
-  if (check_params(p, true) || p->merge != MPV_MERGE_SUM || p->grad_sigma != 0 || W0 < 1 || H0 < 1 ||
-      W0 > MPV_MAX_WIDTH)
+  if (check_params(p, true) || p->merge != MPV_MERGE_SUM || p->grad_sigma != 0 ||
+      p->data_term != MPV_DATA_CENSUS || W0 < 1 || H0 < 1 || W0 > MPV_MAX_WIDTH)
     return 0;
   const LevelWs lw = level_ws(p, W0, H0, nullptr, mpv_schedule{});
   return lw.fits ? lw.total : 0;
@@ -1082,7 +1177,8 @@ mpv_status mpv_lb_coarse(const mpv_params* p, const mpv_image* left0, const mpv_
                          size_t workspace_bytes, hipStream_t stream) {
   mpv_status st = check_params(p, true);
   if (st) return st;
-  if (p->merge != MPV_MERGE_SUM || p->grad_sigma != 0) return MPV_ERR_UNSUPPORTED;
+  if (p->merge != MPV_MERGE_SUM || p->grad_sigma != 0 || p->data_term != MPV_DATA_CENSUS)
+    return MPV_ERR_UNSUPPORTED;
   if (!valid_image(left0) || !valid_image(right0) || !feat || !raw0 || !disp0)
     return MPV_ERR_INVALID_ARG;
   if (left0->width != right0->width || left0->height != right0->height) return MPV_ERR_INVALID_ARG;

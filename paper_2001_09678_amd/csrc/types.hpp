@@ -109,6 +109,18 @@ struct CenPyr {
   int first[5];  // first block of each level (64x4 outputs per block)
 };
 
+// Band of a finer level from the coarser level's raw winners in the paper's own form
+// (Section 3.4). block > 0 (intermediate level): every block x block tile searches around
+// twice the mode of its parents' raw disparities; block == 0 (last level): sampled pixels take
+// twice their parent's raw disparity, the others the linear interpolation of the samples.
+// Band of every pixel: cap disparities from lo = clamp(centre - R, 0, D - cap).
+struct PropArgs {
+  const int16_t* raw;  // coarser level's raw winners [Hc][Wc]
+  int Wc, Hc;
+  int16_t* lo;  // finer level's band starts [H][W]
+  int W, H, D, R, cap, block;
+};
+
 constexpr int RED_MAXW = 4096;
 constexpr int ROAD_MAX_HEIGHT = 4096;  // rows of a v-disparity image the road kernel holds in LDS
 

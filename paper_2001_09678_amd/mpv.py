@@ -29,6 +29,8 @@ class MPVParams:
     merge: str = "sum"
     # 0: constant lambda; 1..255: gradient-weighted TV of eq. EU (lambda * e^(-|dI| / sigma))
     grad_sigma: int = 0
+    # matching cost: "census" (Hamming of 5x5 census signatures) or "ssim" (Section 3.2)
+    data_term: str = "census"
 
     _MERGES = {"sum": _L.MPV_MERGE_SUM, "layered": _L.MPV_MERGE_LAYERED,
                "layered_occ": _L.MPV_MERGE_LAYERED_OCC}
@@ -36,9 +38,12 @@ class MPVParams:
     def c(self) -> _L.Params:
         if self.merge not in self._MERGES:
             raise ValueError(f"merge must be one of {sorted(self._MERGES)}")
+        if self.data_term not in ("census", "ssim"):
+            raise ValueError("data_term must be 'census' or 'ssim'")
         return _L.Params(self.num_disp, 2, self.num_paths, self.lam, self.tau, self.lr_max_diff,
                          _L.MPV_AGG_U16 if self.agg_type == "u16" else _L.MPV_AGG_I32,
-                         self._MERGES[self.merge], self.grad_sigma)
+                         self._MERGES[self.merge], self.grad_sigma,
+                         _L.MPV_DATA_SSIM if self.data_term == "ssim" else _L.MPV_DATA_CENSUS)
 
 
 def _stream():
@@ -170,13 +175,23 @@ class Schedule:
         return _L.Schedule(self.waves_per_block, self.full_lanes, self.band_lanes, self.order)
 
 
-def pyramid_params(params: MPVParams, levels: int, radius: int, sched: Schedule | None = None) -> _L.PyramidParams:
-    return _L.PyramidParams(params.c(), levels, radius, (sched or Schedule()).c())
+_PROPAGATIONS = {"nearest": _L.MPV_PROP_NEAREST, "paper": _L.MPV_PROP_PAPER}
+
+
+def pyramid_params(params: MPVParams, levels: int, radius: int, sched: Schedule | None = None,
+                   propagation: str = "nearest", block: int = 0) -> _L.PyramidParams:
+    """``propagation`` "nearest" (bands centred on twice the parent's raw winner) or "paper"
+    (Section 3.4: block modes at intermediate levels, ``block`` pixels at level 1 (0 = 8),
+    linear interpolation at the last level)."""
+    if propagation not in _PROPAGATIONS:
+        raise ValueError(f"propagation must be one of {sorted(_PROPAGATIONS)}")
+    return _L.PyramidParams(params.c(), levels, radius, (sched or Schedule()).c(), _PROPAGATIONS[propagation],
+                            block)
 
 
 def pyramid_workspace_bytes(params: MPVParams, levels: int, radius: int, width: int, height: int,
-                            sched: Schedule | None = None) -> int:
-    pp = pyramid_params(params, levels, radius, sched)
+                            sched: Schedule | None = None, propagation: str = "nearest", block: int = 0) -> int:
+    pp = pyramid_params(params, levels, radius, sched, propagation, block)
     return int(_L.lib().mpv_pyramid_workspace_bytes(C.byref(pp), width, height))
 
 
@@ -187,10 +202,11 @@ class Pyramid:
     current stream and returns the finest LR-checked disparity (int16, -1 invalid)."""
 
     def __init__(self, params: MPVParams, width: int, height: int, levels: int = 3, radius: int = 4,
-                 device="cuda", keep_levels: bool = False, sched: Schedule | None = None):
+                 device="cuda", keep_levels: bool = False, sched: Schedule | None = None,
+                 propagation: str = "nearest", block: int = 0):
         self.params, self.width, self.height = params, width, height
         self.levels, self.radius = levels, radius
-        self._pp = pyramid_params(params, levels, radius, sched)
+        self._pp = pyramid_params(params, levels, radius, sched, propagation, block)
         need = int(_L.lib().mpv_pyramid_workspace_bytes(C.byref(self._pp), width, height))
         if need == 0:
             raise _L.MPVError(_L.MPV_ERR_INVALID_ARG, "mpv_pyramid_workspace_bytes")
@@ -217,9 +233,11 @@ class Pyramid:
         return self.disp
 
 
-def pyramid(left, right, params: MPVParams, levels=3, radius=4, keep_levels=False, sched=None):
+def pyramid(left, right, params: MPVParams, levels=3, radius=4, keep_levels=False, sched=None,
+            propagation="nearest", block=0):
     h, w = left.shape
-    pyr = Pyramid(params, w, h, levels, radius, device=left.device, keep_levels=keep_levels, sched=sched)
+    pyr = Pyramid(params, w, h, levels, radius, device=left.device, keep_levels=keep_levels, sched=sched,
+                  propagation=propagation, block=block)
     pyr(left, right)
     return pyr
 

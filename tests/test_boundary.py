@@ -230,3 +230,29 @@ def test_noalloc_limits_before_any_device_call(L):
         L.MPV_ERR_INVALID_ARG
     assert lib.mpv_pyramid_noalloc(None, C.byref(small), C.byref(small), C.byref(out), None) == \
         L.MPV_ERR_INVALID_ARG
+
+
+def test_propagation_arguments_checked(L):
+    lib = L.lib()
+    for prop, block, ok in [(0, 0, True), (1, 0, True), (1, 8, True), (1, 32, True), (2, 0, False),
+                            (1, 7, False), (1, 34, False), (1, -2, False)]:
+        pp = L.PyramidParams(_params(L, num_disp=128, num_paths=8), 3, 4)
+        pp.propagation, pp.block = prop, block
+        n = lib.mpv_pyramid_workspace_bytes(C.byref(pp), 640, 480)
+        assert (n > 0) == ok, (prop, block)
+
+
+def test_ssim_combinations_checked(L):
+    """The SSIM data term runs with the sum of the paths and constant weights on the fused
+    path; other combinations, batches and unknown data terms are rejected up front."""
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    for kw, ok in [(dict(data_term=1), True), (dict(data_term=1, merge=1), False),
+                   (dict(data_term=1, grad_sigma=16), False), (dict(data_term=2), False)]:
+        pp = L.PyramidParams(_params(L, num_disp=64, num_paths=8, **kw), 3, 4)
+        assert (lib.mpv_pyramid_workspace_bytes(C.byref(pp), 320, 240) > 0) == ok, kw
+    pp = L.PyramidParams(_params(L, num_disp=64, num_paths=8, data_term=1), 3, 4)
+    item = (L.BatchItem * 1)()
+    item[0] = L.BatchItem(L.Image(fake, 64, 48, 64), L.Image(fake, 64, 48, 64), 32, fake, None, None)
+    h = C.c_void_p()
+    assert lib.mpv_batch_create(C.byref(pp), item, 1, C.byref(h)) == L.MPV_ERR_UNSUPPORTED
