@@ -256,8 +256,59 @@ def learned_bench(params, dev, steps, pairs):
     out["banded"]["mde_s_evaluated"] = round(evaluated / (out["banded"]["ms_per_step"] * 1e-3) / 1e6, 1)
     out["banded"]["mean_band_width"] = round(int(m.len.sum().item()) / (W * H), 3)
     out["quality"] = learned.evaluate(net, specs, params)
+    out["ideal_bands"] = ideal_band_bench(params, dev, specs[:8], steps)
     out["weights"] = {k: meta[k] for k in ("pairs", "first_seed", "steps", "batch", "lr", "beta") if k in meta}
     out["held_out_pairs"] = pairs
+    return out
+
+
+def ideal_band_bench(params, dev, specs, steps, widths=(9, 16, 24, 32, 48, 58)):
+    """The best any band proposal could do: bands of width w centred on plain MPV's own raw
+    winner (lo = clamp(raw - w/2, 0, D - w)), matched through mpv_match at the finest level;
+    bad pixels against plain MPV (plain-valid pixels that are invalid or more than 1 px away)
+    and the banded level's time per frame, next to plain full range."""
+    import torch
+    from paper_2001_09678_amd import learned, mpv
+    from paper_2001_09678_amd.scene import batch_scenes
+    scenes = batch_scenes(specs, workers=16)
+    _, W, H, D, _ = specs[0]
+    plain = mpv.Pyramid(params, W, H, levels=1, device=dev)
+    out = {"pairs": len(specs), "widths": {}}
+    refs = []
+    for sc in scenes:
+        L = torch.from_numpy(sc.left).to(dev)
+        R = torch.from_numpy(sc.right).to(dev)
+        d = plain(L, R).clone()
+        refs.append((L, R, d, plain.raw.clone()))
+    ms_plain, _, _, _ = time_pipeline(plain, refs[0][0], refs[0][1], steps, 5)
+    out["plain_ms"] = round(ms_plain, 4)
+    for w in widths:
+        if w > D:
+            continue
+        bad = valid = 0
+        worst = 0.0
+        for L, R, d, raw in refs:
+            lo = (raw.int() - w // 2).clamp(0, D - w).to(torch.int16)
+            band = mpv.Band(lo.contiguous(), w)
+            got = mpv.match(L, R, params, band)
+            i, df, n = learned.compare_to_plain(got, d)
+            bad, valid = bad + i + df, valid + n
+            worst = max(worst, (i + df) / max(n, 1))
+        L, R, _, raw = refs[0]
+        lo = (raw.int() - w // 2).clamp(0, D - w).to(torch.int16).contiguous()
+        band = mpv.Band(lo, w)
+        ws = torch.empty(mpv.match_workspace_bytes(params, W, H, band), dtype=torch.uint8, device=dev)
+        for _ in range(5):
+            mpv.match(L, R, params, band, workspace=ws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            mpv.match(L, R, params, band, workspace=ws)
+        b.record()
+        torch.cuda.synchronize()
+        out["widths"][str(w)] = {"bad_vs_plain": round(bad / max(valid, 1), 5), "max_pair_bad_vs_plain": round(worst, 5),
+                                 "banded_level_ms": round(a.elapsed_time(b) / steps, 4)}
     return out
 
 
@@ -430,22 +481,23 @@ def road_bench(disp, num_disp, steps=50, eta=8):
 
 def serve_bench(seconds, per_rig=8, saturate=32):
     """Frame-stream service: 8 rigs at 30 fps (shapes and ranges drawn by seed 5), HBM-budget
-    admission, continuous batching on 2 streams; latency is arrival to download complete,
-    host frames in pinned memory. Then the same rigs with every frame offered at once
-    (saturated) for the service's throughput ceiling."""
+    admission, continuous batching: the frames admitted in one scheduler step run as one
+    batched launch per stage (batched executor), beside one mpv_pyramid per frame on 2 streams
+    (streams executor). Latency is arrival to download complete, host frames in pinned memory.
+    Then the same rigs with every frame offered at once (saturated) for the service's
+    throughput ceiling."""
     import torch
     from paper_2001_09678_amd import serve
     specs = serve.rig_specs(8, 5)
     frames = serve.rig_frames(specs, per_rig, pinned=True)
-    ex = serve.GpuExecutor(streams=2)
     budget = 16 << 30
 
     def make(rid, rig, seq, t):
         l, r = frames[rig][seq % per_rig]
         return serve.Request(rid, rig, seq, specs[rig], l, r, t)
 
-    def once(sched, max_inflight):
-        server = serve.Server(ex, budget, max_inflight=max_inflight, max_batch=8)
+    def once(ex, sched, max_inflight, max_batch):
+        server = serve.Server(ex, budget, max_inflight=max_inflight, max_batch=max_batch)
         t0 = time.perf_counter()
         res = serve.run(server, sched, make)
         span = time.perf_counter() - t0
@@ -456,15 +508,39 @@ def serve_bench(seconds, per_rig=8, saturate=32):
         server.close()
         return out
 
-    once([(0.0, r, 0) for r in range(8)], 16)  # warm-up: first allocation of every rig's slot
-    torch.cuda.synchronize()
-    paced = once(serve.arrivals(8, 30.0, seconds, seed=5), 32)
-    paced["offered_fps"] = 240
-    sat = once([(0.0, r, f) for f in range(saturate) for r in range(8)], 32)
-    return {"rigs": [[sp.width, sp.height, sp.num_disp] for sp in specs], "hbm_budget_bytes": budget,
-            "streams": 2, "paced_30fps": paced, "saturated": sat,
-            "fallback_fraction": None,
-            "note": "fixed +/-4 band pyramid per frame; learned bands are not used by the service"}
+    out = {"rigs": [[sp.width, sp.height, sp.num_disp] for sp in specs], "hbm_budget_bytes": budget}
+    for name in ("batched", "streams"):
+        if name == "batched":
+            ex = serve.BatchedGpuExecutor(specs, per_spec=8)
+            cap = dict(max_inflight=48, max_batch=16)
+        else:
+            ex = serve.GpuExecutor(streams=2)
+            cap = dict(max_inflight=32, max_batch=8)
+        once(ex, [(0.0, r, 0) for r in range(8)], **cap)  # warm-up: first use of every rig's slot
+        torch.cuda.synchronize()
+        paced = once(ex, serve.arrivals(8, 30.0, seconds, seed=5), **cap)
+        paced["offered_fps"] = 240
+        sat = once(ex, [(0.0, r, f) for f in range(saturate) for r in range(8)], **cap)
+        out[name] = {"paced_30fps": paced, "saturated": sat, **cap}
+        if name == "batched":
+            out[name]["arena_bytes"] = ex.arena_bytes
+            ex.close()
+    # the learned-band path with plain fallback (trained weights), one frame per launch
+    from paper_2001_09678_amd import learned
+    if os.path.exists(learned.DEFAULT_WEIGHTS):
+        net, _ = learned.BandNet.load(learned.DEFAULT_WEIGHTS)
+        ex = serve.LearnedGpuExecutor(net, streams=2)
+        cap = dict(max_inflight=16, max_batch=8)
+        once(ex, [(0.0, r, 0) for r in range(8)], **cap)
+        ex.frames = ex.fallbacks = 0
+        torch.cuda.synchronize()
+        paced = once(ex, serve.arrivals(8, 30.0, seconds, seed=5), **cap)
+        paced["offered_fps"] = 240
+        out["learned"] = {"paced_30fps": paced, "fallback_fraction": round(ex.fallback_fraction, 4), **cap}
+        out["fallback_fraction"] = round(ex.fallback_fraction, 4)
+    out["note"] = ("batched and streams: fixed +/-4 band pyramid per frame; learned: learned bands with "
+                   "plain full-range fallback")
+    return out
 
 
 def pct(vals, q):

@@ -295,6 +295,15 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t stream);
 /* Same work as one hipGraph: captured on a private stream at the first call, then replayed
  * on `stream` with one hipGraphLaunch per call. */
 mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t stream);
+/* The launches of mpv_batch_run restricted to the n distinct items idx[0..n) (a service's
+ * admitted frames, in any order): each item keeps its own workspace region and outputs, so
+ * its output still equals mpv_pyramid of that pair alone, and the other items' outputs are
+ * untouched. The restricted descriptor tables are planned on the host and copied, through
+ * pinned staging memory the batch owns (a small ring allocated at the first call, freed by
+ * mpv_batch_destroy), into a second table area of the workspace, then the launches are
+ * enqueued. Calls on one batch share that table area: issue them (and mpv_batch_run) on one
+ * stream. The call may wait for the upload of the call four before it to have completed. */
+mpv_status mpv_batch_run_items(mpv_batch b, const int32_t *idx, int32_t n, hipStream_t stream);
 void mpv_batch_destroy(mpv_batch b);
 
 /* Road profile in v-disparity space and the u-disparity image (Section 3.5), downstream of

@@ -100,6 +100,7 @@ def lib():
             "mpv_batch_bind": ([P, P, S, P], i32),
             "mpv_batch_run": ([P, P], i32),
             "mpv_batch_run_graph": ([P, P], i32),
+            "mpv_batch_run_items": ([P, P, i32, P], i32),
             "mpv_batch_destroy": ([P], None),
             "mpv_lb_coarse_workspace_bytes": ([C.POINTER(Params), i32, i32], S),
             "mpv_lb_coarse": ([C.POINTER(Params), C.POINTER(Image), C.POINTER(Image), P, P, P, P, S, P], i32),

@@ -488,7 +488,16 @@ struct mpv_batch_s {
   };
   std::vector<Pair> pairs;
   size_t table_bytes = 0;  // descriptor tables at the start of the workspace
+  // a second table area right after the first holds the tables of mpv_batch_run_items;
+  // the pairs' regions start after both
+  size_t region_base() const { return 2 * table_bytes; }
   size_t total = 0;
+  // mpv_batch_run_items: pinned staging of its tables (a ring, each entry reusable once the
+  // event recorded after its upload has completed)
+  static constexpr int kStage = 4;
+  uint8_t* stage = nullptr;
+  hipEvent_t stage_ev[kStage] = {};
+  int stage_next = 0;
   uint8_t* ws = nullptr;
   enum Kind { DOWN, CENSUS, SCAN_FULL, SCAN_BAND, REDUCE };
   struct Launch {
@@ -501,6 +510,7 @@ struct mpv_batch_s {
     int src;  // scans: SRC_CENSUS, or a layered merge's SRC_CENSUS_OCC / SRC_MERGE
   };
   std::vector<Launch> launches;  // execution order
+  std::vector<Launch> sub_launches;  // launches of the last mpv_batch_run_items
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -527,7 +537,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
   const mpv_schedule& sc = b.p.sched;
   const int n = (int)b.pairs.size();
   auto region = [&](const mpv_batch_s::Pair& pr) -> uint8_t* {
-    return ws ? ws + b.table_bytes + pr.off : nullptr;
+    return ws ? ws + b.region_base() + pr.off : nullptr;
   };
   auto add_pix = [&](mpv_batch_s::Kind kind, int level, std::vector<PixArgs>& d, int views) {
     std::vector<int> first;
@@ -1042,7 +1052,7 @@ mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* i
   TableBuilder tb;
   plan_batch(*b, nullptr, tb);
   b->table_bytes = align_up(tb.bytes.size());
-  b->total = b->table_bytes + off;
+  b->total = b->region_base() + off;
   *out = b;
   return MPV_OK;
 }
@@ -1070,16 +1080,20 @@ mpv_status mpv_batch_bind(mpv_batch b, void* workspace, size_t bytes, hipStream_
   return hipStreamSynchronize(stream) == hipSuccess ? MPV_OK : MPV_ERR_DEVICE;
 }
 
-mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
-  if (!b || !b->ws) return MPV_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+// Enqueue planned launches whose tables start at `tables` in device memory.
+mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& launches, const uint8_t* tables,
+                        hipStream_t s) {
   const int wpb = wpb_of(b->p.sched);
   // the consecutive launches of one stage at one level (kernel variants, layers of a
   // layered merge) are bracketed together by the timing hook
   std::optional<HookScope> hs;
   int hs_stage = -1, hs_level = -1;
-  for (const auto& ln : b->launches) {
-    const void* desc = b->ws + ln.desc_off;
-    const int* first = (const int*)(b->ws + ln.first_off);
+  for (const auto& ln : launches) {
+    const void* desc = tables + ln.desc_off;
+    const int* first = (const int*)(tables + ln.first_off);
     const int stage = ln.kind == mpv_batch_s::DOWN     ? MPV_STAGE_DOWNSAMPLE
                       : ln.kind == mpv_batch_s::CENSUS ? MPV_STAGE_CENSUS
                       : ln.kind == mpv_batch_s::REDUCE ? MPV_STAGE_REDUCE
@@ -1131,6 +1145,49 @@ mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
   }
   return launched();
 }
+}  // namespace
+
+extern "C" {
+
+mpv_status mpv_batch_run(mpv_batch b, hipStream_t s) {
+  if (!b || !b->ws) return MPV_ERR_INVALID_ARG;
+  return run_launches(b, b->launches, b->ws, s);
+}
+
+mpv_status mpv_batch_run_items(mpv_batch b, const int32_t* idx, int32_t n, hipStream_t s) {
+  if (!b || !b->ws || !idx || n < 1 || n > (int32_t)b->pairs.size()) return MPV_ERR_INVALID_ARG;
+  std::vector<char> seen(b->pairs.size(), 0);
+  mpv_batch_s sub;
+  sub.p = b->p;
+  sub.table_bytes = b->table_bytes;
+  for (int i = 0; i < n; ++i) {
+    if (idx[i] < 0 || idx[i] >= (int32_t)b->pairs.size() || seen[idx[i]]) return MPV_ERR_INVALID_ARG;
+    seen[idx[i]] = 1;
+    sub.pairs.push_back(b->pairs[idx[i]]);  // keeps its workspace region (pr.off)
+  }
+  TableBuilder tb;
+  plan_batch(sub, b->ws, tb);
+  if (align_up(tb.bytes.size()) > b->table_bytes) return MPV_ERR_WORKSPACE;  // cannot happen: a subset
+  if (!b->stage) {
+    if (hipHostMalloc((void**)&b->stage, (size_t)mpv_batch_s::kStage * b->table_bytes) != hipSuccess) {
+      b->stage = nullptr;
+      return MPV_ERR_DEVICE;
+    }
+    for (int k = 0; k < mpv_batch_s::kStage; ++k)
+      if (hipEventCreateWithFlags(&b->stage_ev[k], hipEventDisableTiming) != hipSuccess) return MPV_ERR_DEVICE;
+  }
+  const int k = b->stage_next;
+  b->stage_next = (k + 1) % mpv_batch_s::kStage;
+  // this staging entry was last uploaded kStage runs ago: wait until that copy has read it
+  if (hipEventSynchronize(b->stage_ev[k]) != hipSuccess) return MPV_ERR_DEVICE;
+  uint8_t* st = b->stage + (size_t)k * b->table_bytes;
+  std::memcpy(st, tb.bytes.data(), tb.bytes.size());
+  uint8_t* area = b->ws + b->table_bytes;
+  if (hipMemcpyAsync(area, st, tb.bytes.size(), hipMemcpyHostToDevice, s) != hipSuccess) return MPV_ERR_DEVICE;
+  if (hipEventRecord(b->stage_ev[k], s) != hipSuccess) return MPV_ERR_DEVICE;
+  b->sub_launches = std::move(sub.launches);
+  return run_launches(b, b->sub_launches, area, s);
+}
 
 mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t s) {
   if (!b || !b->ws) return MPV_ERR_INVALID_ARG;
@@ -1160,6 +1217,14 @@ void mpv_batch_destroy(mpv_batch b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->stage) {
+    for (int k = 0; k < mpv_batch_s::kStage; ++k)
+      if (b->stage_ev[k]) {
+        (void)hipEventSynchronize(b->stage_ev[k]);
+        (void)hipEventDestroy(b->stage_ev[k]);
+      }
+    (void)hipHostFree(b->stage);
+  }
   delete b;
 }
 

@@ -244,31 +244,49 @@ class LearnedMatcher:
                                   mpv.match_workspace_bytes(params, width, height)), dtype=torch.uint8,
                               device=device)
         self.disp = torch.empty((height, width), dtype=torch.int16, device=device)
+        self.proposed = torch.cuda.Event()
         self.fallbacks = 0
         self.frames = 0
         self.last_fallback = False
 
     def propose(self, left, right):
+        """Enqueue the coarse level, the network and the fine bands on the current stream;
+        the low-confidence count is copied into pinned host memory behind the `proposed`
+        event (nothing waits here)."""
         l0, r0 = coarse_images(left, right, self.cfg.levels)
         feat, raw0, _ = self.coarse(l0, r0)
         o, _ = self.net.forward(feat.unsqueeze(0))
         bands(o[0], raw0, self.W, self.H, self.params.num_disp, self.cfg.theta, self.lo, self.len, self.nlow)
+        self.nlow_host.copy_(self.nlow, non_blocking=True)
+        self.proposed.record()
         return o
 
-    def __call__(self, left, right, allow_fallback=True):
-        """Disparity of one frame. With the fallback on, the low-confidence count is read back
-        (one small device-to-host copy) and decides between the banded and the full-range
-        finest level before either runs."""
-        self.propose(left, right)
+    def ready(self) -> bool:
+        """True once the last proposal's low-confidence count has reached the host."""
+        return self.proposed.query()
+
+    def fallback_due(self) -> bool:
+        """Whether the last proposal sends its frame to full-range matching (call once ready)."""
+        return int(self.nlow_host[0]) > self.cfg.fallback_frac * self.w0 * self.h0
+
+    def finish(self, left, right, fallback: bool):
+        """Enqueue the finest level: the proposed bands, or plain full range for a fallback."""
         self.frames += 1
+        self.last_fallback = fallback
+        self.fallbacks += int(fallback)
+        return mpv.match(left, right, self.params, None if fallback else self.band, workspace=self.ws)
+
+    def __call__(self, left, right, allow_fallback=True):
+        """Disparity of one frame. With the fallback on, the call waits for this frame's
+        proposal event (the count decides which finest level to enqueue); a pipeline that
+        keeps several frames in flight calls propose / ready / finish instead and never
+        waits (serve.LearnedGpuExecutor)."""
+        self.propose(left, right)
+        fb = False
         if allow_fallback:
-            self.nlow_host.copy_(self.nlow, non_blocking=False)
-            if self.nlow_host.item() > self.cfg.fallback_frac * self.w0 * self.h0:
-                self.fallbacks += 1
-                self.last_fallback = True
-                return mpv.match(left, right, self.params, None, workspace=self.ws)
-        self.last_fallback = False
-        return mpv.match(left, right, self.params, self.band, workspace=self.ws)
+            self.proposed.synchronize()
+            fb = self.fallback_due()
+        return self.finish(left, right, fb)
 
 
 # ---------------------------------------------------------------------------------------
@@ -397,7 +415,8 @@ def evaluate(net: BandNet, specs, params: mpv.MPVParams, cfg: LearnedConfig | No
             occ = torch.from_numpy(sc.occluded).cuda()
             ref = plain(L, R).clone()
             banded = lm(L, R, allow_fallback=False).clone()
-            fb = lm.nlow_host.copy_(lm.nlow).item() > cfg.fallback_frac * lm.w0 * lm.h0
+            lm.proposed.synchronize()
+            fb = lm.fallback_due()
             lm.fallbacks += int(fb)
             outs = {"plain": ref, names[1]: fixed(L, R), "learned_banded": banded,
                     "learned": ref if fb else banded}

@@ -284,6 +284,12 @@ class Batch:
         _L.check(_L.lib().mpv_batch_run_graph(self._h, _stream()), "mpv_batch_run_graph")
         return self.disp
 
+    def run_items(self, idx):
+        """Match only the pairs idx (distinct indices) in one batched launch per stage."""
+        arr = (C.c_int32 * len(idx))(*[int(i) for i in idx])
+        _L.check(_L.lib().mpv_batch_run_items(self._h, arr, len(idx), _stream()), "mpv_batch_run_items")
+        return [self.disp[i] for i in idx]
+
     def close(self):
         if getattr(self, "_h", None):
             _L.lib().mpv_batch_destroy(self._h)

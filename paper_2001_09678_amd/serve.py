@@ -27,7 +27,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["FrameSpec", "Request", "Result", "SlotPool", "Server", "rig_specs", "rig_frames", "arrivals", "run",
-           "GpuExecutor", "latency_summary"]
+           "GpuExecutor", "BatchedGpuExecutor", "LearnedGpuExecutor", "latency_summary"]
 
 RESOLUTIONS = [(640, 360), (1280, 720), (1920, 1080)]
 RANGES = [64, 128, 256]
@@ -99,6 +99,8 @@ class SlotPool:
         if self.held + need > self.budget:
             return None
         slot = self.alloc_fn(spec)
+        if slot is None:  # the executor has no slot of this shape free right now
+            return None
         self.held += need
         self.busy += need
         self.peak = max(self.peak, self.held)
@@ -380,3 +382,223 @@ class GpuExecutor:
         if isinstance(ticket, Exception):
             return ticket
         return ticket.host_out.numpy().copy()
+
+
+# ---------------------------------------------------------------------------------------
+# Batched GPU executor: the frames admitted together run as one batched launch per stage
+# ---------------------------------------------------------------------------------------
+class _ArenaSlot:
+    def __init__(self, idx, spec, left, right, host_out):
+        self.idx, self.spec, self.left, self.right, self.host_out = idx, spec, left, right, host_out
+        self.event = None
+
+
+class BatchedGpuExecutor:
+    """Continuous batching through the batched kernels: a fixed arena of `per_spec` slots for
+    each frame shape the rigs deliver (device inputs, outputs and workspace regions of one
+    mpv_batch over all of them). The frames admitted in one scheduler step are uploaded on an
+    upload stream and matched by one mpv_batch_run_items call (every stage one launch over
+    those frames) on the compute stream, which waits for the uploads; downloads follow on the
+    compute stream and every frame of the step completes on the step's event. Uploads of the
+    next step overlap the current step's kernels. Each frame's result equals mpv_pyramid of
+    that frame alone."""
+
+    def __init__(self, specs, per_spec: int = 4, levels: int = 3, radius: int = 4, num_paths: int = 8,
+                 device="cuda", sched=None):
+        import torch
+        from . import _lib, mpv
+        _lib.lib()  # the HIP library is required; there is no other path
+        self.torch = torch
+        self.device = torch.device(device)
+        self.levels, self.radius, self.num_paths = levels, radius, num_paths
+        self.upload = torch.cuda.Stream(device=self.device)
+        self.compute = torch.cuda.Stream(device=self.device)
+        uniq = []
+        for sp in specs:
+            if sp not in uniq and self._valid(sp):
+                uniq.append(sp)
+        self.slots, self.free_slots = [], {}
+        pairs = []
+        for sp in uniq:
+            self.free_slots[sp] = []
+            for _ in range(per_spec):
+                L = torch.zeros((sp.height, sp.width), dtype=torch.uint8, device=self.device)
+                R = torch.zeros_like(L)
+                host = torch.empty((sp.height, sp.width), dtype=torch.int16, pin_memory=True)
+                slot = _ArenaSlot(len(self.slots), sp, L, R, host)
+                self.slots.append(slot)
+                self.free_slots[sp].append(slot)
+                pairs.append((L, R, sp.num_disp))
+        params = mpv.MPVParams(num_disp=max(sp.num_disp for sp in uniq), num_paths=num_paths)
+        with torch.cuda.stream(self.compute):
+            self.batch = mpv.Batch(pairs, params, levels, radius, sched=sched, device=self.device)
+        self.arena_bytes = int(self.batch.workspace.numel()) + sum(
+            3 * sp.width * sp.height for sp in uniq) * per_spec
+        self._bytes = {}
+
+    def _valid(self, spec) -> bool:
+        from . import mpv
+        from ._lib import MPVError
+        try:
+            ws = mpv.pyramid_workspace_bytes(mpv.MPVParams(num_disp=spec.num_disp, num_paths=self.num_paths),
+                                             self.levels, self.radius, spec.width, spec.height)
+        except (MPVError, ValueError):
+            return False
+        return ws > 0
+
+    def bytes_needed(self, spec) -> int:
+        """Bytes one in-flight frame of this shape occupies in the arena (0: not served)."""
+        if spec in self._bytes:
+            return self._bytes[spec]
+        if spec not in self.free_slots:
+            self._bytes[spec] = 0
+            return 0
+        from . import mpv
+        ws = mpv.pyramid_workspace_bytes(mpv.MPVParams(num_disp=spec.num_disp, num_paths=self.num_paths),
+                                         self.levels, self.radius, spec.width, spec.height)
+        self._bytes[spec] = int(ws) + 3 * spec.width * spec.height
+        return self._bytes[spec]
+
+    def alloc(self, spec):
+        free = self.free_slots.get(spec)
+        return free.pop() if free else None
+
+    def free(self, slot):
+        self.free_slots[slot.spec].append(slot)
+
+    def launch(self, items):
+        torch = self.torch
+        tickets, run = [], []
+        with torch.cuda.stream(self.upload):
+            for req, slot in items:
+                try:
+                    if req.inject == "launch":
+                        raise RuntimeError("injected launch fault")
+                    slot.left.copy_(req.left, non_blocking=True)
+                    slot.right.copy_(req.right, non_blocking=True)
+                    run.append(slot)
+                    tickets.append(slot)
+                except Exception as e:  # the failing request only
+                    tickets.append(e)
+            up = torch.cuda.Event()
+            up.record(self.upload)
+        if run:
+            with torch.cuda.stream(self.compute):
+                self.compute.wait_event(up)
+                self.batch.run_items([s.idx for s in run])
+                for slot in run:
+                    slot.host_out.copy_(self.batch.disp[slot.idx], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(self.compute)
+            for slot in run:
+                slot.event = ev
+        return tickets
+
+    def done(self, ticket) -> bool:
+        return isinstance(ticket, Exception) or ticket.event.query()
+
+    def collect(self, ticket):
+        if isinstance(ticket, Exception):
+            return ticket
+        return ticket.host_out.numpy().copy()
+
+    def close(self):
+        self.compute.synchronize()
+        self.batch.close()
+
+
+# ---------------------------------------------------------------------------------------
+# Learned-band executor: proposal, then the banded finest level or the plain fallback
+# ---------------------------------------------------------------------------------------
+class _LearnedTicket:
+    def __init__(self, slot, stream):
+        self.slot, self.stream, self.phase, self.event = slot, stream, 1, None
+
+
+class LearnedGpuExecutor(GpuExecutor):
+    """Frames matched by the learned-band path with plain fallback: the launch enqueues the
+    upload and the proposal (coarse level, network, fine bands; the low-confidence count
+    follows into pinned memory behind an event); once the scheduler sees that event complete
+    it enqueues, on the same stream, the banded finest level, or plain full-range MPV for a
+    frame whose low-confidence fraction is above the threshold, then the download. Nothing
+    blocks the host; `fallback_fraction` counts the fallback frames."""
+
+    def __init__(self, net, cfg=None, **kw):
+        super().__init__(**kw)
+        self.net, self.cfg = net, cfg
+        self.frames = 0
+        self.fallbacks = 0
+
+    def bytes_needed(self, spec) -> int:
+        if spec in self._bytes:
+            return self._bytes[spec]
+        from . import mpv
+        from ._lib import MPVError
+        p = self.params(spec)
+        try:
+            full = mpv.match_workspace_bytes(p, spec.width, spec.height)
+        except (MPVError, ValueError):
+            full = 0
+        if full <= 0 or spec.width >> 2 < 1 or spec.height >> 2 < 1:
+            self._bytes[spec] = 0
+            return 0
+        W, H = spec.width, spec.height
+        # full-range workspace (fallback), bands, both views, maps and the coarse level's buffers
+        total = int(full) + 3 * W * H + 2 * W * H + 2 * W * H + (W >> 2) * (H >> 2) * 64
+        self._bytes[spec] = total
+        return total
+
+    def alloc(self, spec):
+        from .learned import LearnedMatcher
+        torch = self.torch
+        W, H = spec.width, spec.height
+        m = LearnedMatcher(self.net, self.params(spec), W, H, self.cfg, device=self.device)
+        return _Slot(spec, torch.empty((H, W), dtype=torch.uint8, device=self.device),
+                     torch.empty((H, W), dtype=torch.uint8, device=self.device), m,
+                     torch.empty((H, W), dtype=torch.int16, pin_memory=True), torch.cuda.Event())
+
+    def launch(self, items):
+        torch = self.torch
+        s = self.streams[self.k % len(self.streams)]
+        self.k += 1
+        tickets = []
+        with torch.cuda.stream(s):
+            for req, slot in items:
+                try:
+                    if req.inject == "launch":
+                        raise RuntimeError("injected launch fault")
+                    slot.left.copy_(req.left, non_blocking=True)
+                    slot.right.copy_(req.right, non_blocking=True)
+                    slot.matcher.propose(slot.left, slot.right)
+                    tickets.append(_LearnedTicket(slot, s))
+                except Exception as e:  # the failing request only
+                    tickets.append(e)
+        return tickets
+
+    def done(self, ticket) -> bool:
+        if isinstance(ticket, Exception):
+            return True
+        if ticket.phase == 1:
+            m = ticket.slot.matcher
+            if not m.ready():
+                return False
+            torch = self.torch
+            fb = m.fallback_due()
+            with torch.cuda.stream(ticket.stream):
+                out = m.finish(ticket.slot.left, ticket.slot.right, fb)
+                ticket.slot.host_out.copy_(out, non_blocking=True)
+                ticket.slot.event.record(ticket.stream)
+            self.frames += 1
+            self.fallbacks += int(fb)
+            ticket.phase = 2
+            return False
+        return ticket.slot.event.query()
+
+    def collect(self, ticket):
+        if isinstance(ticket, Exception):
+            return ticket
+        return ticket.slot.host_out.numpy().copy()
+
+    @property
+    def fallback_fraction(self):
+        return self.fallbacks / self.frames if self.frames else None

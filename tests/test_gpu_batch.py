@@ -154,3 +154,34 @@ def test_batch_workload_vs_oracle(orc, batch_workload, combo):
     _log("oracle for pair", i, specs[i])
     ref = orc.pyramid(scenes[i].left, scenes[i].right, specs[i][3], levels=3, radius=4, num_paths=8)[-1]
     np.testing.assert_array_equal(got[i], ref.out, err_msg=f"pair {i} {specs[i]} vs oracle")
+
+
+def test_run_items_subsets(mpv, orc):
+    """mpv_batch_run_items: successive runs over different subsets (in any order, more than
+    the staging ring holds) each give the solo results of exactly their pairs and leave the
+    other pairs' outputs untouched; a full run afterwards still works."""
+    import torch
+    scenes = _small_scenes()
+    params = mpv.MPVParams(num_disp=64, num_paths=8)
+    pairs = [(_cuda(sc.left), _cuda(sc.right), d) for sc, (_, _, d) in zip(scenes, SMALL)]
+    solo = [_np(mpv.pyramid(l, r, mpv.MPVParams(num_disp=d, num_paths=8), levels=3, radius=4).disp)
+            for l, r, d in pairs]
+    b = mpv.Batch(pairs, params, levels=3, radius=4, sched=mpv.Schedule(waves_per_block=2, order=1))
+    subsets = [[3], [0, 5], [4, 1, 2], [5], [2, 0], [1, 3, 4, 5], [0]]
+    for sub in subsets:
+        _log("run_items", sub)
+        for t in b.disp:
+            t.fill_(-9)
+        b.run_items(sub)
+        torch.cuda.synchronize()
+        for i in range(len(pairs)):
+            got = _np(b.disp[i])
+            if i in sub:
+                np.testing.assert_array_equal(got, solo[i], err_msg=f"subset {sub} pair {i}")
+            else:
+                assert (got == -9).all(), f"subset {sub} touched pair {i}"
+    b.run()
+    for i in range(len(pairs)):
+        np.testing.assert_array_equal(_np(b.disp[i]), solo[i])
+    ref = orc.pyramid(scenes[2].left, scenes[2].right, SMALL[2][2], levels=3, radius=4, num_paths=8)[-1]
+    np.testing.assert_array_equal(_np(b.disp[2]), ref.out)

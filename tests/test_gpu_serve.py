@@ -50,12 +50,13 @@ def _make(specs, frames, inject=()):
     return make
 
 
+@pytest.mark.parametrize("kind", ["streams", "batched"])
 @pytest.mark.parametrize("tight", [False, True])
-def test_service_results_equal_solo(rigs, tight):
+def test_service_results_equal_solo(rigs, tight, kind):
     from paper_2001_09678_amd import serve
     specs, frames, solo = rigs
-    _log("serve tight" if tight else "serve roomy", [(s.width, s.height, s.num_disp) for s in specs])
-    ex = serve.GpuExecutor(streams=2)
+    _log("serve", kind, "tight" if tight else "roomy", [(s.width, s.height, s.num_disp) for s in specs])
+    ex = serve.GpuExecutor(streams=2) if kind == "streams" else serve.BatchedGpuExecutor(specs, per_spec=3)
     need = sorted(ex.bytes_needed(s) for s in specs)
     budget = need[-1] + need[-2] if tight else 8 << 30
     server = serve.Server(ex, budget, max_inflight=16, max_batch=8)
@@ -72,6 +73,27 @@ def test_service_results_equal_solo(rigs, tight):
     s = serve.latency_summary(res, 0.5)
     _log("latency", s, "launches", server.launches, "peak bytes", server.pool.peak)
     server.close()
+    if kind == "batched":
+        ex.close()
+
+
+def test_batched_service_saturated_equals_solo(rigs):
+    """Every frame offered at once: admission steps carry several frames of mixed shapes into
+    one batched launch, and every result still equals the frame matched alone."""
+    from paper_2001_09678_amd import serve
+    specs, frames, solo = rigs
+    ex = serve.BatchedGpuExecutor(specs, per_spec=4)
+    server = serve.Server(ex, 16 << 30, max_inflight=32, max_batch=16)
+    sched = [(0.0, r, f) for f in range(4) for r in range(8)]
+    res = serve.run(server, sched, _make(specs, frames))
+    assert len(res) == len(sched) and all(r.ok for r in res)
+    for r in res:
+        np.testing.assert_array_equal(r.disp, solo[r.rig][r.seq % 2])
+    assert max(server.batch_sizes) > 1
+    _log("batched saturated: launches", server.launches, "mean batch",
+         sum(server.batch_sizes) / len(server.batch_sizes))
+    server.close()
+    ex.close()
 
 
 def test_invalid_request_fails_alone(rigs):
@@ -87,4 +109,30 @@ def test_invalid_request_fails_alone(rigs):
     assert not res[(1, 0)].ok and "invalid" in res[(1, 0)].error
     np.testing.assert_array_equal(res[(0, 0)].disp, solo[0][0])
     np.testing.assert_array_equal(res[(0, 1)].disp, solo[0][1])
+    server.close()
+
+
+def test_learned_service_equals_solo(rigs):
+    """The learned-band path with plain fallback in the service (proposal, then the banded
+    finest level or full range once the proposal's count reaches the host, no blocking read):
+    every frame equals the learned matcher run on that frame alone, and the fallback fraction
+    is reported."""
+    import torch
+    from paper_2001_09678_amd import learned, mpv, serve
+    specs, frames, _ = rigs
+    net, _ = learned.BandNet.load(learned.DEFAULT_WEIGHTS)
+    solo = []
+    for sp, fr in zip(specs, frames):
+        m = learned.LearnedMatcher(net, mpv.MPVParams(num_disp=sp.num_disp, num_paths=8), sp.width, sp.height)
+        solo.append([m(l.cuda(), r.cuda()).cpu().numpy() for l, r in fr])
+    ex = serve.LearnedGpuExecutor(net, streams=2)
+    server = serve.Server(ex, 16 << 30, max_inflight=8, max_batch=4)
+    sched = serve.arrivals(8, 30.0, 0.3, seed=5)
+    res = serve.run(server, sched, _make(specs, frames))
+    assert len(res) == len(sched)
+    for r in res:
+        assert r.ok, r.error
+        np.testing.assert_array_equal(r.disp, solo[r.rig][r.seq % 2], err_msg=f"rig {r.rig} frame {r.seq}")
+    assert ex.frames == len(res) and 0.0 <= ex.fallback_fraction <= 1.0
+    _log("learned service: fallback fraction", ex.fallback_fraction)
     server.close()
