@@ -49,8 +49,8 @@ FLOOR_B_PER_PIXEL = 4
 SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band_batch.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp"]
-SCAN_TRAFFIC = {"sources_sha1": "e9e28b15dfea887a70c2861c9a7d4e64b16166a0", "frames": 16,
-                "fetch_bytes": 3132743567, "write_bytes": 2003726400}
+SCAN_TRAFFIC = {"sources_sha1": "88e83067430356626e79a1156487cf71dad4b84a", "frames": 16,
+                "fetch_bytes": 3133623742, "write_bytes": 2004598409}
 
 
 def scan_sources_sha1():
@@ -490,7 +490,7 @@ def serve_bench(seconds, per_rig=8, saturate=32):
     from paper_2001_09678_amd import serve
     specs = serve.rig_specs(8, 5)
     frames = serve.rig_frames(specs, per_rig, pinned=True)
-    budget = 16 << 30
+    budget = 32 << 30
 
     def make(rid, rig, seq, t):
         l, r = frames[rig][seq % per_rig]
@@ -511,8 +511,8 @@ def serve_bench(seconds, per_rig=8, saturate=32):
     out = {"rigs": [[sp.width, sp.height, sp.num_disp] for sp in specs], "hbm_budget_bytes": budget}
     for name in ("batched", "streams"):
         if name == "batched":
-            ex = serve.BatchedGpuExecutor(specs, per_spec=8)
-            cap = dict(max_inflight=48, max_batch=16)
+            ex = serve.BatchedGpuExecutor(specs, per_spec=16)
+            cap = dict(max_inflight=96, max_batch=32)
         else:
             ex = serve.GpuExecutor(streams=2)
             cap = dict(max_inflight=32, max_batch=8)
@@ -805,14 +805,24 @@ def main():
     # 2P B per node for the whole plain frame
     s1_bytes = 2 * P * W * H * D
 
-    breakdown = {} if args.no_breakdown else stage_breakdown(pyr, left, right, levels)
-    road_res = {} if args.no_extra else road_bench(pyr.disp, D)
-    c1_res = {} if args.no_extra else c1_gpu_timing(dev, args.plain_steps * 2)
-    batch = {} if args.no_batch else batch_bench(params, levels, dev, args.batch_steps)
-    learned_res = {} if args.no_learned else learned_bench(params, dev, args.plain_steps, args.learned_pairs)
-    serve_res = {} if args.no_serve else serve_bench(args.serve_seconds)
-    layered_res = {} if args.no_layered else layered_bench(params, dev, left, right, levels, sched, psched,
-                                                           args.plain_steps * 2)
+    def section(name, skip, fn):
+        if skip:
+            return {}
+        t = time.perf_counter()
+        print(f"bench: {name} ...", file=sys.stderr, flush=True)
+        res = fn()
+        print(f"bench: {name} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+        return res
+
+    breakdown = section("stage breakdown", args.no_breakdown, lambda: stage_breakdown(pyr, left, right, levels))
+    road_res = section("road profile", args.no_extra, lambda: road_bench(pyr.disp, D))
+    c1_res = section("320x240 D=64", args.no_extra, lambda: c1_gpu_timing(dev, args.plain_steps * 2))
+    batch = section("64-pair batch", args.no_batch, lambda: batch_bench(params, levels, dev, args.batch_steps))
+    learned_res = section("learned bands", args.no_learned,
+                          lambda: learned_bench(params, dev, args.plain_steps, args.learned_pairs))
+    serve_res = section("service", args.no_serve, lambda: serve_bench(args.serve_seconds))
+    layered_res = section("layered merge and propagation", args.no_layered,
+                          lambda: layered_bench(params, dev, left, right, levels, sched, psched, args.plain_steps * 2))
 
     result = {
         "metric": METRIC,
@@ -879,6 +889,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline ...", file=sys.stderr, flush=True)
         cb = cpu_baseline(scene, cfg)
         cb["cpu_model"] = cpu_model()
         cb["c1_oracle"] = c1_oracle_timing()

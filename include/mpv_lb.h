@@ -37,8 +37,9 @@ mpv_status mpv_lb_coarse(const mpv_params *p, const mpv_image *left0, const mpv_
                          size_t workspace_bytes, hipStream_t stream);
 
 /* Packed bf16 weights of one layer (cin, cout multiples of 4 up to 32, or cout = 3):
- * forward: [round16(cout)][round16(9*cin)], k = (ky*3+kx)*cin + ci;
- * backward-data: [round16(cin)][round16(9*round4(cout))], taps mirrored, k = tap*round4(cout) + co. */
+ * forward: [round16(cout)][round32(9*cin)], k = (ky*3+kx)*cin + ci;
+ * backward-data: [round16(cin)][round32(9*round4(cout))], taps mirrored, k = tap*round4(cout) + co
+ * (the reduction padded to the 32-deep steps of the bf16 MFMA). */
 size_t mpv_lb_packed_elems(int32_t cin, int32_t cout);
 size_t mpv_lb_packed_bwd_elems(int32_t cin, int32_t cout);
 mpv_status mpv_lb_pack(const float *w, int32_t cin, int32_t cout, uint16_t *wfwd, uint16_t *wbwd,

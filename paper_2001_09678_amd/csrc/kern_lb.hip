@@ -1,11 +1,14 @@
 // Learned band proposal: features, BF16 MFMA convolutions (forward and backward),
 // deterministic weight gradients, loss/heads, Adam, band maps (include/mpv_lb.h).
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: rows = pixels (16 per
-// wave), columns = output channels (16 per tile), reduction = (tap, input channel) in
-// steps of 16. A lane holds A[pixel l%16][k 4*(l/16)..+3], B[k 4*(l/16)..+3][channel
-// l%16] and receives D[pixel 4*(l/16)+i][channel l%16]. Input channels of a tap are
-// contiguous in NHWC, so each A operand is one 8-byte load (zero outside the image).
+// Convolutions (forward and backward-data) are implicit GEMMs on gfx950's
+// v_mfma_f32_16x16x32_bf16: rows = pixels (16 per wave), columns = output channels (16 per
+// tile), reduction = (tap, input channel) in steps of 32. A lane holds A[pixel l%16][k
+// 8*(l/16)..+7], B[k 8*(l/16)..+7][channel l%16] and receives D[pixel 4*(l/16)+i][channel
+// l%16]. Input channels of a tap are contiguous in NHWC, so an A operand is one 16-byte load
+// for 8 or more channels (two 8-byte loads, one per tap, for 4; zero outside the image).
+// The weight gradient is a GEMM too: rows = (tap, input channel), columns = output channels,
+// reduction = pixels in steps of 32 (8 gathered pixels per lane).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +21,8 @@
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8s __attribute__((ext_vector_type(8)));    // bf16 bits, as loaded
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));    // MFMA operand type
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -30,6 +35,7 @@ __device__ __forceinline__ float bf2f(uint16_t h) {
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return !(h & 0x8000u) && h != 0; }
 
 constexpr int r16(int v) { return (v + 15) / 16 * 16; }
+constexpr int r32(int v) { return (v + 31) / 32 * 32; }
 constexpr int r4(int v) { return (v + 3) / 4 * 4; }
 
 // ---------------------------------------------------------------------------------------
@@ -80,7 +86,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x, in
                                               const uint16_t* __restrict__ mask, int mstride,
                                               void* __restrict__ y, int ystride, int yf32) {
   constexpr int KREAL = 9 * CIN;
-  constexpr int KPAD = r16(KREAL);
+  constexpr int KPAD = r32(KREAL);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long M = (long)N * H * W;
   const long mbase = ((long)blockIdx.x * 4 + wave) * 16;
@@ -90,25 +96,41 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x, in
   const long t = pm / W;
   const int py = (int)(t % H);
   const long pn = t / H;
-  const int kq = (lane >> 4) * 4;
+  const int kq = (lane >> 4) * 4;  // output rows 4*(l/16) .. +3
+  const int k8 = (lane >> 4) * 8;  // reduction slice of this lane
+  // 4 channels of tap `tap` from channel c of this lane's pixel (zero outside the image or K)
+  auto tap4 = [&](int tap, int c) -> bf16x4 {
+    bf16x4 v = {0, 0, 0, 0};
+    if (tap < 9) {
+      const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = *(const bf16x4*)(x + ((pn * H + yy) * W + xx) * CIN + c);
+    }
+    return v;
+  };
   f32x4 acc[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-  for (int k0 = 0; k0 < KPAD; k0 += 16) {
-    const int k = k0 + kq;
-    bf16x4 a = {0, 0, 0, 0};
-    if (k < KREAL) {
+  for (int k0 = 0; k0 < KPAD; k0 += 32) {
+    const int k = k0 + k8;
+    bf16x8s a = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (CIN % 8 == 0) {  // the 8 channels c .. c+7 of one tap
       const int tap = k / CIN, c = k % CIN;
-      const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-        a = *(const bf16x4*)(x + ((pn * H + yy) * W + xx) * CIN + c);
+      if (tap < 9) {
+        const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          a = *(const bf16x8s*)(x + ((pn * H + yy) * W + xx) * CIN + c);
+      }
+    } else {  // CIN == 4: taps k/4 and k/4 + 1
+      const bf16x4 lo = tap4(k / 4, 0), hi = tap4(k / 4 + 1, 0);
+      a = bf16x8s{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
+    const bf16x8 av = __builtin_bit_cast(bf16x8, a);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + (lane & 15);
-      const bf16x4 b = *(const bf16x4*)(wp + (size_t)n * KPAD + k);
-      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+      const bf16x8 b = __builtin_bit_cast(bf16x8, *(const bf16x8s*)(wp + (size_t)n * KPAD + k));
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[nt], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -150,20 +172,20 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ x,
   const long M = (long)N * H * W;
   const long p_begin = (long)blockIdx.x * chunk;
   const long p_end = std::min(p_begin + chunk, M);
-  const int kq = (lane >> 4) * 4;
+  const int kq = (lane >> 4) * 4;  // output rows 4*(l/16) .. +3
+  const int k8 = (lane >> 4) * 8;  // this lane's 8 pixels of a 32-pixel reduction step
   f32x4 acc[MTW][NT];
 #pragma unroll
   for (int j = 0; j < MTW; ++j)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[j][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (long p0 = p_begin; p0 < p_end; p0 += 16) {
-    // this lane's 4 pixels of the reduction step
-    int qx[4], qy[4];
-    long qn[4];
-    bool qv[4];
+  for (long p0 = p_begin; p0 < p_end; p0 += 32) {
+    int qx[8], qy[8];
+    long qn[8];
+    bool qv[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long p = p0 + kq + i;
+    for (int i = 0; i < 8; ++i) {
+      const long p = p0 + k8 + i;
       qv[i] = p < p_end;
       const long pc = qv[i] ? p : p_begin;
       qx[i] = (int)(pc % W);
@@ -171,33 +193,35 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ x,
       qy[i] = (int)(t % H);
       qn[i] = t / H;
     }
-    bf16x4 b[NT];
+    bf16x8 b[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + (lane & 15);
+      bf16x8s v;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        b[nt][i] = (qv[i] && n < cout) ? (short)dz[(p0 + kq + i) * dzs + n] : (short)0;
+      for (int i = 0; i < 8; ++i) v[i] = (qv[i] && n < cout) ? (short)dz[(p0 + k8 + i) * dzs + n] : (short)0;
+      b[nt] = __builtin_bit_cast(bf16x8, v);
     }
 #pragma unroll
     for (int j = 0; j < MTW; ++j) {
       const int mt = wave + 4 * j;
       if (mt >= MT) break;
       const int m = mt * 16 + (lane & 15);
-      bf16x4 a = {0, 0, 0, 0};
+      bf16x8s a = {0, 0, 0, 0, 0, 0, 0, 0};
       if (m < KREAL) {
         const int tap = m / CIN, c = m % CIN;
         const int oy = tap / 3 - 1, ox = tap % 3 - 1;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 8; ++i) {
           const int yy = qy[i] + oy, xx = qx[i] + ox;
           if (qv[i] && yy >= 0 && yy < H && xx >= 0 && xx < W)
             a[i] = (short)x[((qn[i] * H + yy) * W + xx) * CIN + c];
         }
       }
+      const bf16x8 av = __builtin_bit_cast(bf16x8, a);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
-        acc[j][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nt], acc[j][nt], 0, 0, 0);
+        acc[j][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[nt], acc[j][nt], 0, 0, 0);
     }
   }
   float* dst = part + (size_t)blockIdx.x * (MT * 16) * (NT * 16);
@@ -250,8 +274,8 @@ __global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ par
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, int cin, int cout,
                                               uint16_t* __restrict__ wf, uint16_t* __restrict__ wb) {
-  const int kf = r16(9 * cin), nf = r16(cout);
-  const int c4 = r4(cout), kb = r16(9 * c4), nb = r16(cin);
+  const int kf = r32(9 * cin), nf = r16(cout);
+  const int c4 = r4(cout), kb = r32(9 * c4), nb = r16(cin);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (wf && i < nf * kf) {
     const int n = i / kf, k = i % kf;
@@ -369,11 +393,11 @@ void lb_features(const uint8_t* part, long long pstride, int capP, int P, int D,
 extern "C" {
 
 size_t mpv_lb_packed_elems(int32_t cin, int32_t cout) {
-  return (size_t)r16(cout) * r16(9 * cin);
+  return (size_t)r16(cout) * r32(9 * cin);
 }
 
 size_t mpv_lb_packed_bwd_elems(int32_t cin, int32_t cout) {
-  return (size_t)r16(cin) * r16(9 * r4(cout));
+  return (size_t)r16(cin) * r32(9 * r4(cout));
 }
 
 static bool lb_shape_ok(int cin, int cout) {

@@ -398,10 +398,10 @@ class BatchedGpuExecutor:
     each frame shape the rigs deliver (device inputs, outputs and workspace regions of one
     mpv_batch over all of them). The frames admitted in one scheduler step are uploaded on an
     upload stream and matched by one mpv_batch_run_items call (every stage one launch over
-    those frames) on the compute stream, which waits for the uploads; downloads follow on the
-    compute stream and every frame of the step completes on the step's event. Uploads of the
-    next step overlap the current step's kernels. Each frame's result equals mpv_pyramid of
-    that frame alone."""
+    those frames) on the compute stream, which waits for the uploads; the downloads run on a
+    download stream behind the step's kernels and every frame of the step completes on the
+    step's event. Uploads of the next step and downloads of the previous one overlap the
+    current step's kernels. Each frame's result equals mpv_pyramid of that frame alone."""
 
     def __init__(self, specs, per_spec: int = 4, levels: int = 3, radius: int = 4, num_paths: int = 8,
                  device="cuda", sched=None):
@@ -413,6 +413,7 @@ class BatchedGpuExecutor:
         self.levels, self.radius, self.num_paths = levels, radius, num_paths
         self.upload = torch.cuda.Stream(device=self.device)
         self.compute = torch.cuda.Stream(device=self.device)
+        self.download = torch.cuda.Stream(device=self.device)
         uniq = []
         for sp in specs:
             if sp not in uniq and self._valid(sp):
@@ -486,10 +487,14 @@ class BatchedGpuExecutor:
             with torch.cuda.stream(self.compute):
                 self.compute.wait_event(up)
                 self.batch.run_items([s.idx for s in run])
+                matched = torch.cuda.Event()
+                matched.record(self.compute)
+            with torch.cuda.stream(self.download):
+                self.download.wait_event(matched)
                 for slot in run:
                     slot.host_out.copy_(self.batch.disp[slot.idx], non_blocking=True)
                 ev = torch.cuda.Event()
-                ev.record(self.compute)
+                ev.record(self.download)
             for slot in run:
                 slot.event = ev
         return tickets
@@ -504,6 +509,7 @@ class BatchedGpuExecutor:
 
     def close(self):
         self.compute.synchronize()
+        self.download.synchronize()
         self.batch.close()
 
 
