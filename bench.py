@@ -490,7 +490,7 @@ def serve_bench(seconds, per_rig=8, saturate=32):
     from paper_2001_09678_amd import serve
     specs = serve.rig_specs(8, 5)
     frames = serve.rig_frames(specs, per_rig, pinned=True)
-    budget = 32 << 30
+    budget = 16 << 30
 
     def make(rid, rig, seq, t):
         l, r = frames[rig][seq % per_rig]
@@ -511,8 +511,8 @@ def serve_bench(seconds, per_rig=8, saturate=32):
     out = {"rigs": [[sp.width, sp.height, sp.num_disp] for sp in specs], "hbm_budget_bytes": budget}
     for name in ("batched", "streams"):
         if name == "batched":
-            ex = serve.BatchedGpuExecutor(specs, per_spec=16)
-            cap = dict(max_inflight=96, max_batch=32)
+            ex = serve.BatchedGpuExecutor(specs, per_spec=8)
+            cap = dict(max_inflight=48, max_batch=16)
         else:
             ex = serve.GpuExecutor(streams=2)
             cap = dict(max_inflight=32, max_batch=8)

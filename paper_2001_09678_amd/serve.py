@@ -394,8 +394,8 @@ class _ArenaSlot:
 
 
 class BatchedGpuExecutor:
-    """Continuous batching through the batched kernels: a fixed arena of `per_spec` slots for
-    each frame shape the rigs deliver (device inputs, outputs and workspace regions of one
+    """Continuous batching through the batched kernels: a fixed arena of `per_spec` slots per
+    rig for each frame shape the rigs deliver (device inputs, outputs and workspace regions of one
     mpv_batch over all of them). The frames admitted in one scheduler step are uploaded on an
     upload stream and matched by one mpv_batch_run_items call (every stage one launch over
     those frames) on the compute stream, which waits for the uploads; the downloads run on a
@@ -422,7 +422,9 @@ class BatchedGpuExecutor:
         pairs = []
         for sp in uniq:
             self.free_slots[sp] = []
-            for _ in range(per_spec):
+            # per_spec slots for every rig delivering this shape, so that rigs sharing a shape
+            # do not block the queue's head on each other's slots
+            for _ in range(per_spec * sum(1 for x in specs if x == sp)):
                 L = torch.zeros((sp.height, sp.width), dtype=torch.uint8, device=self.device)
                 R = torch.zeros_like(L)
                 host = torch.empty((sp.height, sp.width), dtype=torch.int16, pin_memory=True)
@@ -434,7 +436,7 @@ class BatchedGpuExecutor:
         with torch.cuda.stream(self.compute):
             self.batch = mpv.Batch(pairs, params, levels, radius, sched=sched, device=self.device)
         self.arena_bytes = int(self.batch.workspace.numel()) + sum(
-            3 * sp.width * sp.height for sp in uniq) * per_spec
+            3 * s.spec.width * s.spec.height for s in self.slots)
         self._bytes = {}
 
     def _valid(self, spec) -> bool:
