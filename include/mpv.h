@@ -183,9 +183,17 @@ typedef struct {
     int32_t waves_per_block; /* scan blocks hold 1, 2 or 4 independent waves */
     int32_t full_lanes;      /* full-range scans: lanes per line (16, 32, 64) if the range fits
                                 2 packed pairs per lane, else the default layout */
-    int32_t band_lanes;      /* banded scans: lanes per line (16, 32, 64) if the band fits */
+    int32_t band_lanes;      /* banded scans: lanes per line (16, 32, 64) if the band fits, or
+                                MPV_BAND_LANES_LINE */
     int32_t order;           /* batched scans: 0 = pair by pair, 1 = longest lines first */
 } mpv_schedule;
+
+/* mpv_schedule.band_lanes: one scan line per lane for the directions that cross image rows
+ * (vertical and diagonal; a wave walks 64 neighbouring lines row by row), 16-lane groups for
+ * the horizontal ones, in one launch. Taken by the pyramid levels and batches whose bands hold
+ * 5 or 9 disparities with tau_eff = min(tau, D-1) of 1, 2 or 4, for the census data term, the
+ * sum of the paths and constant weights; every other level runs as with band_lanes = 0. */
+#define MPV_BAND_LANES_LINE 1
 
 /* How a finer pyramid level's search band is centred (mpv_pyramid_params.propagation).
  * MPV_PROP_NEAREST: every pixel on twice its parent's raw winner.

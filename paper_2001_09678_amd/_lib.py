@@ -14,6 +14,7 @@ MPV_MERGE_SUM, MPV_MERGE_LAYERED, MPV_MERGE_LAYERED_OCC = 0, 1, 2
 MPV_PROP_NEAREST, MPV_PROP_PAPER = 0, 1
 MPV_DATA_CENSUS, MPV_DATA_SSIM = 0, 1
 MPV_MAX_BLOCK = 32
+MPV_BAND_LANES_LINE = 1
 MPV_MAX_LEVELS = 4
 MPV_MAX_DISP = 256
 MPV_MAX_WIDTH = 4096

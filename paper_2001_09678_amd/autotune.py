@@ -50,8 +50,11 @@ def candidates(batched: bool = False):
     """Every schedule the tuner tries (all valid for any workload: a layout that does not
     fit a range falls back to the default layout inside the library)."""
     orders = (0, 1) if batched else (0,)
+    # one line per lane pays off only with many frames in flight (a lone frame's lines are
+    # long serial chains), so only batches try it
+    bands = (0, 32, mpv.Schedule.LINE) if batched else (0, 32)
     out = []
-    for wpb, fl, bl, order in itertools.product((1, 2, 4), (0, 32), (0, 32), orders):
+    for wpb, fl, bl, order in itertools.product((1, 2, 4), (0, 32), bands, orders):
         out.append(mpv.Schedule(waves_per_block=wpb, full_lanes=fl, band_lanes=bl, order=order))
     return out
 

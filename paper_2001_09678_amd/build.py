@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -38,13 +39,34 @@ def _obj(src: str) -> str:
     return os.path.join(OBJ, os.path.basename(src) + ".o")
 
 
+_INCLUDE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def _deps(path: str, seen: set | None = None) -> set:
+    """The file and every local header it includes, transitively (quoted includes resolved
+    beside the including file, then in include/)."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        text = f.read()
+    for name in _INCLUDE.findall(text):
+        for d in (os.path.dirname(path), os.path.join(os.path.dirname(HERE), "include")):
+            cand = os.path.join(d, name)
+            if os.path.exists(cand):
+                _deps(cand, seen)
+                break
+    return seen
+
+
 def _stale(src: str) -> bool:
-    """The object is missing or older than its source or any shared header."""
+    """The object is missing or older than its source or a header it includes."""
     obj = _obj(src)
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    return any(os.path.getmtime(d) > t for d in [src, *HEADERS])
+    return any(os.path.getmtime(d) > t for d in _deps(src))
 
 
 def _compile(src: str) -> tuple[str, str]:

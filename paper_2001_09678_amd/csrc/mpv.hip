@@ -64,7 +64,8 @@ mpv_status check_sched(const mpv_schedule& s) {
   const bool wpb = s.waves_per_block == 0 || s.waves_per_block == 1 || s.waves_per_block == 2 ||
                    s.waves_per_block == 4;
   const bool fl = s.full_lanes == 0 || s.full_lanes == 16 || s.full_lanes == 32 || s.full_lanes == 64;
-  const bool bl = s.band_lanes == 0 || s.band_lanes == 16 || s.band_lanes == 32 || s.band_lanes == 64;
+  const bool bl = s.band_lanes == 0 || s.band_lanes == MPV_BAND_LANES_LINE || s.band_lanes == 16 ||
+                  s.band_lanes == 32 || s.band_lanes == 64;
   return (wpb && fl && bl && (s.order == 0 || s.order == 1)) ? MPV_OK : MPV_ERR_INVALID_ARG;
 }
 
@@ -135,11 +136,16 @@ struct ScanChoice {
   int capP;  // partial slots per pixel
   bool absolute;
   bool masked;  // full-range kernel with band masks
+  // one line per lane for the directions with dy != 0 where the scan source allows it
+  // (census, sum of the paths, constant weights); 16-lane groups otherwise
+  bool line;
 };
 ScanChoice choose_scan(int D, const mpv_band* band, int tau, const mpv_schedule& sc) {
   const int te = tau_eff(tau, D);
   if (band && band->lo) {
-    const int lpl = band_lanes(band->cap, te, sc.band_lanes);
+    if (sc.band_lanes == MPV_BAND_LANES_LINE && !band->len && mpvl::band_line_ok(band->cap, te))
+      return {true, 16, 1, 16, false, false, true};
+    const int lpl = band_lanes(band->cap, te, sc.band_lanes == MPV_BAND_LANES_LINE ? 0 : sc.band_lanes);
     if (lpl) return {true, lpl, 1, lpl, false, false};
     FullLayout f = full_layout(D, sc.full_lanes);
     return {false, f.LPL, f.K, f.dpad(), true, true};
@@ -347,7 +353,25 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
       int dirs[8];
       for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
       plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
-      if (fuse && !ssim && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
+      // one line per lane: horizontal directions in 16-lane groups (descriptor hg, partial
+      // volumes first), then the others one line per lane (descriptor ln)
+      ScanArgs hg = a, ln = a;
+      int nh = 0, nv = 0;
+      if (lw.sc.line && data == SRC_CENSUS && !grad) {
+        int hd[8], vd[8];
+        for (int i = 0; i < p->num_paths; ++i) {
+          if (kDY[i] == 0) hd[nh++] = i;
+          else vd[nv++] = i;
+        }
+        plan_dirs(hg, hd, nh, lw.sc.LPL);
+        plan_dirs(ln, vd, nv, 1);
+        ln.line_lanes = 1;
+        ln.dir_base = nh;
+      }
+      if (nv) {
+        launch_scan(hg, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
+        mpvl::scan_lane(ln, a.cap, a.tau, wpb_of(sched), s);
+      } else if (fuse && !ssim && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
         mpvl::scan_full_cen(a, SRC_CENSUS | grad, *fuse, cen0, ncen, lw.sc.LPL, lw.sc.K, wpb_of(sched), s);
       else
         launch_scan(a, lw.sc, data | grad, OUT_PART, sched, s);
@@ -508,9 +532,16 @@ struct mpv_batch_s {
     int LPL, K, tau, stride;
     bool masked;
     int src;  // scans: SRC_CENSUS, or a layered merge's SRC_CENSUS_OCC / SRC_MERGE
+    bool line;  // banded scans with one line per lane (bands of cap disparities)
+    int cap;
+    bool beside;  // runs on the auxiliary stream beside the next launch (joined after it)
   };
   std::vector<Launch> launches;  // execution order
   std::vector<Launch> sub_launches;  // launches of the last mpv_batch_run_items
+  // a level's lane-group scan runs beside its one-line-per-lane scan: the two kernels have
+  // different register budgets and fill the machine together
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -620,22 +651,25 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       bool band;
       int LPL, K, tau;
       bool masked;
+      int line_cap;  // > 0: one line per lane for the directions with dy != 0, bands of this cap
       bool operator==(const Key& o) const {
-        return band == o.band && LPL == o.LPL && K == o.K && tau == o.tau && masked == o.masked;
+        return band == o.band && LPL == o.LPL && K == o.K && tau == o.tau && masked == o.masked &&
+               line_cap == o.line_cap;
       }
     };
+    const bool layered = b.p.base.merge != MPV_MERGE_SUM;
+    const int grad = b.p.base.grad_sigma > 0 ? SRC_GRAD : 0;
     auto key_of = [&](int i) {
       const ScanChoice& c = lws[i].sc;
-      return Key{c.banded_kernel, c.LPL, c.K, sargs[i].tau, c.masked};
+      const bool line = c.line && !layered && !grad;
+      return Key{c.banded_kernel, c.LPL, c.K, sargs[i].tau, c.masked, line ? sargs[i].cap : 0};
     };
     std::vector<Key> keys;
     for (int i = 0; i < n; ++i)
       if (std::find(keys.begin(), keys.end(), key_of(i)) == keys.end()) keys.push_back(key_of(i));
     // sum: one launch per variant with every direction of every pair; layered merge: the
     // layers in turn, each one launch per variant with its two directions of every pair
-    const bool layered = b.p.base.merge != MPV_MERGE_SUM;
     const int nstage = layered ? b.p.base.num_paths / 2 : 1;
-    const int grad = b.p.base.grad_sigma > 0 ? SRC_GRAD : 0;
     for (int stage = 0; stage < nstage; ++stage)
     for (const Key& k : keys) {
       struct Item {
@@ -651,35 +685,52 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
           ScanArgs a = sargs[i];
           if (layered) src = layered_layer(&b.p.base, a, stage);
           a.dir_base = r;
-          plan_dirs(a, &r, 1, k.LPL);
+          if (k.line_cap && kDY[r] != 0) {
+            plan_dirs(a, &r, 1, 1);
+            a.line_lanes = 1;
+          } else {
+            plan_dirs(a, &r, 1, k.LPL);
+          }
           items.push_back({a, line_len_host(r, a.W, a.H)});
         }
       }
       if (sc.order == 1)  // longest lines first: the last waves to start are the short ones
         std::stable_sort(items.begin(), items.end(),
                          [](const Item& x, const Item& y) { return x.len > y.len; });
-      std::vector<ScanArgs> d;
-      std::vector<int> first;
-      int waves = 0;
-      for (auto& it : items) {
-        d.push_back(it.a);
+      // one launch per layout: lane groups, then (line_cap) the one-line-per-lane descriptors
+      for (int lines = 0; lines < (k.line_cap ? 2 : 1); ++lines) {
+        std::vector<ScanArgs> d;
+        std::vector<int> first;
+        int waves = 0;
+        for (auto& it : items) {
+          if (it.a.line_lanes != lines) continue;
+          d.push_back(it.a);
+          first.push_back(waves);
+          waves += it.a.gprefix[1];
+        }
+        if (d.empty()) continue;
         first.push_back(waves);
-        waves += it.a.gprefix[1];
+        mpv_batch_s::Launch ln{};
+        ln.kind = k.band ? mpv_batch_s::SCAN_BAND : mpv_batch_s::SCAN_FULL;
+        ln.level = l;
+        ln.desc_off = tb.put(d);
+        ln.first_off = tb.put(first);
+        ln.nseg = (int)d.size();
+        ln.units = waves;
+        ln.LPL = k.LPL;
+        ln.K = k.K;
+        ln.tau = k.tau;
+        ln.masked = k.masked;
+        ln.src = src | grad;
+        ln.line = lines == 1;
+        ln.cap = k.line_cap;
+        b.launches.push_back(ln);
       }
-      first.push_back(waves);
-      mpv_batch_s::Launch ln{};
-      ln.kind = k.band ? mpv_batch_s::SCAN_BAND : mpv_batch_s::SCAN_FULL;
-      ln.level = l;
-      ln.desc_off = tb.put(d);
-      ln.first_off = tb.put(first);
-      ln.nseg = (int)d.size();
-      ln.units = waves;
-      ln.LPL = k.LPL;
-      ln.K = k.K;
-      ln.tau = k.tau;
-      ln.masked = k.masked;
-      ln.src = src | grad;
-      b.launches.push_back(ln);
+      // both layouts present: the lane-group launch runs beside the line launch after it
+      const size_t nl = b.launches.size();
+      if (k.line_cap && nl >= 2 && b.launches[nl - 1].line && !b.launches[nl - 2].line &&
+          b.launches[nl - 2].kind == mpv_batch_s::SCAN_BAND && b.launches[nl - 2].level == l)
+        b.launches[nl - 2].beside = true;
     }
     // reduce: pairs grouped by partial stride
     std::vector<int> strides;
@@ -1066,6 +1117,14 @@ mpv_status mpv_batch_bind(mpv_batch b, void* workspace, size_t bytes, hipStream_
   TableBuilder tb;
   plan_batch(*b, b->ws, tb);
   if (align_up(tb.bytes.size()) > b->table_bytes) return MPV_ERR_WORKSPACE;
+  const bool side = std::any_of(b->launches.begin(), b->launches.end(),
+                                [](const mpv_batch_s::Launch& x) { return x.beside; });
+  if (side && !b->aux) {  // without them the launches run one after the other on the stream
+    if (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming) != hipSuccess)
+      return MPV_ERR_DEVICE;
+  }
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
@@ -1091,6 +1150,7 @@ mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& lau
   // layered merge) are bracketed together by the timing hook
   std::optional<HookScope> hs;
   int hs_stage = -1, hs_level = -1;
+  bool join = false;  // the auxiliary stream's last launch is joined after this one
   for (const auto& ln : launches) {
     const void* desc = tables + ln.desc_off;
     const int* first = (const int*)(tables + ln.first_off);
@@ -1103,6 +1163,12 @@ mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& lau
       hs.emplace(stage, ln.level, s);
       hs_stage = stage;
       hs_level = ln.level;
+    }
+    hipStream_t s_main = s;
+    if (ln.beside && b->aux) {  // fork: the auxiliary stream starts after everything before
+      if (hipEventRecord(b->fork_ev, s) != hipSuccess || hipStreamWaitEvent(b->aux, b->fork_ev, 0) != hipSuccess)
+        return MPV_ERR_DEVICE;
+      s = b->aux;
     }
     switch (ln.kind) {
       case mpv_batch_s::DOWN: {
@@ -1126,7 +1192,9 @@ mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& lau
         break;
       }
       case mpv_batch_s::SCAN_BAND: {
-        if (src_grad(ln.src))
+        if (ln.line)
+          mpvl::scan_lane_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.cap, ln.tau, wpb, s);
+        else if (src_grad(ln.src))
           mpvl::scan_band_batch_grad({(const ScanArgs*)desc, first, ln.nseg}, ln.src, ln.units, ln.LPL,
                                      ln.tau, wpb, s);
         else if (ln.src == SRC_CENSUS)
@@ -1142,7 +1210,16 @@ mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& lau
         break;
       }
     }
+    if (s != s_main) {  // launched beside: joined after the next launch
+      s = s_main;
+      if (hipEventRecord(b->join_ev, b->aux) != hipSuccess) return MPV_ERR_DEVICE;
+      join = true;
+    } else if (join) {
+      if (hipStreamWaitEvent(s, b->join_ev, 0) != hipSuccess) return MPV_ERR_DEVICE;
+      join = false;
+    }
   }
+  if (join && hipStreamWaitEvent(s, b->join_ev, 0) != hipSuccess) return MPV_ERR_DEVICE;
   return launched();
 }
 }  // namespace
@@ -1215,6 +1292,12 @@ mpv_status mpv_batch_run_graph(mpv_batch b, hipStream_t s) {
 
 void mpv_batch_destroy(mpv_batch b) {
   if (!b) return;
+  if (b->aux) {
+    (void)hipStreamSynchronize(b->aux);
+    (void)hipStreamDestroy(b->aux);
+  }
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  if (b->join_ev) (void)hipEventDestroy(b->join_ev);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->stage) {

@@ -50,6 +50,9 @@ struct ScanArgs {
   // SRC_GRAD: the left image of the level ([H][ipitch]) and sigma >= 1
   const uint8_t* img;
   int ipitch, sigma;
+  // 1: one line per lane (directions with dy != 0, census source, fixed-length bands);
+  // gprefix then counts 64 lines per wave
+  int line_lanes;
 };
 
 // Segment table of a batched launch: global wave u belongs to descriptor s with

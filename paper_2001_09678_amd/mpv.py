@@ -165,7 +165,10 @@ def match(left, right, params: MPVParams, band: Band | None = None, workspace=No
 class Schedule:
     """Launch schedule (all give bit-identical results): waves per scan block (1/2/4),
     lanes per line of full-range scans (0 default, 16/32/64), lanes per line of banded
-    scans (0 default, 16/32/64), batched scan order (0 pair by pair, 1 longest first)."""
+    scans (0 default, 16/32/64, or 1 = ``LINE``: one line per lane for the vertical and
+    diagonal directions where the level allows it), batched scan order (0 pair by pair,
+    1 longest first)."""
+    LINE = _L.MPV_BAND_LANES_LINE
     waves_per_block: int = 0
     full_lanes: int = 0
     band_lanes: int = 0
