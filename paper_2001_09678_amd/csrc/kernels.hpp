@@ -907,9 +907,9 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
         // pst is wave-uniform for 64-lane groups: scalar offset, constant lane offset
         const uint32_t vo = LPL == 64 ? 2 * l * K : pst + 2 * l * K, so = LPL == 64 ? pst : 0u;
         if constexpr (K == 1)
-          __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, rpart, (int)vo, (int)so, 0);
+          __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, rpart, (int)vo, (int)so, kPartStorePolicy);
         else
-          __builtin_amdgcn_raw_buffer_store_b32(v, rpart, (int)vo, (int)so, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(v, rpart, (int)vo, (int)so, kPartStorePolicy);
       } else {
         // past the line's end the store goes to a sink behind the last direction's volume
         uint8_t* dst = t < la.n ? part + la.pix(t) * (uint32_t)a.capP + 2 * l * K : sinkp + 4 * lane;

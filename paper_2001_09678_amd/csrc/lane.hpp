@@ -276,6 +276,14 @@ __device__ __forceinline__ int wave_max_s(int v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Cache policy of the partial-volume stores whose wave writes whole cache lines at a time
+// (full-range scans, one line per lane): non-temporal. The volumes are written once, read
+// once by the reduce after the whole scan, and (batched) far larger than the caches;
+// streaming them past the caches leaves room for the census words that the scans reuse.
+// The lane-group banded scan writes 16-byte pieces of many lines per step, which the L2 has
+// to merge: those stores keep the default policy (measured: non-temporal is slower there).
+constexpr int kPartStorePolicy = 2;  // nt
+
 // Buffer resource over `p` (raw addressing, no stride; gfx9 data-format word): loads and
 // stores then take a scalar offset plus a 32-bit lane offset, with no 64-bit address math.
 typedef __amdgpu_buffer_rsrc_t rsrc_t;

@@ -219,11 +219,11 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
     }
     if constexpr (FAST) {
       const uint32_t so = (uint32_t)(yat(g) * W + u0 + dx * g) << 4;
-      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)(vpart + so), 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)(vpart + so), 0, kPartStorePolicy);
     } else if (live) {
       int p, c, x;
       pix_at(g, p, c, x);
-      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)((uint32_t)p << 4), 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)((uint32_t)p << 4), 0, kPartStorePolicy);
     }
     lo_prev = b0;
   };
