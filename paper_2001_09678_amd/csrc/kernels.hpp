@@ -962,7 +962,7 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
 // anywhere, so the envelope is built in the previous pixel's frame extended by tau-1
 // slots on each side, then lane j of the new pixel picks position j + lo(p) - lo(p-r).
 // VAR: per-pixel band lengths (otherwise every pixel has len = cap).
-template <int LPL, int SRC, int OUT, int TAU, bool VAR>
+template <int LPL, int SRC, int OUT, int TAU, bool VAR, bool STAGED = false>
 __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs& tab, int unit) {
   const int lane = lane_id();
   const int j = LPL == 64 ? lane : lane % LPL;
@@ -993,6 +993,16 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   uint8_t* const sinkp = a.part + (long long)a.npd * a.part_stride;  // 256 B behind the volumes
   const rsrc_t rpart = make_rsrc(part);
   const rsrc_t rcr = make_rsrc(a.cr);
+  // staged partial stores (STAGED: batched launches, where throughput counts; a lone
+  // frame's horizontal lines are its longest chains, and the flush would lengthen them): on
+  // lines whose consecutive pixels are consecutive in memory (horizontal), a fast chunk
+  // collects its 16 steps' bytes in LDS (16 x 16 per group), then lane j writes pixel
+  // t0 + j's 16 slots with one store: whole cache lines, one store instruction per chunk
+  // instead of one per step
+  __shared__ uint8_t stage_tile[4 * 64 * 16];
+  const bool hstage =
+      STAGED && LPL == 16 && OUT == OUT_PART && a.capP == 16 && (la.dp == 1 || la.dp == -1);
+  uint8_t* const tile = stage_tile + (threadIdx.x & ~15) * 16;  // this group's 16 x 16 bytes
 
   uint32_t ring[PREFETCH];  // right census of this lane's candidate
   uint32_t bw[PREFETCH];    // broadcast step words (left census | band start << 24)
@@ -1036,9 +1046,10 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   const uint32_t pstep = (uint32_t)(la.dp * a.capP);
 
   // One step; FAST as in the full-range scan (no clamps, no border test, no sink).
-  auto step = [&](auto kc, auto fc, const uint2& nxt, int t0, uint32_t pst, uint32_t cpf) {
+  auto step = [&](auto kc, auto fc, const uint2& nxt, int t0, uint32_t pst, uint32_t cpf, auto stc) {
     constexpr int k = decltype(kc)::value;
     constexpr bool FAST = decltype(fc)::value;
+    constexpr bool STAGE = decltype(stc)::value;
     constexpr int slot = k % PREFETCH;
     const int t = t0 + k;
     const uint32_t w = bw[slot];
@@ -1126,7 +1137,9 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     }
     if constexpr (OUT == OUT_PART) {
       const uint8_t v8 = (uint8_t)min(P, 255u);
-      if constexpr (FAST) {
+      if constexpr (FAST && STAGE) {
+        tile[k * 16 + j] = v8;
+      } else if constexpr (FAST) {
         const uint32_t vo = LPL == 64 ? (uint32_t)j : pst + j, so = LPL == 64 ? pst : 0u;
         __builtin_amdgcn_raw_buffer_store_b8(v8, rpart, (int)vo, (int)so, 0);
       } else {
@@ -1144,16 +1157,31 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     const int xa = la.x0 + t0 * la.dx, xb = xa + (CHUNK - 1) * la.dx;
     const bool fast = wave_all(t0 + CHUNK + PREFETCH <= la.n &&
                                (!src_census(SRC) || min(xa, xb) >= a.D - 1));
-    if (fast) {
+    if (fast && hstage) {
+      const uint32_t pst0 = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;
+      uint32_t pst = pst0;
+      uint32_t cpf = (uint32_t)(la.c0 + (t0 + PREFETCH) * la.dc);
+      static_for<CHUNK>([&](auto kc) {
+        step(kc, std::true_type{}, nxt, t0, pst, cpf, std::true_type{});
+        pst += pstep;
+        cpf += (uint32_t)la.dc;
+      });
+      // lane j of the group: pixel t0 + j's 16 slots
+      __builtin_amdgcn_wave_barrier();
+      const uint4 v = *(const uint4*)(tile + j * 16);
+      typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+      const u4v w = {v.x, v.y, v.z, v.w};  // offset in the vector register (see the line scans)
+      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)(pst0 + (uint32_t)j * pstep), 0, kPartStorePolicy);
+    } else if (fast) {
       uint32_t pst = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;
       uint32_t cpf = (uint32_t)(la.c0 + (t0 + PREFETCH) * la.dc);
       static_for<CHUNK>([&](auto kc) {
-        step(kc, std::true_type{}, nxt, t0, pst, cpf);
+        step(kc, std::true_type{}, nxt, t0, pst, cpf, std::false_type{});
         pst += pstep;
         cpf += (uint32_t)la.dc;
       });
     } else {
-      static_for<CHUNK>([&](auto kc) { step(kc, std::false_type{}, nxt, t0, 0u, 0u); });
+      static_for<CHUNK>([&](auto kc) { step(kc, std::false_type{}, nxt, t0, 0u, 0u, std::false_type{}); });
     }
     cur = nxt;
   }
@@ -1207,7 +1235,7 @@ __global__ __launch_bounds__(256) void k_scan_band_batch(Batch<ScanArgs> b) {
   if (u >= b.first[b.nseg]) return;
   const int s = batch_find(b.first, b.nseg, u);
   const ScanArgs a = b.desc[s];  // private copy, as above
-  scan_band_wave<LPL, SRC, OUT, TAU, VAR>(a, b.desc[s], u - b.first[s]);
+  scan_band_wave<LPL, SRC, OUT, TAU, VAR, true>(a, b.desc[s], u - b.first[s]);
 }
 
 // ---------------------------------------------------------------------------------------
