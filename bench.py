@@ -40,15 +40,17 @@ OPS_PER_NODE_PATH = 14
 FLOOR_B_PER_NODE = 2
 FLOOR_B_PER_PIXEL = 4
 
-# HBM traffic of the dominant kernel (the finest level's banded scan over all frames of a
-# step, one batched launch) per launch, from `rocprofv3 --pmc FETCH_SIZE` and
-# `--pmc WRITE_SIZE` runs of this script (see profiles/), each calibrated by the same counter
-# on a 1 GiB int32 negation kernel (1 GiB read, 1 GiB written). Valid only for the kernel
-# sources and frame count they were taken with (SHA-1 over the files below); reported as
-# null otherwise.
+# HBM traffic of the dominant unit (the finest level's banded scan stage over all frames of a
+# step: with one line per lane, the line kernel and, beside it on a second stream, the
+# lane-group kernel of the horizontal directions; otherwise one batched launch), summed over
+# its launches, from `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of this script
+# (see profiles/), each calibrated by the same counter on a 1 GiB int32 negation kernel
+# (1 GiB read, 1 GiB written). Valid only for the kernel sources and frame count they were
+# taken with (SHA-1 over the files below); reported as null otherwise.
 SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/csrc/lane.hpp",
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band_batch.hip",
-                "paper_2001_09678_amd/csrc/scan_launch.hpp"]
+                "paper_2001_09678_amd/csrc/scan_launch.hpp", "paper_2001_09678_amd/csrc/lines.hpp",
+                "paper_2001_09678_amd/csrc/kern_band_lines.hip"]
 SCAN_TRAFFIC = {"sources_sha1": "88e83067430356626e79a1156487cf71dad4b84a", "frames": 16,
                 "fetch_bytes": 3133623742, "write_bytes": 2004598409}
 
@@ -758,8 +760,13 @@ def main():
     if (SCAN_TRAFFIC["sources_sha1"] and SCAN_TRAFFIC["sources_sha1"] == scan_sources_sha1()
             and SCAN_TRAFFIC["frames"] == F):
         traffic = int(SCAN_TRAFFIC["fetch_bytes"] + SCAN_TRAFFIC["write_bytes"])
-    roof.update({"traffic": traffic, "kernel": "k_scan_band_batch<16,census,partial> (finest level, 8 directions, "
-                                                f"{F} frames per launch)",
+    if bsched.band_lanes == mpv.Schedule.LINE:
+        kname = (f"finest-level scan stage, {F} frames: k_scan_lane_batch<tau 4, cap 9> (vertical and diagonal "
+                 "directions, one line per lane) beside k_scan_band_batch<16,census,partial> (horizontal "
+                 "directions) on a second stream")
+    else:
+        kname = f"k_scan_band_batch<16,census,partial> (finest level, 8 directions, {F} frames per launch)"
+    roof.update({"traffic": traffic, "kernel": kname,
                  "kernel_ms": round(scan_avg, 4), "launches_timed": len(scan_list),
                  "units": f"{fine_nodes} evaluated nodes x {FLOOR_B_PER_NODE} B + {F * wf * hf} px x "
                           f"{FLOOR_B_PER_PIXEL} B",

@@ -1532,12 +1532,51 @@ __device__ __forceinline__ bool batch_pixel(const Batch<PixArgs>& b, const PixAr
 }
 
 #ifdef MPV_MISC_KERNELS
+// One 64 x CENSUS_TILE_ROWS census tile per block: the tile and its 2-pixel border
+// (coordinates clamped to the image, as the census clamps its neighbours) are read into LDS
+// once, then every thread takes one column of the tile, comparing each pixel with its 24
+// neighbours there. Tall tiles amortise the block's descriptor lookup.
 __global__ __launch_bounds__(256) void k_census_batch(Batch<PixArgs> b) {
-  const PixArgs* a;
-  int v, x, y;
-  if (!batch_pixel(b, a, v, x, y)) return;
-  ((uint32_t*)a->out[v])[(size_t)y * a->opitch + a->omargin + x] =
-      census_at(a->in[v], a->W, a->H, a->in_pitch[v], x, y);
+  constexpr int R = CENSUS_TILE_ROWS;
+  __shared__ uint8_t tile[R + 4][68];
+  const int u = blockIdx.x;
+  const int s = batch_find(b.first, b.nseg, u);
+  const PixArgs* a = &b.desc[s];
+  int t = u - b.first[s];
+  const int v = t >= a->tiles;
+  t -= v * a->tiles;
+  const int W = a->W, H = a->H;
+  const int x0 = (t % a->tiles_x) * 64, y0 = (t / a->tiles_x) * R;
+  const uint8_t* img = a->in[v];
+  const int pitch = a->in_pitch[v];
+  for (int i = threadIdx.x; i < (R + 4) * 68; i += 256) {
+    const int ty = i / 68, tx = i - ty * 68;
+    const int x = min(max(x0 + tx - 2, 0), W - 1), y = min(max(y0 + ty - 2, 0), H - 1);
+    tile[ty][tx] = img[(size_t)y * pitch + x];
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63;
+  const int x = x0 + tx;
+  if (x >= W) return;
+  uint32_t* const out = (uint32_t*)a->out[v] + a->omargin + x;
+#pragma unroll
+  for (int r = 0; r < R / 4; ++r) {
+    const int ty = (threadIdx.x >> 6) + 4 * r;
+    const int y = y0 + ty;
+    if (y >= H) break;
+    const int c = tile[ty + 2][tx + 2];
+    uint32_t val = 0;
+    int bit = 0;
+#pragma unroll
+    for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (dx == 0 && dy == 0) continue;
+        val |= (uint32_t)(tile[ty + 2 + dy][tx + 2 + dx] < c) << bit;
+        ++bit;
+      }
+    out[(size_t)y * a->opitch] = val;
+  }
 }
 #endif
 

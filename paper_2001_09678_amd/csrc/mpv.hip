@@ -573,9 +573,10 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
   auto add_pix = [&](mpv_batch_s::Kind kind, int level, std::vector<PixArgs>& d, int views) {
     std::vector<int> first;
     int blocks = 0;
+    const int rows = kind == mpv_batch_s::CENSUS ? mpvk::CENSUS_TILE_ROWS : 4;  // tile: 64 x rows pixels
     for (auto& a : d) {
       a.tiles_x = (a.W + 63) / 64;
-      a.tiles = a.tiles_x * ((a.H + 3) / 4);
+      a.tiles = a.tiles_x * ((a.H + rows - 1) / rows);
       first.push_back(blocks);
       blocks += a.tiles * views;
     }

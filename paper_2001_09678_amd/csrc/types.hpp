@@ -125,6 +125,7 @@ struct PropArgs {
 };
 
 constexpr int RED_MAXW = 4096;
+constexpr int CENSUS_TILE_ROWS = 16;  // batched census: 64 x 16 pixels per block
 constexpr int ROAD_MAX_HEIGHT = 4096;  // rows of a v-disparity image the road kernel holds in LDS
 
 }  // namespace mpvk
