@@ -188,11 +188,13 @@ typedef struct {
     int32_t order;           /* batched scans: 0 = pair by pair, 1 = longest lines first */
 } mpv_schedule;
 
-/* mpv_schedule.band_lanes: one scan line per lane for the directions that cross image rows
- * (vertical and diagonal; a wave walks 64 neighbouring lines row by row), 16-lane groups for
- * the horizontal ones, in one launch. Taken by the pyramid levels and batches whose bands hold
- * 5 or 9 disparities with tau_eff = min(tau, D-1) of 1, 2 or 4, for the census data term, the
- * sum of the paths and constant weights; every other level runs as with band_lanes = 0. */
+/* mpv_schedule.band_lanes of a batch (mpv_batch_create): one scan line per lane for the
+ * directions that cross image rows (vertical and diagonal; a wave walks 64 neighbouring lines
+ * row by row), with the horizontal directions' 16-lane groups running beside them on a second
+ * stream, and 12 partial slots per pixel. Taken by the levels whose bands hold 5 or 9
+ * disparities with tau_eff = min(tau, D-1) of 1, 2 or 4, for the census data term, the sum
+ * of the paths and constant weights; every other level, and every single-pair entry point
+ * (whose lone frame's lines would be long serial chains), runs as with band_lanes = 0. */
 #define MPV_BAND_LANES_LINE 1
 
 /* How a finer pyramid level's search band is centred (mpv_pyramid_params.propagation).

@@ -1,5 +1,4 @@
-// Banded scans with one line per lane for the directions that cross image rows: single-level
-// and batched launches.
+// Batched banded scans with one line per lane for the directions that cross image rows.
 #include "launch.hpp"
 #include "lines.hpp"
 
@@ -24,15 +23,7 @@ bool with_shape(int cap, int tau, F&& f) {
 }  // namespace
 
 bool band_line_ok(int cap, int tau) {
-  return with_shape(cap, tau, [](auto, auto) {}) && cap + 2 * (tau - 1) <= 16;
-}
-
-void scan_lane(const ScanArgs& a, int cap, int tau, int wpb, hipStream_t s) {
-  const int units = a.gprefix[a.ndir];
-  with_shape(cap, tau, [&](auto cc, auto tc) {
-    constexpr int CAP = decltype(cc)::value, TAU = decltype(tc)::value;
-    hipLaunchKernelGGL((k_scan_lane<TAU, CAP>), dim3((units + wpb - 1) / wpb), dim3(64 * wpb), 0, s, a);
-  });
+  return with_shape(cap, tau, [](auto, auto) {}) && cap + 2 * (tau - 1) <= 16 && cap <= 12;
 }
 
 void scan_lane_batch(const Batch<ScanArgs>& b, int units, int cap, int tau, int wpb, hipStream_t s) {

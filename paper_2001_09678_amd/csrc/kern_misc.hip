@@ -14,6 +14,10 @@ dim3 pix_grid(int W, int H, int views) {
 }  // namespace
 
 void reduce_part(const RedArgs& a, int need_lr, hipStream_t s) {
+  if (a.stride == 12) {
+    hipLaunchKernelGGL((k_reduce_part<1, 12>), dim3(a.H), dim3(256), 0, s, a, need_lr);
+    return;
+  }
   switch (a.stride / 16) {
     case 1: hipLaunchKernelGGL(k_reduce_part<1>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
     case 2: hipLaunchKernelGGL(k_reduce_part<2>, dim3(a.H), dim3(256), 0, s, a, need_lr); break;
@@ -24,6 +28,10 @@ void reduce_part(const RedArgs& a, int need_lr, hipStream_t s) {
 }
 
 void reduce_part_batch(const Batch<RedArgs>& b, int rows, int stride, hipStream_t s) {
+  if (stride == 12) {
+    hipLaunchKernelGGL((k_reduce_part_batch<1, 12>), dim3(rows), dim3(256), 0, s, b);
+    return;
+  }
   switch (stride / 16) {
     case 1: hipLaunchKernelGGL(k_reduce_part_batch<1>, dim3(rows), dim3(256), 0, s, b); break;
     case 2: hipLaunchKernelGGL(k_reduce_part_batch<2>, dim3(rows), dim3(256), 0, s, b); break;

@@ -1000,8 +1000,12 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   // t0 + j's 16 slots with one store: whole cache lines, one store instruction per chunk
   // instead of one per step
   __shared__ uint8_t stage_tile[4 * 64 * 16];
-  const bool hstage =
-      STAGED && LPL == 16 && OUT == OUT_PART && a.capP == 16 && (la.dp == 1 || la.dp == -1);
+  const bool hstage = STAGED && LPL == 16 && OUT == OUT_PART && (a.capP == 16 || a.capP == 12) &&
+                      (la.dp == 1 || la.dp == -1);
+  // lanes past the slot pitch keep their bytes (every band fits the first capP slots): the
+  // 12-slot layout of batched levels with one line per lane, whose lane groups hold only the
+  // horizontal lines (staged in fast chunks, so only the per-step stores check)
+  const bool slot_ok = j < a.capP;
   uint8_t* const tile = stage_tile + (threadIdx.x & ~15) * 16;  // this group's 16 x 16 bytes
 
   uint32_t ring[PREFETCH];  // right census of this lane's candidate
@@ -1143,7 +1147,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
         const uint32_t vo = LPL == 64 ? (uint32_t)j : pst + j, so = LPL == 64 ? pst : 0u;
         __builtin_amdgcn_raw_buffer_store_b8(v8, rpart, (int)vo, (int)so, 0);
       } else {
-        *(t < la.n ? part + la.pix(t) * (uint32_t)a.capP + j : sinkp + lane) = v8;
+        *(t < la.n && slot_ok ? part + la.pix(t) * (uint32_t)a.capP + j : sinkp + lane) = v8;
       }
     } else {
       if (t < la.n && j < bn) export_canonical<OUT>(a.agg, (size_t)la.pix(t) * a.cap + j, L + acc, a.first);
@@ -1166,12 +1170,20 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
         pst += pstep;
         cpf += (uint32_t)la.dc;
       });
-      // lane j of the group: pixel t0 + j's 16 slots
+      // lane j of the group: pixel t0 + j's capP slots (offset in the vector register: see
+      // the one-line-per-lane scans)
       __builtin_amdgcn_wave_barrier();
       const uint4 v = *(const uint4*)(tile + j * 16);
-      typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-      const u4v w = {v.x, v.y, v.z, v.w};  // offset in the vector register (see the line scans)
-      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)(pst0 + (uint32_t)j * pstep), 0, kPartStorePolicy);
+      const int vo = (int)(pst0 + (uint32_t)j * pstep);
+      if (a.capP == 16) {
+        typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+        const u4v w = {v.x, v.y, v.z, v.w};
+        __builtin_amdgcn_raw_buffer_store_b128(w, rpart, vo, 0, kPartStorePolicy);
+      } else {
+        typedef unsigned int u3v __attribute__((ext_vector_type(3)));
+        const u3v w = {v.x, v.y, v.z};
+        __builtin_amdgcn_raw_buffer_store_b96(w, rpart, vo, 0, kPartStorePolicy);
+      }
     } else if (fast) {
       uint32_t pst = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;
       uint32_t cpf = (uint32_t)(la.c0 + (t0 + PREFETCH) * la.dc);
@@ -1377,12 +1389,15 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
 }
 
 // Fused-path reduce over the P uint8 partial volumes (their sum, or for a layered merge
-// the smaller or the floor mean of the last layer's two): a lane owns 16 consecutive slots
-// of one pixel (one 16-byte load per partial), LPP = stride/16 lanes per pixel, 64/LPP
-// pixels per wave step. Sums fit 16 bits (P * 255), so two slots share a register.
-// need_lr = false (intermediate pyramid levels) writes the raw winner only.
-template <int LPP>
+// the smaller or the floor mean of the last layer's two): a lane owns SL = 16 consecutive
+// slots of one pixel (one 16-byte load per partial), LPP = stride/16 lanes per pixel, 64/LPP
+// pixels per wave step; or (stride 12, the compact layout of the one-line-per-lane scans)
+// SL = 12 slots, one lane per pixel. Sums fit 16 bits (P * 255), so two slots share a
+// register. need_lr = false (intermediate pyramid levels) writes the raw winner only.
+template <int LPP, int SL = 16>
 __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int need_lr) {
+  static_assert(SL == 16 || (SL == 12 && LPP == 1), "16-slot lanes, or one 12-slot lane per pixel");
+  constexpr int NQ = SL / 4;  // 32-bit words of slots per lane
   __shared__ uint32_t s_rkey[RED_MAXW];
   __shared__ int16_t s_dl[RED_MAXW];
   constexpr uint32_t NOK = 0xFFFFFFFFu;
@@ -1394,49 +1409,54 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
   const int lane = lane_id();
   const int wave = tid >> 6;
   const int jl = lane % LPP;
-  const int j0 = jl * 16;
+  const int j0 = jl * SL;
   constexpr int PPW = 64 / LPP;  // pixels per wave step
   const int xsteps = (a.W + nw * PPW - 1) / (nw * PPW);
   for (int it = 0; it < xsteps; ++it) {
     const int x = (it * nw + wave) * PPW + lane / LPP;
     const bool xin = x < a.W;
     const size_t p = (size_t)y * a.W + (xin ? x : a.W - 1);
-    // every direction's 16 slots are loaded before any is used (npart <= 8, uniform)
+    // every direction's slots are loaded before any is used (npart <= 8, uniform)
     const uint8_t* q0 = a.part + p * a.stride + j0;
-    uint4 wv[8];
+    uint32_t wv[8][NQ];
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-      wv[r] = r < a.npart ? *(const uint4*)(q0 + r * a.part_stride) : make_uint4(0u, 0u, 0u, 0u);
+    for (int r = 0; r < 8; ++r) {
+      if constexpr (SL == 16) {
+        const uint4 w = r < a.npart ? *(const uint4*)(q0 + r * a.part_stride) : make_uint4(0u, 0u, 0u, 0u);
+        wv[r][0] = w.x, wv[r][1] = w.y, wv[r][2] = w.z, wv[r][3] = w.w;
+      } else {
+        const uint3 w = r < a.npart ? *(const uint3*)(q0 + r * a.part_stride) : make_uint3(0u, 0u, 0u);
+        wv[r][0] = w.x, wv[r][1] = w.y, wv[r][2] = w.z;
+      }
+    }
     int b0, bn;
     band_at(a.lo, a.len, p, a.D, a.bcap, b0, bn);
     // s[2q]: slots 4q (lo), 4q+2 (hi); s[2q+1]: slots 4q+1 (lo), 4q+3 (hi)
-    uint32_t sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (a.merge == 1 + MERGE_MIN) {  // layered merge: the smaller of the two passes
-      const uint32_t wa[4] = {wv[0].x, wv[0].y, wv[0].z, wv[0].w};
-      const uint32_t wb[4] = {wv[1].x, wv[1].y, wv[1].z, wv[1].w};
+    uint32_t sm[2 * NQ];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        sm[2 * q] = pk_min(wa[q] & 0x00FF00FFu, wb[q] & 0x00FF00FFu);
-        sm[2 * q + 1] = pk_min((wa[q] >> 8) & 0x00FF00FFu, (wb[q] >> 8) & 0x00FF00FFu);
+    for (int i = 0; i < 2 * NQ; ++i) sm[i] = 0;
+    if (a.merge == 1 + MERGE_MIN) {  // layered merge: the smaller of the two passes
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        sm[2 * q] = pk_min(wv[0][q] & 0x00FF00FFu, wv[1][q] & 0x00FF00FFu);
+        sm[2 * q + 1] = pk_min((wv[0][q] >> 8) & 0x00FF00FFu, (wv[1][q] >> 8) & 0x00FF00FFu);
       }
     } else {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const uint4 w = wv[r];
-        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          sm[2 * q] += ws[q] & 0x00FF00FFu;
-          sm[2 * q + 1] += (ws[q] >> 8) & 0x00FF00FFu;
+        for (int q = 0; q < NQ; ++q) {
+          sm[2 * q] += wv[r][q] & 0x00FF00FFu;
+          sm[2 * q + 1] += (wv[r][q] >> 8) & 0x00FF00FFu;
         }
       }
       if (a.merge == 1 + MERGE_MEAN)  // layered merge: the mean of the two, rounded down
 #pragma unroll
-        for (int i = 0; i < 8; ++i) sm[i] = (sm[i] >> 1) & 0x7FFF7FFFu;
+        for (int i = 0; i < 2 * NQ; ++i) sm[i] = (sm[i] >> 1) & 0x7FFF7FFFu;
     }
-    uint32_t v[16];
+    uint32_t v[SL];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       v[4 * q + 0] = sm[2 * q] & 0xFFFFu;
       v[4 * q + 1] = sm[2 * q + 1] & 0xFFFFu;
       v[4 * q + 2] = sm[2 * q] >> 16;
@@ -1444,7 +1464,7 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
     }
     uint32_t best = NOK;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < SL; ++i) {
       const int jj = j0 + i;
       const bool ok = a.absolute ? (jj >= b0 && jj < b0 + bn) : jj < bn;
       best = min(best, ok ? (v[i] << 9) | (uint32_t)jj : NOK);
@@ -1467,7 +1487,7 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
       }
       if (need_lr) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < SL; ++i) {
           const int jj = j0 + i;
           const bool ok = a.absolute ? (jj >= b0 && jj < b0 + bn) : jj < bn;
           const int d = a.absolute ? jj : b0 + jj;
@@ -1496,18 +1516,18 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
 }
 
 // Blocks of 256 threads, or 1024 for pixels of 4 or more lanes (more loads in flight per row).
-template <int LPP>
+template <int LPP, int SL = 16>
 __global__ __launch_bounds__(1024) void k_reduce_part(RedArgs a, int need_lr) {
-  reduce_part_row<LPP>(a, blockIdx.x, need_lr);
+  reduce_part_row<LPP, SL>(a, blockIdx.x, need_lr);
 }
 
 // Batched: one block per image row of every pair; need_lr is per descriptor (a.lr_need).
-template <int LPP>
+template <int LPP, int SL = 16>
 __global__ __launch_bounds__(1024) void k_reduce_part_batch(Batch<RedArgs> b) {
   const int u = blockIdx.x;
   const int s = batch_find(b.first, b.nseg, u);
   const RedArgs a = b.desc[s];  // private copy: not re-read after every store
-  reduce_part_row<LPP>(a, u - b.first[s], a.need_lr);
+  reduce_part_row<LPP, SL>(a, u - b.first[s], a.need_lr);
 }
 
 

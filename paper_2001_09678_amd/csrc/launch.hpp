@@ -26,11 +26,9 @@ void scan_full_batch(const Batch<ScanArgs>& b, int units, int LPL, int K, int ta
 void scan_band(const ScanArgs& a, int LPL, int src, int out, bool var, int wpb, hipStream_t s);
 void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, int wpb, hipStream_t s);
 // One line per lane for the directions with dy != 0 (kern_band_lines.hip): band lengths and
-// reduced tau with kernels, then one descriptor and a batch of descriptors whose directions
-// all have dy != 0 (ScanArgs::line_lanes, gprefix counting 64 lines per wave). Both write
-// 16 partial slots per pixel.
+// reduced tau with kernels, then a batch of descriptors whose directions all have dy != 0
+// (ScanArgs::line_lanes, gprefix counting 64 lines per wave), 12 partial slots per pixel.
 bool band_line_ok(int cap, int tau);
-void scan_lane(const ScanArgs& a, int cap, int tau, int wpb, hipStream_t s);
 void scan_lane_batch(const Batch<ScanArgs>& b, int units, int cap, int tau, int wpb, hipStream_t s);
 // Cost-volume source with partial output (the fused SSIM path; kern_cost_src.hip).
 void scan_full_cost(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);

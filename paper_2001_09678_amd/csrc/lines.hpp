@@ -22,7 +22,10 @@ namespace mpvk {
 // extension hold lambda*tau. A lane's energies stay zero until its line starts, and the
 // line's first pixel reads them at offset 0: no transition term.
 // Needs fixed-length bands with lo in [0, D-CAP] (the pyramid's own bands) and
-// 24 + lambda*tau <= 255, so that every normalised energy is its own partial byte.
+// 24 + lambda*tau <= 255, so that every normalised energy is its own partial byte. Its
+// levels use 12 partial slots per pixel (capP = 12): 12-byte stores of consecutive pixels
+// (and 12-byte loads in the reduce) cover whole cache lines with a quarter fewer bytes than
+// the 16-slot pitch of the lane groups.
 // ---------------------------------------------------------------------------------------
 template <int CAP, int TAU>
 struct LaneRow {
@@ -37,6 +40,7 @@ struct LaneRow {
 __device__ __forceinline__ int wave_min_s(int v) { return -wave_max_s(-v); }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 
 template <int CAP, int TAU>
 __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs& tab, int unit) {
@@ -46,7 +50,7 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
   constexpr int CPF = 2;  // steps between a pixel's census loads and their use
   constexpr int CH = 8;  // steps per chunk (one fast/slow decision)
   static_assert(LPF > CPF && CH % LPF == 0 && CH % CPF == 0, "rings divide the chunk");
-  static_assert(CAP >= 1 && CAP <= 16, "partials are stored as one 16-byte slot group");
+  static_assert(CAP >= 1 && CAP <= 12, "partials are stored as one 12-byte slot group");
   __shared__ uint32_t lds_rows[4 * 64 * RW::DW];
   const int lane = lane_id();
   uint32_t* const row = lds_rows + (size_t)threadIdx.x * RW::DW;  // blockDim <= 256
@@ -94,7 +98,7 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
   const uint32_t vcl = (uint32_t)(lane + a.cmargin) << 2;
   const int vcr = (lane + a.cmargin - (CAP - 1)) << 2;  // >= 4*(D + 64) - 4*(CAP-1) > 4*bmax
   const uint32_t vlo = (uint32_t)lane << 1;
-  const uint32_t vpart = (uint32_t)lane << 4;
+  const uint32_t vpart = (uint32_t)lane * 12u;
 
   // prefetch rings: band starts of steps g .. g+LPF-1, census of steps g .. g+CPF-1
   int b0q[LPF];
@@ -217,13 +221,14 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
       for (int bb = 0; bb < 4; ++bb) v |= (4 * q + bb < CAP ? P[min(4 * q + bb, CAP - 1)] : 0xFFu) << (8 * bb);
       w[q] = v;
     }
+    const u32x3 w3 = {w[0], w[1], w[2]};  // the 12-slot layout (capP = 12)
     if constexpr (FAST) {
-      const uint32_t so = (uint32_t)(yat(g) * W + u0 + dx * g) << 4;
-      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)(vpart + so), 0, kPartStorePolicy);
+      const uint32_t so = (uint32_t)(yat(g) * W + u0 + dx * g) * 12u;
+      __builtin_amdgcn_raw_buffer_store_b96(w3, rpart, (int)(vpart + so), 0, kPartStorePolicy);
     } else if (live) {
       int p, c, x;
       pix_at(g, p, c, x);
-      __builtin_amdgcn_raw_buffer_store_b128(w, rpart, (int)((uint32_t)p << 4), 0, kPartStorePolicy);
+      __builtin_amdgcn_raw_buffer_store_b96(w3, rpart, (int)((uint32_t)p * 12u), 0, kPartStorePolicy);
     }
     lo_prev = b0;
   };
@@ -241,13 +246,7 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
   }
 }
 
-// Banded scans with one line per lane: one descriptor, or a batch of descriptors.
-template <int TAU, int CAP>
-__global__ __launch_bounds__(256) void k_scan_lane(ScanArgs a) {
-  const int u = wave_unit();
-  if (u < a.gprefix[a.ndir]) scan_lane_wave<CAP, TAU>(a, a, u);
-}
-
+// Batched banded scans with one line per lane.
 template <int TAU, int CAP>
 __global__ __launch_bounds__(256) void k_scan_lane_batch(Batch<ScanArgs> b) {
   const int u = wave_unit();

@@ -140,11 +140,13 @@ struct ScanChoice {
   // (census, sum of the paths, constant weights); 16-lane groups otherwise
   bool line;
 };
-ScanChoice choose_scan(int D, const mpv_band* band, int tau, const mpv_schedule& sc) {
+// line_ok: the level may run one line per lane (a batched level with the census data term,
+// the sum of the paths and constant weights); it then stores 12 partial slots per pixel.
+ScanChoice choose_scan(int D, const mpv_band* band, int tau, const mpv_schedule& sc, bool line_ok = false) {
   const int te = tau_eff(tau, D);
   if (band && band->lo) {
-    if (sc.band_lanes == MPV_BAND_LANES_LINE && !band->len && mpvl::band_line_ok(band->cap, te))
-      return {true, 16, 1, 16, false, false, true};
+    if (line_ok && sc.band_lanes == MPV_BAND_LANES_LINE && !band->len && mpvl::band_line_ok(band->cap, te))
+      return {true, 16, 1, 12, false, false, true};
     const int lpl = band_lanes(band->cap, te, sc.band_lanes == MPV_BAND_LANES_LINE ? 0 : sc.band_lanes);
     if (lpl) return {true, lpl, 1, lpl, false, false};
     FullLayout f = full_layout(D, sc.full_lanes);
@@ -209,9 +211,11 @@ struct LevelWs {
 // own_census: the level workspace holds the census of both views (false when the caller
 // computed them elsewhere in the same layout).
 LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const mpv_schedule& s,
-                 bool own_census = true) {
+                 bool own_census = true, bool batched = false) {
   LevelWs w{};
-  w.sc = choose_scan(p->num_disp, band, p->tau, s);
+  const bool line_ok = batched && p->data_term == MPV_DATA_CENSUS && p->merge == MPV_MERGE_SUM &&
+                       p->grad_sigma == 0;
+  w.sc = choose_scan(p->num_disp, band, p->tau, s, line_ok);
   // left census margin: covers x - d for every lane of a full-range (padded range) or
   // banded (band start <= D-1, up to 64 lanes) scan
   w.cmargin = (int)align_up((size_t)std::max(max_dpad(p->num_disp), p->num_disp + 64) + 1, 16);
@@ -353,25 +357,7 @@ mpv_status run_level(const mpv_params* p, const uint8_t* L, int lpitch, const ui
       int dirs[8];
       for (int i = 0; i < p->num_paths; ++i) dirs[i] = i;
       plan_dirs(a, dirs, p->num_paths, lw.sc.LPL);
-      // one line per lane: horizontal directions in 16-lane groups (descriptor hg, partial
-      // volumes first), then the others one line per lane (descriptor ln)
-      ScanArgs hg = a, ln = a;
-      int nh = 0, nv = 0;
-      if (lw.sc.line && data == SRC_CENSUS && !grad) {
-        int hd[8], vd[8];
-        for (int i = 0; i < p->num_paths; ++i) {
-          if (kDY[i] == 0) hd[nh++] = i;
-          else vd[nv++] = i;
-        }
-        plan_dirs(hg, hd, nh, lw.sc.LPL);
-        plan_dirs(ln, vd, nv, 1);
-        ln.line_lanes = 1;
-        ln.dir_base = nh;
-      }
-      if (nv) {
-        launch_scan(hg, lw.sc, SRC_CENSUS, OUT_PART, sched, s);
-        mpvl::scan_lane(ln, a.cap, a.tau, wpb_of(sched), s);
-      } else if (fuse && !ssim && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
+      if (fuse && !ssim && !lw.sc.banded_kernel && !lw.sc.masked)  // finer census beside this scan
         mpvl::scan_full_cen(a, SRC_CENSUS | grad, *fuse, cen0, ncen, lw.sc.LPL, lw.sc.K, wpb_of(sched), s);
       else
         launch_scan(a, lw.sc, data | grad, OUT_PART, sched, s);
@@ -458,7 +444,7 @@ int prop_block(const mpv_pyramid_params* p, int L, int l) {
 
 // fused_census (mpv_pyramid): the census of every level is computed up front from the input
 // (no coarse images are kept); otherwise (batches) coarse images and per-level census.
-PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g, bool fused_census = false) {
+PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g, bool fused_census = false, bool batched = false) {
   PyrWs w{};
   size_t off = 0;
   for (int l = 0; l + 1 < g.L && !fused_census; ++l) {
@@ -483,7 +469,7 @@ PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g, bool fused_census = 
     mpv_band b{nullptr, nullptr, g.cap[l]};
     int16_t dummy;
     if (l > 0) b.lo = &dummy;  // only presence matters for sizing
-    const LevelWs lw = level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched, !fused_census);
+    const LevelWs lw = level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched, !fused_census, batched);
     lvl = std::max(lvl, lw.total);
     if (fused_census) {
       w.cen_off[l] = off;
@@ -628,7 +614,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       static int16_t dummy_lo;
       mpv_band band{l > 0 ? (r ? (const int16_t*)(r + pr.w.lo_off[l & 1]) : &dummy_lo) : nullptr,
                     nullptr, pr.g.cap[l]};
-      lws[i] = level_ws(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, sc);
+      lws[i] = level_ws(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, sc, true, true);
       sargs[i] = level_scan_args(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, lws[i],
                                  r ? r + pr.w.level_off : nullptr);
       if (!r) sargs[i].lo = nullptr;
@@ -1096,7 +1082,7 @@ mpv_status mpv_batch_create(const mpv_pyramid_params* p, const mpv_batch_item* i
       delete b;
       return st;
     }
-    pr.w = pyr_ws(p, pr.g);
+    pr.w = pyr_ws(p, pr.g, false, true);
     pr.off = off;
     off += align_up(pr.w.total);
     b->pairs.push_back(pr);

@@ -1,14 +1,16 @@
-"""One scan line per lane (mpv_schedule.band_lanes = MPV_BAND_LANES_LINE), through the C ABI.
+"""One scan line per lane in batches (mpv_schedule.band_lanes = MPV_BAND_LANES_LINE), through
+the C ABI.
 
-A banded level's vertical and diagonal directions run with one line per lane, 64 neighbouring
-lines per wave walked row by row, and its horizontal ones in 16-lane groups of the same
-launch. Against the oracle bit for bit (every level's raw winners, the finest right disparity
-and LR-checked map): both band lengths with kernels (5 and 9), the three compile-time reduced
-taus, 4 and 8 paths, ragged waves at the end of a direction, lines that start and end on
-different rows, tall and narrow images (every diagonal line starts on a side), rows shorter
-than the disparity range, the paper's propagation; at full size against the default layout
-for one frame and for the 16-frame and mixed batches. Levels the layout does not take
-(other band lengths, layered merges, gradient weights, SSIM) must run as before.
+A batched banded level's vertical and diagonal directions run with one line per lane, 64
+neighbouring lines per wave walked row by row, 12 partial slots per pixel, while the
+horizontal directions' 16-lane groups run beside them on a second stream. Against the oracle
+bit for bit (the finest level's raw winners, right disparities and LR-checked map): both band
+lengths with kernels (5 and 9), the three compile-time reduced taus, 4 and 8 paths, ragged
+waves at the end of a direction, lines that start and end on different rows, tall and narrow
+images (every diagonal line starts on a side), rows shorter than the disparity range; at full
+size against the default layout for one pair, the 16-frame batch (eager and graph replay) and
+a mixed batch. Levels the layout does not take (other band lengths or taus, layered merges,
+gradient weights) and single-pair entry points must run as with the default schedule.
 """
 import numpy as np
 import pytest
@@ -44,55 +46,58 @@ def _line(mpv, **kw):
     return mpv.Schedule(band_lanes=mpv.Schedule.LINE, **kw)
 
 
-# (width, height, D, levels, radius, paths, tau, lambda, propagation)
+def _batch1(mpv, L, R, D, params, levels, radius, sched):
+    b = mpv.Batch([(L, R, D)], params, levels=levels, radius=radius, sched=sched, want_all=True)
+    b.run()
+    return b
+
+
+# (width, height, D, levels, radius, paths, tau, lambda)
 CASES = [
-    (160, 96, 64, 3, 4, 8, 4, 8, "nearest"),
-    (131, 75, 48, 3, 4, 8, 4, 8, "nearest"),
-    (61, 150, 32, 2, 4, 8, 4, 8, "nearest"),
-    (200, 40, 64, 3, 2, 8, 4, 8, "nearest"),
-    (97, 61, 64, 3, 4, 4, 4, 8, "nearest"),
-    (150, 90, 96, 3, 4, 8, 2, 10, "nearest"),
-    (150, 90, 96, 3, 2, 8, 1, 20, "nearest"),
-    (70, 9, 40, 2, 4, 8, 4, 8, "nearest"),
-    (5, 33, 16, 2, 2, 8, 4, 8, "nearest"),
-    (129, 65, 128, 2, 4, 8, 4, 8, "nearest"),
-    (163, 99, 64, 3, 4, 8, 4, 8, "paper"),
-    (300, 70, 256, 3, 4, 8, 4, 7, "nearest"),
+    (160, 96, 64, 3, 4, 8, 4, 8),
+    (131, 75, 48, 3, 4, 8, 4, 8),
+    (61, 150, 32, 2, 4, 8, 4, 8),
+    (200, 40, 64, 3, 2, 8, 4, 8),
+    (97, 61, 64, 3, 4, 4, 4, 8),
+    (150, 90, 96, 3, 4, 8, 2, 10),
+    (150, 90, 96, 3, 2, 8, 1, 20),
+    (70, 9, 40, 2, 4, 8, 4, 8),
+    (5, 33, 16, 2, 2, 8, 4, 8),
+    (129, 65, 128, 2, 4, 8, 4, 8),
+    (163, 99, 64, 3, 4, 8, 4, 8),
+    (300, 70, 256, 3, 4, 8, 4, 7),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}_D{c[2]}_L{c[3]}_R{c[4]}_P{c[5]}_t{c[6]}_{c[8]}"
-                                             for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}_D{c[2]}_L{c[3]}_R{c[4]}_P{c[5]}_t{c[6]}" for c in CASES])
 def test_line_layout_vs_oracle(mpv, orc, case):
+    """A one-pair batch with one line per lane against the oracle: raw winners, right
+    disparities and the LR-checked map of the finest level."""
     from paper_2001_09678_amd.scene import make_scene
-    w, h, D, levels, R, P, tau, lam, prop = case
+    w, h, D, levels, R, P, tau, lam = case
     _log("line layout", case)
     sc = make_scene(900 + w + h, w, h, D - 1, 6, ground=True)
     p = mpv.MPVParams(num_disp=D, num_paths=P, lam=lam, tau=tau)
-    pyr = mpv.pyramid(_cuda(sc.left), _cuda(sc.right), p, levels=levels, radius=R, keep_levels=True,
-                      sched=_line(mpv), propagation=prop)
-    ref = orc.pyramid(sc.left, sc.right, D, levels=levels, radius=R, num_paths=P, lam=lam, tau=tau,
-                      propagation=prop)
-    for l in range(levels):
-        np.testing.assert_array_equal(_np(pyr.level_raw[l]), ref[l].dl, err_msg=f"level {l}")
-    np.testing.assert_array_equal(_np(pyr.right), ref[-1].dr)
-    np.testing.assert_array_equal(_np(pyr.disp), ref[-1].out)
+    b = _batch1(mpv, _cuda(sc.left), _cuda(sc.right), D, p, levels, R, _line(mpv, waves_per_block=2))
+    ref = orc.pyramid(sc.left, sc.right, D, levels=levels, radius=R, num_paths=P, lam=lam, tau=tau)[-1]
+    np.testing.assert_array_equal(_np(b.raw[0]), ref.dl)
+    np.testing.assert_array_equal(_np(b.right[0]), ref.dr)
+    np.testing.assert_array_equal(_np(b.disp[0]), ref.out)
 
 
 @pytest.mark.parametrize("wpb", [1, 2, 4])
 def test_line_layout_full_size(mpv, wpb):
-    """1280x720, D=128, 3 levels, +/-4 bands: identical to the default layout."""
+    """1280x720, D=128, 3 levels, +/-4 bands, one pair: identical to the default layout."""
     from paper_2001_09678_amd.scene import config_scene
     _log("line layout full size, waves per block", wpb)
     sc, _ = config_scene("c2")
     L, R = _cuda(sc.left), _cuda(sc.right)
     params = mpv.MPVParams(num_disp=128, num_paths=8)
-    ref = mpv.pyramid(L, R, params, levels=3, radius=4, keep_levels=True)
-    got = mpv.pyramid(L, R, params, levels=3, radius=4, keep_levels=True, sched=_line(mpv, waves_per_block=wpb))
-    for l in range(3):
-        np.testing.assert_array_equal(_np(got.level_raw[l]), _np(ref.level_raw[l]), err_msg=f"level {l}")
-    np.testing.assert_array_equal(_np(got.right), _np(ref.right))
-    np.testing.assert_array_equal(_np(got.disp), _np(ref.disp))
+    ref = _batch1(mpv, L, R, 128, params, 3, 4, mpv.Schedule(waves_per_block=wpb))
+    got = _batch1(mpv, L, R, 128, params, 3, 4, _line(mpv, waves_per_block=wpb))
+    np.testing.assert_array_equal(_np(got.raw[0]), _np(ref.raw[0]))
+    np.testing.assert_array_equal(_np(got.right[0]), _np(ref.right[0]))
+    np.testing.assert_array_equal(_np(got.disp[0]), _np(ref.disp[0]))
 
 
 def test_line_layout_workload_oracle(mpv, orc):
@@ -100,11 +105,11 @@ def test_line_layout_workload_oracle(mpv, orc):
     from paper_2001_09678_amd.scene import config_scene
     sc, _ = config_scene("c2")
     _log("line layout vs oracle, 1280x720")
-    got = mpv.pyramid(_cuda(sc.left), _cuda(sc.right), mpv.MPVParams(num_disp=128, num_paths=8), levels=3,
-                      radius=4, sched=_line(mpv, waves_per_block=4))
+    b = _batch1(mpv, _cuda(sc.left), _cuda(sc.right), 128, mpv.MPVParams(num_disp=128, num_paths=8), 3, 4,
+                _line(mpv, waves_per_block=4))
     ref = orc.pyramid(sc.left, sc.right, 128, levels=3, radius=4, num_paths=8)[-1]
-    np.testing.assert_array_equal(_np(got.raw), ref.dl)
-    np.testing.assert_array_equal(_np(got.disp), ref.out)
+    np.testing.assert_array_equal(_np(b.raw[0]), ref.dl)
+    np.testing.assert_array_equal(_np(b.disp[0]), ref.out)
 
 
 def test_line_layout_step_batch(mpv):
@@ -152,10 +157,11 @@ def test_line_layout_mixed_batch(mpv, orc):
         np.testing.assert_array_equal(_np(b.right[i]), ref.dr, err_msg=f"pair {i} right")
 
 
-@pytest.mark.parametrize("kw", [dict(merge="layered"), dict(grad_sigma=16), dict(data_term="ssim"),
-                                dict(radius=3), dict(tau=3)], ids=["layered", "grad", "ssim", "cap7", "tau3"])
+@pytest.mark.parametrize("kw", [dict(merge="layered"), dict(grad_sigma=16), dict(radius=3), dict(tau=3)],
+                         ids=["layered", "grad", "cap7", "tau3"])
 def test_line_schedule_elsewhere_unchanged(mpv, kw):
-    """Where the layout does not apply, the schedule gives the default's bits."""
+    """Where the layout does not apply, a batch with the schedule gives the default's bits,
+    and so does a single pair through mpv_pyramid (which never takes it)."""
     from paper_2001_09678_amd.scene import make_scene
     kw = dict(kw)
     radius = kw.pop("radius", 4)
@@ -163,7 +169,21 @@ def test_line_schedule_elsewhere_unchanged(mpv, kw):
     L, R = _cuda(sc.left), _cuda(sc.right)
     p = mpv.MPVParams(num_disp=64, num_paths=8, **kw)
     _log("line schedule elsewhere", kw, radius)
-    ref = mpv.pyramid(L, R, p, levels=3, radius=radius)
-    got = mpv.pyramid(L, R, p, levels=3, radius=radius, sched=_line(mpv))
-    np.testing.assert_array_equal(_np(got.disp), _np(ref.disp))
-    np.testing.assert_array_equal(_np(got.raw), _np(ref.raw))
+    ref = _batch1(mpv, L, R, 64, p, 3, radius, mpv.Schedule())
+    got = _batch1(mpv, L, R, 64, p, 3, radius, _line(mpv))
+    np.testing.assert_array_equal(_np(got.disp[0]), _np(ref.disp[0]))
+    np.testing.assert_array_equal(_np(got.raw[0]), _np(ref.raw[0]))
+    solo = mpv.pyramid(L, R, p, levels=3, radius=radius, sched=_line(mpv))
+    np.testing.assert_array_equal(_np(solo.disp), _np(ref.disp[0]))
+
+
+def test_line_schedule_single_pair_is_default(mpv):
+    """mpv_pyramid with the schedule runs the default layout (a lone frame's lines would be
+    long serial chains): identical bits, SSIM data term included."""
+    from paper_2001_09678_amd.scene import make_scene
+    sc = make_scene(45, 150, 90, 63, 6, ground=True)
+    L, R = _cuda(sc.left), _cuda(sc.right)
+    for p in (mpv.MPVParams(num_disp=64, num_paths=8), mpv.MPVParams(num_disp=64, num_paths=8, data_term="ssim")):
+        ref = mpv.pyramid(L, R, p, levels=3, radius=4)
+        got = mpv.pyramid(L, R, p, levels=3, radius=4, sched=_line(mpv))
+        np.testing.assert_array_equal(_np(got.disp), _np(ref.disp))
