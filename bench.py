@@ -51,8 +51,8 @@ SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/c
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band_batch.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp", "paper_2001_09678_amd/csrc/lines.hpp",
                 "paper_2001_09678_amd/csrc/kern_band_lines.hip"]
-SCAN_TRAFFIC = {"sources_sha1": "88e83067430356626e79a1156487cf71dad4b84a", "frames": 16,
-                "fetch_bytes": 3133623742, "write_bytes": 2004598409}
+SCAN_TRAFFIC = {"sources_sha1": "e037fb792f40fe15b84b70ce959856db503a01f3", "frames": 16,
+                "fetch_bytes": 1359156649, "write_bytes": 1461370777}
 
 
 def scan_sources_sha1():

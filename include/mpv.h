@@ -300,7 +300,10 @@ mpv_status mpv_batch_create(const mpv_pyramid_params *p, const mpv_batch_item *i
                             mpv_batch *out);
 size_t mpv_batch_workspace_bytes(mpv_batch b);
 mpv_status mpv_batch_bind(mpv_batch b, void *workspace, size_t workspace_bytes, hipStream_t stream);
-/* Enqueue the whole batch (about 4 launches per level) on `stream`. */
+/* Enqueue the whole batch (about 4 launches per level) on `stream`. With band_lanes =
+ * MPV_BAND_LANES_LINE a line level's horizontal scan runs on a stream the batch owns, after
+ * an event recorded on `stream` and joined back by another before the level's reduce, so the
+ * batch stays ordered with the caller's work on `stream` (also in mpv_batch_run_graph). */
 mpv_status mpv_batch_run(mpv_batch b, hipStream_t stream);
 /* Same work as one hipGraph: captured on a private stream at the first call, then replayed
  * on `stream` with one hipGraphLaunch per call. */
