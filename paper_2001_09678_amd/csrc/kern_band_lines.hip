@@ -26,10 +26,15 @@ bool band_line_ok(int cap, int tau) {
   return with_shape(cap, tau, [](auto, auto) {}) && cap + 2 * (tau - 1) <= 16 && cap <= 12;
 }
 
-void scan_lane_batch(const Batch<ScanArgs>& b, int units, int cap, int tau, int wpb, hipStream_t s) {
+void scan_lane_batch(const Batch<ScanArgs>& b, int units, int cap, int tau, bool p6, int wpb,
+                     hipStream_t s) {
   with_shape(cap, tau, [&](auto cc, auto tc) {
     constexpr int CAP = decltype(cc)::value, TAU = decltype(tc)::value;
-    hipLaunchKernelGGL((k_scan_lane_batch<TAU, CAP>), dim3((units + wpb - 1) / wpb), dim3(64 * wpb), 0, s, b);
+    const dim3 grid((units + wpb - 1) / wpb), block(64 * wpb);
+    if (p6)
+      hipLaunchKernelGGL((k_scan_lane_batch<TAU, CAP, true>), grid, block, 0, s, b);
+    else
+      hipLaunchKernelGGL((k_scan_lane_batch<TAU, CAP, false>), grid, block, 0, s, b);
   });
 }
 

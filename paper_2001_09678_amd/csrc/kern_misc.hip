@@ -28,6 +28,10 @@ void reduce_part(const RedArgs& a, int need_lr, hipStream_t s) {
 }
 
 void reduce_part_batch(const Batch<RedArgs>& b, int rows, int stride, hipStream_t s) {
+  if (stride == PART6_PITCH) {
+    hipLaunchKernelGGL((k_reduce_part_batch<1, PART6_SLOTS>), dim3(rows), dim3(256), 0, s, b);
+    return;
+  }
   if (stride == 12) {
     hipLaunchKernelGGL((k_reduce_part_batch<1, 12>), dim3(rows), dim3(256), 0, s, b);
     return;

@@ -957,6 +957,18 @@ __device__ __forceinline__ void scan_full_wave(const ScanArgs& a, const ScanArgs
   }
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Slots 0..9 of a pixel's staged bytes in the six-bit layout (PART6_PITCH): each byte's low
+// six bits (the slots past the band hold 255, read as 63 and never summed).
+__device__ __forceinline__ u32x2 pack6_bytes(const uint4 v) {
+  const uint32_t b[3] = {v.x, v.y, v.z};
+  u32x2 w = {0u, 0u};
+#pragma unroll
+  for (int i = 0; i < PART6_SLOTS; ++i) w[i / 5] |= ((b[i / 4] >> (8 * (i % 4))) & 63u) << (6 * (i % 5));
+  return w;
+}
+
 // Banded scan: each pixel searches cap <= LPL - 2(tau-1) consecutive disparities starting
 // at lo(p); lane j holds d = lo(p) + j. Neighbouring pixels may place their bands
 // anywhere, so the envelope is built in the previous pixel's frame extended by tau-1
@@ -1000,8 +1012,11 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   // t0 + j's 16 slots with one store: whole cache lines, one store instruction per chunk
   // instead of one per step
   __shared__ uint8_t stage_tile[4 * 64 * 16];
-  const bool hstage = STAGED && LPL == 16 && OUT == OUT_PART && (a.capP == 16 || a.capP == 12) &&
-                      (la.dp == 1 || la.dp == -1);
+  const bool hstage = STAGED && LPL == 16 && OUT == OUT_PART &&
+                      (a.capP == 16 || a.capP == 12 || a.capP == PART6_PITCH) && (la.dp == 1 || la.dp == -1);
+  // six-bit slots (levels with one line per lane whose energies fit six bits): a lane's byte
+  // cannot be stored alone, so every chunk goes through the tile, fast or not
+  const bool p6 = hstage && a.capP == PART6_PITCH;
   // lanes past the slot pitch keep their bytes (every band fits the first capP slots): the
   // 12-slot layout of batched levels with one line per lane, whose lane groups hold only the
   // horizontal lines (staged in fast chunks, so only the per-step stores check)
@@ -1141,7 +1156,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     }
     if constexpr (OUT == OUT_PART) {
       const uint8_t v8 = (uint8_t)min(P, 255u);
-      if constexpr (FAST && STAGE) {
+      if constexpr (STAGE) {
         tile[k * 16 + j] = v8;
       } else if constexpr (FAST) {
         const uint32_t vo = LPL == 64 ? (uint32_t)j : pst + j, so = LPL == 64 ? pst : 0u;
@@ -1175,7 +1190,9 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       __builtin_amdgcn_wave_barrier();
       const uint4 v = *(const uint4*)(tile + j * 16);
       const int vo = (int)(pst0 + (uint32_t)j * pstep);
-      if (a.capP == 16) {
+      if (p6) {
+        __builtin_amdgcn_raw_buffer_store_b64(pack6_bytes(v), rpart, vo, 0, kPartStorePolicy);
+      } else if (a.capP == 16) {
         typedef unsigned int u4v __attribute__((ext_vector_type(4)));
         const u4v w = {v.x, v.y, v.z, v.w};
         __builtin_amdgcn_raw_buffer_store_b128(w, rpart, vo, 0, kPartStorePolicy);
@@ -1192,6 +1209,15 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
         pst += pstep;
         cpf += (uint32_t)la.dc;
       });
+    } else if (STAGED && p6) {
+      if constexpr (STAGED) {
+        static_for<CHUNK>([&](auto kc) { step(kc, std::false_type{}, nxt, t0, 0u, 0u, std::true_type{}); });
+        __builtin_amdgcn_wave_barrier();
+        const uint4 v = *(const uint4*)(tile + j * 16);
+        if (t0 + j < la.n)
+          __builtin_amdgcn_raw_buffer_store_b64(pack6_bytes(v), rpart, (int)(la.pix(t0 + j) * (uint32_t)PART6_PITCH),
+                                                0, kPartStorePolicy);
+      }
     } else {
       static_for<CHUNK>([&](auto kc) { step(kc, std::false_type{}, nxt, t0, 0u, 0u, std::false_type{}); });
     }
@@ -1393,11 +1419,15 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
 // slots of one pixel (one 16-byte load per partial), LPP = stride/16 lanes per pixel, 64/LPP
 // pixels per wave step; or (stride 12, the compact layout of the one-line-per-lane scans)
 // SL = 12 slots, one lane per pixel. Sums fit 16 bits (P * 255), so two slots share a
-// register. need_lr = false (intermediate pyramid levels) writes the raw winner only.
+// register. SL = PART6_SLOTS: the six-bit layout (8 bytes per pixel, one lane per pixel), whose
+// sums fit 9 bits: fields 12 bits apart share a register. need_lr = false (intermediate
+// pyramid levels) writes the raw winner only.
 template <int LPP, int SL = 16>
 __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int need_lr) {
-  static_assert(SL == 16 || (SL == 12 && LPP == 1), "16-slot lanes, or one 12-slot lane per pixel");
-  constexpr int NQ = SL / 4;  // 32-bit words of slots per lane
+  constexpr bool P6 = SL == PART6_SLOTS;
+  static_assert(SL == 16 || ((SL == 12 || P6) && LPP == 1),
+                "16-slot lanes, or one 12-slot or six-bit lane per pixel");
+  constexpr int NQ = P6 ? 2 : SL / 4;  // 32-bit words of slots per lane
   __shared__ uint32_t s_rkey[RED_MAXW];
   __shared__ int16_t s_dl[RED_MAXW];
   constexpr uint32_t NOK = 0xFFFFFFFFu;
@@ -1424,6 +1454,9 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
       if constexpr (SL == 16) {
         const uint4 w = r < a.npart ? *(const uint4*)(q0 + r * a.part_stride) : make_uint4(0u, 0u, 0u, 0u);
         wv[r][0] = w.x, wv[r][1] = w.y, wv[r][2] = w.z, wv[r][3] = w.w;
+      } else if constexpr (P6) {
+        const uint2 w = r < a.npart ? *(const uint2*)(q0 + r * a.part_stride) : make_uint2(0u, 0u);
+        wv[r][0] = w.x, wv[r][1] = w.y;
       } else {
         const uint3 w = r < a.npart ? *(const uint3*)(q0 + r * a.part_stride) : make_uint3(0u, 0u, 0u);
         wv[r][0] = w.x, wv[r][1] = w.y, wv[r][2] = w.z;
@@ -1435,32 +1468,57 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
     uint32_t sm[2 * NQ];
 #pragma unroll
     for (int i = 0; i < 2 * NQ; ++i) sm[i] = 0;
-    if (a.merge == 1 + MERGE_MIN) {  // layered merge: the smaller of the two passes
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        sm[2 * q] = pk_min(wv[0][q] & 0x00FF00FFu, wv[1][q] & 0x00FF00FFu);
-        sm[2 * q + 1] = pk_min((wv[0][q] >> 8) & 0x00FF00FFu, (wv[1][q] >> 8) & 0x00FF00FFu);
-      }
-    } else {
+    uint32_t v[SL];
+    if constexpr (P6) {
+      // the sum of the paths (the layout serves no layered merge): word q's fields 5q, 5q+2
+      // at bits 0, 12 of sm[2q], 5q+1, 5q+3 at bits 0, 12 of sm[2q+1], fields 4 and 9 at bits
+      // 0 and 12 of s4
+      uint32_t s4 = 0;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          sm[2 * q] += wv[r][q] & 0x00FF00FFu;
-          sm[2 * q + 1] += (wv[r][q] >> 8) & 0x00FF00FFu;
+        for (int q = 0; q < 2; ++q) {
+          sm[2 * q] += wv[r][q] & 0x3F03Fu;
+          sm[2 * q + 1] += (wv[r][q] >> 6) & 0x3F03Fu;
         }
+        s4 += (wv[r][0] >> 24) | ((wv[r][1] >> 12) & 0x3F000u);
       }
-      if (a.merge == 1 + MERGE_MEAN)  // layered merge: the mean of the two, rounded down
 #pragma unroll
-        for (int i = 0; i < 2 * NQ; ++i) sm[i] = (sm[i] >> 1) & 0x7FFF7FFFu;
-    }
-    uint32_t v[SL];
+      for (int q = 0; q < 2; ++q) {
+        v[5 * q + 0] = sm[2 * q] & 0xFFFu;
+        v[5 * q + 1] = sm[2 * q + 1] & 0xFFFu;
+        v[5 * q + 2] = sm[2 * q] >> 12;
+        v[5 * q + 3] = sm[2 * q + 1] >> 12;
+      }
+      v[4] = s4 & 0xFFFu;
+      v[9] = s4 >> 12;
+    } else {
+      if (a.merge == 1 + MERGE_MIN) {  // layered merge: the smaller of the two passes
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      v[4 * q + 0] = sm[2 * q] & 0xFFFFu;
-      v[4 * q + 1] = sm[2 * q + 1] & 0xFFFFu;
-      v[4 * q + 2] = sm[2 * q] >> 16;
-      v[4 * q + 3] = sm[2 * q + 1] >> 16;
+        for (int q = 0; q < NQ; ++q) {
+          sm[2 * q] = pk_min(wv[0][q] & 0x00FF00FFu, wv[1][q] & 0x00FF00FFu);
+          sm[2 * q + 1] = pk_min((wv[0][q] >> 8) & 0x00FF00FFu, (wv[1][q] >> 8) & 0x00FF00FFu);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            sm[2 * q] += wv[r][q] & 0x00FF00FFu;
+            sm[2 * q + 1] += (wv[r][q] >> 8) & 0x00FF00FFu;
+          }
+        }
+        if (a.merge == 1 + MERGE_MEAN)  // layered merge: the mean of the two, rounded down
+#pragma unroll
+          for (int i = 0; i < 2 * NQ; ++i) sm[i] = (sm[i] >> 1) & 0x7FFF7FFFu;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        v[4 * q + 0] = sm[2 * q] & 0xFFFFu;
+        v[4 * q + 1] = sm[2 * q + 1] & 0xFFFFu;
+        v[4 * q + 2] = sm[2 * q] >> 16;
+        v[4 * q + 3] = sm[2 * q + 1] >> 16;
+      }
     }
     uint32_t best = NOK;
 #pragma unroll

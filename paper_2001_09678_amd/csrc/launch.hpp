@@ -27,9 +27,11 @@ void scan_band(const ScanArgs& a, int LPL, int src, int out, bool var, int wpb, 
 void scan_band_batch(const Batch<ScanArgs>& b, int units, int LPL, int tau, int wpb, hipStream_t s);
 // One line per lane for the directions with dy != 0 (kern_band_lines.hip): band lengths and
 // reduced tau with kernels, then a batch of descriptors whose directions all have dy != 0
-// (ScanArgs::line_lanes, gprefix counting 64 lines per wave), 12 partial slots per pixel.
+// (ScanArgs::line_lanes, gprefix counting 64 lines per wave), 12 partial slots per pixel, or
+// (p6) six-bit slots in PART6_PITCH bytes.
 bool band_line_ok(int cap, int tau);
-void scan_lane_batch(const Batch<ScanArgs>& b, int units, int cap, int tau, int wpb, hipStream_t s);
+void scan_lane_batch(const Batch<ScanArgs>& b, int units, int cap, int tau, bool p6, int wpb,
+                     hipStream_t s);
 // Cost-volume source with partial output (the fused SSIM path; kern_cost_src.hip).
 void scan_full_cost(const ScanArgs& a, int LPL, int K, bool banded, int wpb, hipStream_t s);
 void scan_band_cost(const ScanArgs& a, int LPL, bool var, int wpb, hipStream_t s);
@@ -65,7 +67,8 @@ void scan_full_batch_grad_layered(const Batch<ScanArgs>& b, int src, int units, 
 void scan_band_batch_grad(const Batch<ScanArgs>& b, int src, int units, int LPL, int tau, int wpb,
                           hipStream_t s);
 
-// Sum + WTA (+ right disparity + LR when need_lr) over P uint8 partial volumes.
+// Sum + WTA (+ right disparity + LR when need_lr) over P partial volumes (uint8 slots; batched:
+// also six-bit slots at stride PART6_PITCH).
 void reduce_part(const RedArgs& a, int need_lr, hipStream_t s);
 void reduce_part_batch(const Batch<RedArgs>& b, int rows, int stride, hipStream_t s);
 // WTA + right disparity + LR over an exported uint16 / int32 aggregate volume.

@@ -25,7 +25,8 @@ namespace mpvk {
 // 24 + lambda*tau <= 255, so that every normalised energy is its own partial byte. Its
 // levels use 12 partial slots per pixel (capP = 12): 12-byte stores of consecutive pixels
 // (and 12-byte loads in the reduce) cover whole cache lines with a quarter fewer bytes than
-// the 16-slot pitch of the lane groups.
+// the 16-slot pitch of the lane groups. P6: where 24 + lambda*tau <= 63 every normalised
+// energy fits six bits, and a pixel's slots go in 8 bytes instead (PART6_PITCH).
 // ---------------------------------------------------------------------------------------
 template <int CAP, int TAU>
 struct LaneRow {
@@ -39,10 +40,9 @@ struct LaneRow {
 
 __device__ __forceinline__ int wave_min_s(int v) { return -wave_max_s(-v); }
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 
-template <int CAP, int TAU>
+template <int CAP, int TAU, bool P6>
 __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs& tab, int unit) {
   using RW = LaneRow<CAP, TAU>;
   constexpr int M = RW::M;
@@ -50,7 +50,8 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
   constexpr int CPF = 2;  // steps between a pixel's census loads and their use
   constexpr int CH = 8;  // steps per chunk (one fast/slow decision)
   static_assert(LPF > CPF && CH % LPF == 0 && CH % CPF == 0, "rings divide the chunk");
-  static_assert(CAP >= 1 && CAP <= 12, "partials are stored as one 12-byte slot group");
+  static_assert(CAP >= 1 && CAP <= (P6 ? PART6_SLOTS : 12), "a pixel's partials are one slot group");
+  constexpr uint32_t PITCH = P6 ? PART6_PITCH : 12;
   __shared__ uint32_t lds_rows[4 * 64 * RW::DW];
   const int lane = lane_id();
   uint32_t* const row = lds_rows + (size_t)threadIdx.x * RW::DW;  // blockDim <= 256
@@ -98,7 +99,7 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
   const uint32_t vcl = (uint32_t)(lane + a.cmargin) << 2;
   const int vcr = (lane + a.cmargin - (CAP - 1)) << 2;  // >= 4*(D + 64) - 4*(CAP-1) > 4*bmax
   const uint32_t vlo = (uint32_t)lane << 1;
-  const uint32_t vpart = (uint32_t)lane * 12u;
+  const uint32_t vpart = (uint32_t)lane * PITCH;
 
   // prefetch rings: band starts of steps g .. g+LPF-1, census of steps g .. g+CPF-1
   int b0q[LPF];
@@ -209,26 +210,39 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
         for (int j = 0; j < CAP; ++j) P[j] = 0;
       }
     }
-    // partial bytes (every normalised energy is at most 24 + lambda*tau <= 255), 255 past CAP.
-    // The whole offset goes in the vector register: a 16-byte buffer store with a scalar
-    // offset has been seen to store the next instruction's result in its upper half (the
-    // compiler models that hazard only for stores without a scalar offset register).
-    u32x4 w;
+    // the pixel's partials (offsets in the vector register: a 16-byte buffer store with a
+    // scalar offset has been seen to store the next instruction's result in its upper half,
+    // and the compiler models that hazard only for stores without a scalar offset register)
+    const uint32_t po = FAST ? vpart + (uint32_t)(yat(g) * W + u0 + dx * g) * PITCH : 0u;
+    if constexpr (P6) {
+      // six-bit fields (every normalised energy is at most 24 + lambda*tau <= 63)
+      u32x2 w = {0u, 0u};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t v = 0;
+      for (int i = 0; i < CAP; ++i) w[i / 5] |= P[i] << (6 * (i % 5));
+      if constexpr (FAST) {
+        __builtin_amdgcn_raw_buffer_store_b64(w, rpart, (int)po, 0, kPartStorePolicy);
+      } else if (live) {
+        int p, c, x;
+        pix_at(g, p, c, x);
+        __builtin_amdgcn_raw_buffer_store_b64(w, rpart, (int)((uint32_t)p * PITCH), 0, kPartStorePolicy);
+      }
+    } else {
+      // bytes (every normalised energy is at most 24 + lambda*tau <= 255), 255 past CAP
+      u32x3 w = {0u, 0u, 0u};
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb) v |= (4 * q + bb < CAP ? P[min(4 * q + bb, CAP - 1)] : 0xFFu) << (8 * bb);
-      w[q] = v;
-    }
-    const u32x3 w3 = {w[0], w[1], w[2]};  // the 12-slot layout (capP = 12)
-    if constexpr (FAST) {
-      const uint32_t so = (uint32_t)(yat(g) * W + u0 + dx * g) * 12u;
-      __builtin_amdgcn_raw_buffer_store_b96(w3, rpart, (int)(vpart + so), 0, kPartStorePolicy);
-    } else if (live) {
-      int p, c, x;
-      pix_at(g, p, c, x);
-      __builtin_amdgcn_raw_buffer_store_b96(w3, rpart, (int)((uint32_t)p * 12u), 0, kPartStorePolicy);
+      for (int q = 0; q < 3; ++q) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) v |= (4 * q + bb < CAP ? P[min(4 * q + bb, CAP - 1)] : 0xFFu) << (8 * bb);
+        w[q] = v;
+      }
+      if constexpr (FAST) {
+        __builtin_amdgcn_raw_buffer_store_b96(w, rpart, (int)po, 0, kPartStorePolicy);
+      } else if (live) {
+        int p, c, x;
+        pix_at(g, p, c, x);
+        __builtin_amdgcn_raw_buffer_store_b96(w, rpart, (int)((uint32_t)p * PITCH), 0, kPartStorePolicy);
+      }
     }
     lo_prev = b0;
   };
@@ -246,14 +260,14 @@ __device__ __forceinline__ void scan_lane_wave(const ScanArgs& a, const ScanArgs
   }
 }
 
-// Batched banded scans with one line per lane.
-template <int TAU, int CAP>
+// Batched banded scans with one line per lane; P6: six-bit partial slots.
+template <int TAU, int CAP, bool P6>
 __global__ __launch_bounds__(256) void k_scan_lane_batch(Batch<ScanArgs> b) {
   const int u = wave_unit();
   if (u >= b.first[b.nseg]) return;
   const int s = batch_find(b.first, b.nseg, u);
   const ScanArgs a = b.desc[s];  // private copy, as above
-  scan_lane_wave<CAP, TAU>(a, b.desc[s], u - b.first[s]);
+  scan_lane_wave<CAP, TAU, P6>(a, b.desc[s], u - b.first[s]);
 }
 
 }  // namespace mpvk

@@ -141,12 +141,17 @@ struct ScanChoice {
   bool line;
 };
 // line_ok: the level may run one line per lane (a batched level with the census data term,
-// the sum of the paths and constant weights); it then stores 12 partial slots per pixel.
-ScanChoice choose_scan(int D, const mpv_band* band, int tau, const mpv_schedule& sc, bool line_ok = false) {
+// the sum of the paths and constant weights); it then stores 12 partial slots per pixel, or
+// six-bit slots in PART6_PITCH bytes where every normalised energy, at most
+// 24 + lambda*tau, fits six bits.
+ScanChoice choose_scan(int D, const mpv_band* band, int tau, const mpv_schedule& sc, bool line_ok = false,
+                       int lambda = 0) {
   const int te = tau_eff(tau, D);
   if (band && band->lo) {
-    if (line_ok && sc.band_lanes == MPV_BAND_LANES_LINE && !band->len && mpvl::band_line_ok(band->cap, te))
-      return {true, 16, 1, 12, false, false, true};
+    if (line_ok && sc.band_lanes == MPV_BAND_LANES_LINE && !band->len && mpvl::band_line_ok(band->cap, te)) {
+      const bool six = 24 + (long)lambda * te <= 63 && band->cap <= PART6_SLOTS;
+      return {true, 16, 1, six ? PART6_PITCH : 12, false, false, true};
+    }
     const int lpl = band_lanes(band->cap, te, sc.band_lanes == MPV_BAND_LANES_LINE ? 0 : sc.band_lanes);
     if (lpl) return {true, lpl, 1, lpl, false, false};
     FullLayout f = full_layout(D, sc.full_lanes);
@@ -215,7 +220,7 @@ LevelWs level_ws(const mpv_params* p, int W, int H, const mpv_band* band, const 
   LevelWs w{};
   const bool line_ok = batched && p->data_term == MPV_DATA_CENSUS && p->merge == MPV_MERGE_SUM &&
                        p->grad_sigma == 0;
-  w.sc = choose_scan(p->num_disp, band, p->tau, s, line_ok);
+  w.sc = choose_scan(p->num_disp, band, p->tau, s, line_ok, p->lambda);
   // left census margin: covers x - d for every lane of a full-range (padded range) or
   // banded (band start <= D-1, up to 64 lanes) scan
   w.cmargin = (int)align_up((size_t)std::max(max_dpad(p->num_disp), p->num_disp + 64) + 1, 16);
@@ -639,9 +644,10 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       int LPL, K, tau;
       bool masked;
       int line_cap;  // > 0: one line per lane for the directions with dy != 0, bands of this cap
+      int pitch;     // partial slots per pixel (PART6_PITCH: six-bit slots)
       bool operator==(const Key& o) const {
         return band == o.band && LPL == o.LPL && K == o.K && tau == o.tau && masked == o.masked &&
-               line_cap == o.line_cap;
+               line_cap == o.line_cap && pitch == o.pitch;
       }
     };
     const bool layered = b.p.base.merge != MPV_MERGE_SUM;
@@ -649,7 +655,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
     auto key_of = [&](int i) {
       const ScanChoice& c = lws[i].sc;
       const bool line = c.line && !layered && !grad;
-      return Key{c.banded_kernel, c.LPL, c.K, sargs[i].tau, c.masked, line ? sargs[i].cap : 0};
+      return Key{c.banded_kernel, c.LPL, c.K, sargs[i].tau, c.masked, line ? sargs[i].cap : 0, c.capP};
     };
     std::vector<Key> keys;
     for (int i = 0; i < n; ++i)
@@ -711,6 +717,7 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
         ln.src = src | grad;
         ln.line = lines == 1;
         ln.cap = k.line_cap;
+        ln.stride = k.pitch;
         b.launches.push_back(ln);
       }
       // both layouts present: the lane-group launch runs beside the line launch after it
@@ -1180,7 +1187,8 @@ mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& lau
       }
       case mpv_batch_s::SCAN_BAND: {
         if (ln.line)
-          mpvl::scan_lane_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.cap, ln.tau, wpb, s);
+          mpvl::scan_lane_batch({(const ScanArgs*)desc, first, ln.nseg}, ln.units, ln.cap, ln.tau,
+                                ln.stride == PART6_PITCH, wpb, s);
         else if (src_grad(ln.src))
           mpvl::scan_band_batch_grad({(const ScanArgs*)desc, first, ln.nseg}, ln.src, ln.units, ln.LPL,
                                      ln.tau, wpb, s);

@@ -32,7 +32,7 @@ struct ScanArgs {
   const uint8_t* len;
   uint8_t* part;
   long long part_stride;  // bytes between direction volumes
-  int capP;               // partial slots per pixel
+  int capP;               // partial slots per pixel (bytes), or PART6_PITCH: six-bit slots
   void* agg;              // canonical export [H][W][cap]
   int first;              // canonical export: this direction writes instead of adding
   // Directions of this descriptor: dir[0..ndir), their partial volumes are numbers
@@ -123,6 +123,12 @@ struct PropArgs {
   int16_t* lo;  // finer level's band starts [H][W]
   int W, H, D, R, cap, block;
 };
+
+// Six-bit partial layout: a pixel's slots 0..9 in 8 bytes, slot i in bits 6*(i%5) .. +5 of
+// 32-bit word i/5 (bits 30, 31 zero). Taken where every normalised energy fits six bits
+// (24 + lambda*tau <= 63); the sum of 8 paths then fits 9 bits.
+constexpr int PART6_PITCH = 8;
+constexpr int PART6_SLOTS = 10;
 
 constexpr int RED_MAXW = 4096;
 constexpr int CENSUS_TILE_ROWS = 16;  // batched census: 64 x 16 pixels per block

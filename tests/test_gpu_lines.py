@@ -2,10 +2,12 @@
 the C ABI.
 
 A batched banded level's vertical and diagonal directions run with one line per lane, 64
-neighbouring lines per wave walked row by row, 12 partial slots per pixel, while the
-horizontal directions' 16-lane groups run beside them on a second stream. Against the oracle
+neighbouring lines per wave walked row by row, while the horizontal directions' 16-lane groups
+run beside them on a second stream. A pixel's partials are six-bit slots in 8 bytes where
+every normalised energy fits (24 + lambda*tau <= 63), else 12 byte slots. Against the oracle
 bit for bit (the finest level's raw winners, right disparities and LR-checked map): both band
-lengths with kernels (5 and 9), the three compile-time reduced taus, 4 and 8 paths, ragged
+lengths with kernels (5 and 9), the three compile-time reduced taus, both slot layouts (and
+the largest energy six bits hold), 4 and 8 paths, ragged
 waves at the end of a direction, lines that start and end on different rows, tall and narrow
 images (every diagonal line starts on a side), rows shorter than the disparity range; at full
 size against the default layout for one pair, the 16-frame batch (eager and graph replay) and
@@ -66,6 +68,11 @@ CASES = [
     (129, 65, 128, 2, 4, 8, 4, 8),
     (163, 99, 64, 3, 4, 8, 4, 8),
     (300, 70, 256, 3, 4, 8, 4, 7),
+    # 24 + lambda*tau = 63: the largest energy the six-bit slots hold; 64 and 72: 12-byte slots
+    (131, 75, 48, 3, 4, 8, 1, 39),
+    (131, 75, 48, 3, 4, 8, 1, 40),
+    (150, 90, 96, 3, 4, 8, 4, 12),
+    (97, 61, 64, 3, 4, 4, 2, 20),
 ]
 
 
