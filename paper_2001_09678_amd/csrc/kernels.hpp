@@ -1105,7 +1105,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
     } else {
       C = (j < bn) ? (uint32_t)a.cost[(size_t)la.pix(t) * a.cap + min(j, a.cap - 1)] : INF32;
     }
-    uint32_t L, m;
+    uint32_t L, m, sb;
     const int src = j + (b0 - lo_prev) + e;
     if constexpr (TAU > 0) {
       // complement encoding: Pu = INF32 - P (absent 0), larger is better
@@ -1122,7 +1122,8 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
           cu -= (int)lt_s;       // increases of tau or more cost 2*lambda*tau
         }
       }
-      const int Mu = t == 0 ? (int)INF32 : max(Ev, cu);
+      // (the fast chunks of batched launches never hold a line's first pixel)
+      const int Mu = (FAST && STAGED) || t != 0 ? max(Ev, cu) : (int)INF32;
       const int Lu = (j < bn) ? Mu - (int)C : 0;
       Pu = Lu;  // next state
       int mu;
@@ -1135,6 +1136,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       L = (j < bn) ? INF32 - (uint32_t)Lu : INF32;  // canonical energy itself
       m = 0;                                          // (no offset to carry)
       P = (j < bn) ? (uint32_t)(mu - Lu) : INF32;    // energy minus the line minimum
+      sb = (uint32_t)(mu - Lu);  // its byte where the slot is in the band, else unused
     } else {
       uint32_t E = band_envelope<LPL, TAU>(P, a.tau, lam_s, lam_up);  // lane i <-> position i - e
       if constexpr (src_occ(SRC)) {
@@ -1153,11 +1155,14 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       L = C + (t == 0 ? 0u : min(Ev, cl));
       m = group_min<LPL>(L);
       P = (j < bn) ? L - m : INF32;
+      sb = min(P, 255u);
     }
     if constexpr (OUT == OUT_PART) {
       const uint8_t v8 = (uint8_t)min(P, 255u);
       if constexpr (STAGE) {
-        tile[k * 16 + j] = v8;
+        // staged slots past the band are never read (the reduce and the layered merges test
+        // the band length), so the tile takes the normalised energy's byte unclamped
+        tile[k * 16 + j] = (uint8_t)sb;
       } else if constexpr (FAST) {
         const uint32_t vo = LPL == 64 ? (uint32_t)j : pst + j, so = LPL == 64 ? pst : 0u;
         __builtin_amdgcn_raw_buffer_store_b8(v8, rpart, (int)vo, (int)so, 0);
@@ -1174,7 +1179,7 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   for (int t0 = 0; t0 < nmax; t0 += CHUNK) {
     const uint2 nxt = load_chunk<true, SRC>(a, la, t0 + CHUNK, kk);
     const int xa = la.x0 + t0 * la.dx, xb = xa + (CHUNK - 1) * la.dx;
-    const bool fast = wave_all(t0 + CHUNK + PREFETCH <= la.n &&
+    const bool fast = wave_all(t0 + CHUNK + PREFETCH <= la.n && (!STAGED || t0 > 0) &&
                                (!src_census(SRC) || min(xa, xb) >= a.D - 1));
     if (fast && hstage) {
       const uint32_t pst0 = (uint32_t)(la.p0 + t0 * la.dp) * (uint32_t)a.capP;

@@ -427,7 +427,7 @@ struct PyrWs {
   size_t gimg_off[MPV_MAX_LEVELS];  // mpv_pyramid with gradient weights: left image of level l
   size_t raw_off[MPV_MAX_LEVELS];
   size_t lo_off[2];  // band starts: level l reads buffer l & 1, its reduce writes the other
-  size_t cen_off[MPV_MAX_LEVELS];  // mpv_pyramid: census of both views of every level
+  size_t cen_off[MPV_MAX_LEVELS];  // census of both views of every level (not in unfused mpv_pyramid)
   int cpitch[MPV_MAX_LEVELS], cmargin[MPV_MAX_LEVELS];
   size_t level_off;  // census + partials, reused per level
   size_t total;
@@ -448,10 +448,13 @@ int prop_block(const mpv_pyramid_params* p, int L, int l) {
 }
 
 // fused_census (mpv_pyramid): the census of every level is computed up front from the input
-// (no coarse images are kept); otherwise (batches) coarse images and per-level census.
+// (no coarse images are kept); otherwise coarse images. mpv_pyramid and batches keep every
+// level's census apart from the level workspace (batches compute a finer level's census while
+// the coarser levels are matched).
 PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g, bool fused_census = false, bool batched = false) {
   PyrWs w{};
   size_t off = 0;
+  const bool cen_levels = fused_census || batched;
   for (int l = 0; l + 1 < g.L && !fused_census; ++l) {
     w.img_off[l] = off;
     off += align_up((size_t)2 * g.W[l] * g.H[l]);
@@ -474,9 +477,9 @@ PyrWs pyr_ws(const mpv_pyramid_params* p, const PyrGeom& g, bool fused_census = 
     mpv_band b{nullptr, nullptr, g.cap[l]};
     int16_t dummy;
     if (l > 0) b.lo = &dummy;  // only presence matters for sizing
-    const LevelWs lw = level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched, !fused_census, batched);
+    const LevelWs lw = level_ws(&lp, g.W[l], g.H[l], l > 0 ? &b : nullptr, p->sched, !cen_levels, batched);
     lvl = std::max(lvl, lw.total);
-    if (fused_census) {
+    if (cen_levels) {
       w.cen_off[l] = off;
       w.cpitch[l] = lw.cpitch;
       w.cmargin[l] = lw.cmargin;
@@ -525,7 +528,10 @@ struct mpv_batch_s {
     int src;  // scans: SRC_CENSUS, or a layered merge's SRC_CENSUS_OCC / SRC_MERGE
     bool line;  // banded scans with one line per lane (bands of cap disparities)
     int cap;
-    bool beside;  // runs on the auxiliary stream beside the next launch (joined after it)
+    bool beside;  // runs on the auxiliary stream beside the previous launch: forked from before
+                  // it (which is dispatched first), joined after both
+    bool early;   // a finer level's census: runs on the census stream from here on, joined
+                  // before its level's first scan
   };
   std::vector<Launch> launches;  // execution order
   std::vector<Launch> sub_launches;  // launches of the last mpv_batch_run_items
@@ -533,6 +539,9 @@ struct mpv_batch_s {
   // different register budgets and fill the machine together
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // the finer levels' census runs on a stream of its own while the coarser levels are matched
+  hipStream_t caux = nullptr;
+  hipEvent_t cfork_ev = nullptr, cjoin_ev[MPV_MAX_LEVELS] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -619,10 +628,15 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       static int16_t dummy_lo;
       mpv_band band{l > 0 ? (r ? (const int16_t*)(r + pr.w.lo_off[l & 1]) : &dummy_lo) : nullptr,
                     nullptr, pr.g.cap[l]};
-      lws[i] = level_ws(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, sc, true, true);
+      lws[i] = level_ws(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, sc, false, true);
       sargs[i] = level_scan_args(&lp, pr.g.W[l], pr.g.H[l], l > 0 ? &band : nullptr, lws[i],
                                  r ? r + pr.w.level_off : nullptr);
-      if (!r) sargs[i].lo = nullptr;
+      if (r) {  // the level's census, in its own region
+        sargs[i].cl = (const uint32_t*)(r + pr.w.cen_off[l]);
+        sargs[i].cr = sargs[i].cl + align_up((size_t)pr.g.H[l] * lws[i].cpitch * sizeof(uint32_t)) / sizeof(uint32_t);
+      } else {
+        sargs[i].lo = nullptr;
+      }
       if (b.p.base.grad_sigma > 0) {  // eq. EU weights from the level's left image
         sargs[i].img = img_at(pr, l, 0, sargs[i].ipitch);
         sargs[i].sigma = b.p.base.grad_sigma;
@@ -720,11 +734,14 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
         ln.stride = k.pitch;
         b.launches.push_back(ln);
       }
-      // both layouts present: the lane-group launch runs beside the line launch after it
+      // both layouts present: the line launch first (its long chains start at once), the
+      // lane-group launch beside it
       const size_t nl = b.launches.size();
       if (k.line_cap && nl >= 2 && b.launches[nl - 1].line && !b.launches[nl - 2].line &&
-          b.launches[nl - 2].kind == mpv_batch_s::SCAN_BAND && b.launches[nl - 2].level == l)
-        b.launches[nl - 2].beside = true;
+          b.launches[nl - 2].kind == mpv_batch_s::SCAN_BAND && b.launches[nl - 2].level == l) {
+        std::swap(b.launches[nl - 2], b.launches[nl - 1]);
+        b.launches[nl - 1].beside = true;
+      }
     }
     // reduce: pairs grouped by partial stride
     std::vector<int> strides;
@@ -770,6 +787,22 @@ void plan_batch(mpv_batch_s& b, uint8_t* ws, TableBuilder& tb) {
       b.launches.push_back(ln);
     }
   }
+  // the finer levels' census (each in its own region) starts after the top level's census,
+  // beside the coarser levels' scans and reduces
+  std::vector<mpv_batch_s::Launch> early, order;
+  for (auto& ln : b.launches) {
+    if (ln.kind == mpv_batch_s::CENSUS && ln.level > 0) {
+      ln.early = true;
+      early.push_back(ln);
+    } else {
+      order.push_back(ln);
+    }
+  }
+  auto top = std::find_if(order.begin(), order.end(), [](const mpv_batch_s::Launch& x) {
+    return x.kind == mpv_batch_s::CENSUS && x.level == 0;
+  });
+  order.insert(top == order.end() ? order.end() : top + 1, early.begin(), early.end());
+  b.launches = std::move(order);
 }
 
 // mpv_pyramid over the SSIM data term: the coarser images of both views are built first
@@ -1119,6 +1152,15 @@ mpv_status mpv_batch_bind(mpv_batch b, void* workspace, size_t bytes, hipStream_
         hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming) != hipSuccess)
       return MPV_ERR_DEVICE;
   }
+  const bool early = std::any_of(b->launches.begin(), b->launches.end(),
+                                 [](const mpv_batch_s::Launch& x) { return x.early; });
+  if (early && !b->caux) {
+    if (hipStreamCreateWithFlags(&b->caux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->cfork_ev, hipEventDisableTiming) != hipSuccess)
+      return MPV_ERR_DEVICE;
+    for (int l = 0; l < MPV_MAX_LEVELS; ++l)
+      if (hipEventCreateWithFlags(&b->cjoin_ev[l], hipEventDisableTiming) != hipSuccess) return MPV_ERR_DEVICE;
+  }
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
@@ -1144,24 +1186,37 @@ mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& lau
   // layered merge) are bracketed together by the timing hook
   std::optional<HookScope> hs;
   int hs_stage = -1, hs_level = -1;
-  bool join = false;  // the auxiliary stream's last launch is joined after this one
-  for (const auto& ln : launches) {
+  bool cpend[MPV_MAX_LEVELS] = {};  // the level's census runs on the census stream
+  for (size_t li = 0; li < launches.size(); ++li) {
+    const auto& ln = launches[li];
     const void* desc = tables + ln.desc_off;
     const int* first = (const int*)(tables + ln.first_off);
     const int stage = ln.kind == mpv_batch_s::DOWN     ? MPV_STAGE_DOWNSAMPLE
                       : ln.kind == mpv_batch_s::CENSUS ? MPV_STAGE_CENSUS
                       : ln.kind == mpv_batch_s::REDUCE ? MPV_STAGE_REDUCE
                                                        : MPV_STAGE_SCAN;
+    const bool scan = ln.kind == mpv_batch_s::SCAN_FULL || ln.kind == mpv_batch_s::SCAN_BAND;
+    if (scan && cpend[ln.level]) {  // join the level's census (before the stage's timing event)
+      if (hipStreamWaitEvent(s, b->cjoin_ev[ln.level], 0) != hipSuccess) return MPV_ERR_DEVICE;
+      cpend[ln.level] = false;
+    }
+    hipStream_t s_main = s;
+    const bool on_caux = ln.early && b->caux;
+    if (on_caux) {  // fork: the census stream starts after everything before
+      if (hipEventRecord(b->cfork_ev, s) != hipSuccess || hipStreamWaitEvent(b->caux, b->cfork_ev, 0) != hipSuccess)
+        return MPV_ERR_DEVICE;
+      s = b->caux;
+    }
     if (stage != hs_stage || ln.level != hs_level) {
       hs.reset();
       hs.emplace(stage, ln.level, s);
       hs_stage = stage;
       hs_level = ln.level;
     }
-    hipStream_t s_main = s;
-    if (ln.beside && b->aux) {  // fork: the auxiliary stream starts after everything before
-      if (hipEventRecord(b->fork_ev, s) != hipSuccess || hipStreamWaitEvent(b->aux, b->fork_ev, 0) != hipSuccess)
-        return MPV_ERR_DEVICE;
+    const bool fork = b->aux && li + 1 < launches.size() && launches[li + 1].beside;
+    if (fork && hipEventRecord(b->fork_ev, s) != hipSuccess) return MPV_ERR_DEVICE;  // before this one
+    if (ln.beside && b->aux) {  // the auxiliary stream starts where the previous launch did
+      if (hipStreamWaitEvent(b->aux, b->fork_ev, 0) != hipSuccess) return MPV_ERR_DEVICE;
       s = b->aux;
     }
     switch (ln.kind) {
@@ -1205,16 +1260,18 @@ mpv_status run_launches(mpv_batch b, const std::vector<mpv_batch_s::Launch>& lau
         break;
       }
     }
-    if (s != s_main) {  // launched beside: joined after the next launch
+    if (on_caux) {
       s = s_main;
-      if (hipEventRecord(b->join_ev, b->aux) != hipSuccess) return MPV_ERR_DEVICE;
-      join = true;
-    } else if (join) {
-      if (hipStreamWaitEvent(s, b->join_ev, 0) != hipSuccess) return MPV_ERR_DEVICE;
-      join = false;
+      if (hipEventRecord(b->cjoin_ev[ln.level], b->caux) != hipSuccess) return MPV_ERR_DEVICE;
+      cpend[ln.level] = true;
+    } else if (s != s_main) {  // launched beside the previous launch: joined after both
+      s = s_main;
+      if (hipEventRecord(b->join_ev, b->aux) != hipSuccess || hipStreamWaitEvent(s, b->join_ev, 0) != hipSuccess)
+        return MPV_ERR_DEVICE;
     }
   }
-  if (join && hipStreamWaitEvent(s, b->join_ev, 0) != hipSuccess) return MPV_ERR_DEVICE;
+  for (int l = 0; l < MPV_MAX_LEVELS; ++l)  // a census no scan waited for (none planned so)
+    if (cpend[l] && hipStreamWaitEvent(s, b->cjoin_ev[l], 0) != hipSuccess) return MPV_ERR_DEVICE;
   return launched();
 }
 }  // namespace
@@ -1293,6 +1350,13 @@ void mpv_batch_destroy(mpv_batch b) {
   }
   if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
   if (b->join_ev) (void)hipEventDestroy(b->join_ev);
+  if (b->caux) {
+    (void)hipStreamSynchronize(b->caux);
+    (void)hipStreamDestroy(b->caux);
+  }
+  if (b->cfork_ev) (void)hipEventDestroy(b->cfork_ev);
+  for (int l = 0; l < MPV_MAX_LEVELS; ++l)
+    if (b->cjoin_ev[l]) (void)hipEventDestroy(b->cjoin_ev[l]);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->stage) {
