@@ -51,8 +51,8 @@ SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/c
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band_batch.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp", "paper_2001_09678_amd/csrc/lines.hpp",
                 "paper_2001_09678_amd/csrc/kern_band_lines.hip"]
-SCAN_TRAFFIC = {"sources_sha1": "e037fb792f40fe15b84b70ce959856db503a01f3", "frames": 16,
-                "fetch_bytes": 1359156649, "write_bytes": 1461370777}
+SCAN_TRAFFIC = {"sources_sha1": "514d70a1b215df521f81433f13d31210d8ba3fb2", "frames": 16,
+                "fetch_bytes": 1353378143, "write_bytes": 970160640}
 
 
 def scan_sources_sha1():
@@ -754,7 +754,12 @@ def main():
     wf, hf = sizes[-1]
     fine_nodes = F * wf * hf * caps[-1]
     roof = roofline_floor(fine_nodes, F * wf * hf, scan_avg)
-    sched_bytes = F * (P * wf * hf * caps[-1] + 2 * 4 * wf * hf)
+    # the schedule's own model: every direction's partial slot group of every pixel written once
+    # (bytes per pixel: the band's uint8 slots, or 8 for the six-bit slots of the
+    # one-line-per-lane levels where 24 + lambda*tau <= 63) plus both census images once
+    six = bsched.band_lanes == mpv.Schedule.LINE and 24 + params.lam * min(params.tau, D - 1) <= 63
+    slot_bytes = 8 if six else caps[-1]
+    sched_bytes = F * (P * wf * hf * slot_bytes + 2 * 4 * wf * hf)
     scan_ops = OPS_PER_NODE_PATH * P * fine_nodes
     traffic = None
     if (SCAN_TRAFFIC["sources_sha1"] and SCAN_TRAFFIC["sources_sha1"] == scan_sources_sha1()
@@ -771,8 +776,9 @@ def main():
                  "units": f"{fine_nodes} evaluated nodes x {FLOOR_B_PER_NODE} B + {F * wf * hf} px x "
                           f"{FLOOR_B_PER_PIXEL} B",
                  "schedule_model": {"bytes": sched_bytes,
-                                    "note": "one uint8 partial per evaluated node and direction written plus "
-                                            "both census images once",
+                                    "note": (f"each direction's {slot_bytes}-byte partial slot group per pixel "
+                                             "written once" + (" (six-bit slots)" if six else " (uint8 slots)") +
+                                             " plus both census images once"),
                                     "achieved": round(sched_bytes / (scan_avg * 1e-3) / 1e9, 1),
                                     "frac": round(sched_bytes / (scan_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}})
     if traffic is not None:
