@@ -191,7 +191,8 @@ typedef struct {
 /* mpv_schedule.band_lanes of a batch (mpv_batch_create): one scan line per lane for the
  * directions that cross image rows (vertical and diagonal; a wave walks 64 neighbouring lines
  * row by row), with the horizontal directions' 16-lane groups running beside them on a second
- * stream, and 12 partial slots per pixel. Taken by the levels whose bands hold 5 or 9
+ * stream; a pixel's partial energies take 8 bytes of six-bit slots where
+ * 24 + lambda*tau_eff <= 63, else 12 byte slots. Taken by the levels whose bands hold 5 or 9
  * disparities with tau_eff = min(tau, D-1) of 1, 2 or 4, for the census data term, the sum
  * of the paths and constant weights; every other level, and every single-pair entry point
  * (whose lone frame's lines would be long serial chains), runs as with band_lanes = 0. */
@@ -300,10 +301,12 @@ mpv_status mpv_batch_create(const mpv_pyramid_params *p, const mpv_batch_item *i
                             mpv_batch *out);
 size_t mpv_batch_workspace_bytes(mpv_batch b);
 mpv_status mpv_batch_bind(mpv_batch b, void *workspace, size_t workspace_bytes, hipStream_t stream);
-/* Enqueue the whole batch (about 4 launches per level) on `stream`. With band_lanes =
- * MPV_BAND_LANES_LINE a line level's horizontal scan runs on a stream the batch owns, after
- * an event recorded on `stream` and joined back by another before the level's reduce, so the
- * batch stays ordered with the caller's work on `stream` (also in mpv_batch_run_graph). */
+/* Enqueue the whole batch (about 4 launches per level) on `stream`. The census of the finer
+ * levels runs on a stream the batch owns, forked by an event recorded on `stream` after the
+ * coarsest level's census and joined back before its level's first scan; with band_lanes =
+ * MPV_BAND_LANES_LINE a line level's horizontal scan runs on a second owned stream, forked
+ * before the level's line scan and joined back before its reduce. The batch stays ordered
+ * with the caller's work on `stream` (also in mpv_batch_run_graph). */
 mpv_status mpv_batch_run(mpv_batch b, hipStream_t stream);
 /* Same work as one hipGraph: captured on a private stream at the first call, then replayed
  * on `stream` with one hipGraphLaunch per call. */
