@@ -255,6 +255,7 @@ class Batch:
     def __init__(self, pairs, params: MPVParams, levels=3, radius=4, sched: Schedule | None = None,
                  device="cuda", want_all=False):
         self.params, self.levels, self.radius = params, levels, radius
+        self.sched = sched if sched is not None else Schedule()
         self.pairs = list(pairs)  # [(left, right, num_disp)]
         self.disp, self.right, self.raw = [], [], []
         items = (_L.BatchItem * len(self.pairs))()

@@ -401,10 +401,15 @@ class BatchedGpuExecutor:
     those frames) on the compute stream, which waits for the uploads; the downloads run on a
     download stream behind the step's kernels and every frame of the step completes on the
     step's event. Uploads of the next step and downloads of the previous one overlap the
-    current step's kernels. Each frame's result equals mpv_pyramid of that frame alone."""
+    current step's kernels. Each frame's result equals mpv_pyramid of that frame alone.
+    Default schedule: the batched layouts (one line per lane for the banded levels' vertical and
+    diagonal directions, longest lines first, two waves per block). Steps that admit at most
+    `lone_max` frames (light load) run a second batch over the same slots with the lane-group
+    layouts instead, whose chains are short: a lone frame's latency, where the batched layouts
+    would turn its lines into long serial chains (0 = always the first batch)."""
 
     def __init__(self, specs, per_spec: int = 4, levels: int = 3, radius: int = 4, num_paths: int = 8,
-                 device="cuda", sched=None):
+                 device="cuda", sched=None, lone_max: int = 3, lone_sched=None):
         import torch
         from . import _lib, mpv
         _lib.lib()  # the HIP library is required; there is no other path
@@ -433,10 +438,20 @@ class BatchedGpuExecutor:
                 self.free_slots[sp].append(slot)
                 pairs.append((L, R, sp.num_disp))
         params = mpv.MPVParams(num_disp=max(sp.num_disp for sp in uniq), num_paths=num_paths)
+        if sched is None:
+            sched = mpv.Schedule(waves_per_block=2, band_lanes=mpv.Schedule.LINE, order=1)
+        self.lone_max = lone_max
+        self.launches = {"batched": 0, "lone": 0}  # admission steps run by each batch
         with torch.cuda.stream(self.compute):
             self.batch = mpv.Batch(pairs, params, levels, radius, sched=sched, device=self.device)
+            self.lone = (mpv.Batch(pairs, params, levels, radius, sched=lone_sched or mpv.Schedule(waves_per_block=4),
+                                   device=self.device) if lone_max > 0 else None)
+        # a slot: both images (2 B per pixel) and each batch's int16 disparity output
+        self.px_bytes = 2 + 2 * (2 if self.lone is not None else 1)
         self.arena_bytes = int(self.batch.workspace.numel()) + sum(
-            3 * s.spec.width * s.spec.height for s in self.slots)
+            self.px_bytes * s.spec.width * s.spec.height for s in self.slots)
+        if self.lone is not None:
+            self.arena_bytes += int(self.lone.workspace.numel())
         self._bytes = {}
 
     def _valid(self, spec) -> bool:
@@ -459,7 +474,7 @@ class BatchedGpuExecutor:
         from . import mpv
         ws = mpv.pyramid_workspace_bytes(mpv.MPVParams(num_disp=spec.num_disp, num_paths=self.num_paths),
                                          self.levels, self.radius, spec.width, spec.height)
-        self._bytes[spec] = int(ws) + 3 * spec.width * spec.height
+        self._bytes[spec] = int(ws) + self.px_bytes * spec.width * spec.height
         return self._bytes[spec]
 
     def alloc(self, spec):
@@ -486,15 +501,18 @@ class BatchedGpuExecutor:
             up = torch.cuda.Event()
             up.record(self.upload)
         if run:
+            lone = self.lone is not None and len(run) <= self.lone_max
+            b = self.lone if lone else self.batch
+            self.launches["lone" if lone else "batched"] += 1
             with torch.cuda.stream(self.compute):
                 self.compute.wait_event(up)
-                self.batch.run_items([s.idx for s in run])
+                b.run_items([s.idx for s in run])
                 matched = torch.cuda.Event()
                 matched.record(self.compute)
             with torch.cuda.stream(self.download):
                 self.download.wait_event(matched)
                 for slot in run:
-                    slot.host_out.copy_(self.batch.disp[slot.idx], non_blocking=True)
+                    slot.host_out.copy_(b.disp[slot.idx], non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(self.download)
             for slot in run:
@@ -513,6 +531,8 @@ class BatchedGpuExecutor:
         self.compute.synchronize()
         self.download.synchronize()
         self.batch.close()
+        if self.lone is not None:
+            self.lone.close()
 
 
 # ---------------------------------------------------------------------------------------

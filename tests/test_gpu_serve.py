@@ -74,6 +74,7 @@ def test_service_results_equal_solo(rigs, tight, kind):
     _log("latency", s, "launches", server.launches, "peak bytes", server.pool.peak)
     server.close()
     if kind == "batched":
+        assert ex.launches["lone"] > 0  # light load: the lane-group batch serves lone frames
         ex.close()
 
 
@@ -90,8 +91,9 @@ def test_batched_service_saturated_equals_solo(rigs):
     for r in res:
         np.testing.assert_array_equal(r.disp, solo[r.rig][r.seq % 2])
     assert max(server.batch_sizes) > 1
+    assert ex.launches["batched"] > 0  # steps of several frames take the batched layouts
     _log("batched saturated: launches", server.launches, "mean batch",
-         sum(server.batch_sizes) / len(server.batch_sizes))
+         sum(server.batch_sizes) / len(server.batch_sizes), ex.launches)
     server.close()
     ex.close()
 
