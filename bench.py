@@ -51,7 +51,7 @@ SCAN_SOURCES = ["paper_2001_09678_amd/csrc/kernels.hpp", "paper_2001_09678_amd/c
                 "paper_2001_09678_amd/csrc/types.hpp", "paper_2001_09678_amd/csrc/kern_band_batch.hip",
                 "paper_2001_09678_amd/csrc/scan_launch.hpp", "paper_2001_09678_amd/csrc/lines.hpp",
                 "paper_2001_09678_amd/csrc/kern_band_lines.hip"]
-SCAN_TRAFFIC = {"sources_sha1": "514d70a1b215df521f81433f13d31210d8ba3fb2", "frames": 16,
+SCAN_TRAFFIC = {"sources_sha1": "481bfe3fb0519f4f892c04ff685b276ebefd1598", "frames": 16,
                 "fetch_bytes": 1353378143, "write_bytes": 970160640}
 
 

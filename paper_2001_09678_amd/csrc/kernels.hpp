@@ -1009,8 +1009,8 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
   // frame's horizontal lines are its longest chains, and the flush would lengthen them): on
   // lines whose consecutive pixels are consecutive in memory (horizontal), a fast chunk
   // collects its 16 steps' bytes in LDS (16 x 16 per group), then lane j writes pixel
-  // t0 + j's 16 slots with one store: whole cache lines, one store instruction per chunk
-  // instead of one per step
+  // t0 + j's slot group (16 or 12 bytes, or 8 bytes of six-bit slots) with one store: whole
+  // cache lines, one store instruction per chunk instead of one per step
   __shared__ uint8_t stage_tile[4 * 64 * 16];
   const bool hstage = STAGED && LPL == 16 && OUT == OUT_PART &&
                       (a.capP == 16 || a.capP == 12 || a.capP == PART6_PITCH) && (la.dp == 1 || la.dp == -1);
