@@ -183,8 +183,8 @@ typedef struct {
     int32_t waves_per_block; /* scan blocks hold 1, 2 or 4 independent waves */
     int32_t full_lanes;      /* full-range scans: lanes per line (16, 32, 64) if the range fits
                                 2 packed pairs per lane, else the default layout */
-    int32_t band_lanes;      /* banded scans: lanes per line (16, 32, 64) if the band fits, or
-                                MPV_BAND_LANES_LINE */
+    int32_t band_lanes;      /* banded scans: lanes per line (16, 32, 64) if the band fits
+                                (cap + 2*(tau_eff-1) < lanes), or MPV_BAND_LANES_LINE */
     int32_t order;           /* batched scans: 0 = pair by pair, 1 = longest lines first */
 } mpv_schedule;
 

@@ -23,7 +23,7 @@ bool with_shape(int cap, int tau, F&& f) {
 }  // namespace
 
 bool band_line_ok(int cap, int tau) {
-  return with_shape(cap, tau, [](auto, auto) {}) && cap + 2 * (tau - 1) <= 16 && cap <= 12;
+  return with_shape(cap, tau, [](auto, auto) {}) && cap + 2 * (tau - 1) < 16 && cap <= 12;
 }
 
 void scan_lane_batch(const Batch<ScanArgs>& b, int units, int cap, int tau, bool p6, int wpb,

@@ -969,7 +969,7 @@ __device__ __forceinline__ u32x2 pack6_bytes(const uint4 v) {
   return w;
 }
 
-// Banded scan: each pixel searches cap <= LPL - 2(tau-1) consecutive disparities starting
+// Banded scan: each pixel searches cap < LPL - 2(tau-1) consecutive disparities starting
 // at lo(p); lane j holds d = lo(p) + j. Neighbouring pixels may place their bands
 // anywhere, so the envelope is built in the previous pixel's frame extended by tau-1
 // slots on each side, then lane j of the new pixel picks position j + lo(p) - lo(p-r).
@@ -1113,8 +1113,18 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       if constexpr (src_occ(SRC)) {
         if (occ) E = max(E, suffix_max_lanes<LPL>(zshift_up<LPL, TAU - 1>(Pu)) - (int)lt_s);
       }
-      const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
-      int Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
+      // batched launches: a source outside the group reads the group's last lane instead, whose
+      // envelope is absent (0): its position lies more than tau-1 slots past every band slot,
+      // since the host keeps cap + 2(tau-1) < LPL (the layered merge's occlusion term is not
+      // absent there). Single-frame launches keep the select, which schedules their latency-bound
+      // chains better.
+      int Ev;
+      if constexpr (src_occ(SRC) || !STAGED) {
+        const int got = __builtin_amdgcn_ds_bpermute((gbase + (src & (LPL - 1))) << 2, E);
+        Ev = ((unsigned)src < (unsigned)LPL) ? got : 0;
+      } else {
+        Ev = __builtin_amdgcn_ds_bpermute((gbase + (int)min((unsigned)src, (unsigned)(LPL - 1))) << 2, E);
+      }
       int cu = GRAD ? mprev - (int)lt_s : capu;
       if constexpr (src_occ(SRC)) {
         if (occ) {

@@ -119,14 +119,15 @@ FullLayout full_layout(int D, int lanes) {
 // Widest padded range any layout may use for D (sizes the census margin).
 int max_dpad(int D) { return std::max(2 * 64 * ((D + 127) / 128), 64); }
 
-// Smallest lane group that holds a band of `cap` plus tau-1 neighbours on each side (or the
-// requested one if it fits); 0 if none.
+// Smallest lane group that holds a band of `cap` plus tau-1 neighbours on each side and one
+// spare lane (or the requested one if it does); 0 if none. The spare last lane's envelope is
+// always absent, and the banded scans read it for every source position outside the group.
 int band_lanes(int cap, int te, int want) {
   const int need = cap + 2 * (te - 1);
-  if (want && need <= want) return want;
-  if (need <= 16) return 16;
-  if (need <= 32) return 32;
-  if (need <= 64) return 64;
+  if (want && need < want) return want;
+  if (need < 16) return 16;
+  if (need < 32) return 32;
+  if (need < 64) return 64;
   return 0;
 }
 
