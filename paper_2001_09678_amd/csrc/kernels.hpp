@@ -1134,7 +1134,10 @@ __device__ __forceinline__ void scan_band_wave(const ScanArgs& a, const ScanArgs
       }
       // (the fast chunks of batched launches never hold a line's first pixel)
       const int Mu = (FAST && STAGED) || t != 0 ? max(Ev, cu) : (int)INF32;
-      const int Lu = (j < bn) ? Mu - (int)C : 0;
+      // a slot past the band (cost INF32 and up) is absent: batched launches leave it at
+      // Mu - C <= 0, below every present value (INF32 - L > 0) in each maximum that follows;
+      // the others set it to 0
+      const int Lu = (STAGED && !src_occ(SRC)) || j < bn ? Mu - (int)C : 0;
       Pu = Lu;  // next state
       int mu;
       if constexpr (LPL == 64)
