@@ -1464,21 +1464,17 @@ __device__ __forceinline__ void reduce_part_row(const RedArgs& a, int y, int nee
     const int x = (it * nw + wave) * PPW + lane / LPP;
     const bool xin = x < a.W;
     const size_t p = (size_t)y * a.W + (xin ? x : a.W - 1);
-    // every direction's slots are loaded before any is used (npart <= 8, uniform)
+    // every direction's slots are loaded before any is used (npart <= 8, uniform); the
+    // partial volumes are read once, so the loads are non-temporal
     const uint8_t* q0 = a.part + p * a.stride + j0;
     uint32_t wv[8][NQ];
+    typedef unsigned int vq __attribute__((ext_vector_type(NQ)));
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      if constexpr (SL == 16) {
-        const uint4 w = r < a.npart ? *(const uint4*)(q0 + r * a.part_stride) : make_uint4(0u, 0u, 0u, 0u);
-        wv[r][0] = w.x, wv[r][1] = w.y, wv[r][2] = w.z, wv[r][3] = w.w;
-      } else if constexpr (P6) {
-        const uint2 w = r < a.npart ? *(const uint2*)(q0 + r * a.part_stride) : make_uint2(0u, 0u);
-        wv[r][0] = w.x, wv[r][1] = w.y;
-      } else {
-        const uint3 w = r < a.npart ? *(const uint3*)(q0 + r * a.part_stride) : make_uint3(0u, 0u, 0u);
-        wv[r][0] = w.x, wv[r][1] = w.y, wv[r][2] = w.z;
-      }
+      vq w = {};
+      if (r < a.npart) w = __builtin_nontemporal_load((const vq*)(q0 + r * a.part_stride));
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) wv[r][q] = w[q];
     }
     int b0, bn;
     band_at(a.lo, a.len, p, a.D, a.bcap, b0, bn);
